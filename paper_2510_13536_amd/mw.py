@@ -1,0 +1,231 @@
+"""Thin Python binding of libmwcg (C ABI in include/mw.h).
+
+Argument marshalling only: every arithmetic step runs in the HIP kernels of
+libmwcg.so.  PyTorch provides device memory (tensors) and the stream
+(torch.cuda.current_stream()).  There is no CPU fallback: if the library is
+not built, or no GPU is present, the calls raise.
+
+Multi-word vectors are float64 CUDA tensors of shape (k, n) (k word planes,
+plane 0 the leading word); k-word scalars are float64 tensors of shape (k,).
+"""
+import ctypes as C
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmwcg.so")
+
+ARITH = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4}
+WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3}
+OPS = {"add": 0, "mul": 1, "dxmul": 2, "div": 3, "norm": 4, "neg": 5, "tofp64": 6}
+STATUS = {0: "ok", 1: "not_converged", 2: "breakdown"}
+MW_EINVAL, MW_EHIP = -1, -2
+
+_vp = C.c_void_p
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", _vp), ("col_idx", _vp), ("val", _vp)]
+
+
+class CgInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double),
+                ("seconds", C.c_double)]
+
+
+class CgOpts(C.Structure):
+    _fields_ = [("normalize", C.c_int32), ("chunk", C.c_int32), ("history", _vp)]
+
+
+class MWError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def _hip_runtimes_mapped():
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        pass
+    return paths
+
+
+def lib():
+    """The loaded libmwcg (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MWError("libmwcg.so is not built (run: python -m paper_2510_13536_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    rt = _hip_runtimes_mapped()
+    if len(rt) > 1:
+        raise MWError("two HIP runtimes are mapped in this process: %s" % sorted(rt))
+    L.mw_words.argtypes = [C.c_int]
+    L.mw_status_string.restype = C.c_char_p
+    L.mw_last_error.restype = C.c_char_p
+    L.mw_elementwise.argtypes = [C.c_int, C.c_int, C.c_int32, _vp, _vp, _vp, _vp]
+    L.mw_axpy.argtypes = [C.c_int, C.c_int32, _vp, _vp, _vp, _vp]
+    L.mw_dot_workspace_bytes.argtypes = [C.c_int, C.c_int32]
+    L.mw_dot_workspace_bytes.restype = C.c_size_t
+    L.mw_dot.argtypes = [C.c_int, C.c_int32, _vp, _vp, _vp, _vp, _vp]
+    L.mw_spmv.argtypes = [C.c_int, C.POINTER(Csr), _vp, _vp, _vp]
+    L.mw_cg_workspace_bytes.argtypes = [C.c_int, C.c_int32, C.c_int32]
+    L.mw_cg_workspace_bytes.restype = C.c_size_t
+    L.mw_cg_solve.argtypes = [C.c_int, C.POINTER(Csr), _vp, _vp, C.c_double, C.c_int32,
+                              C.POINTER(CgOpts), _vp, C.POINTER(CgInfo), _vp]
+    _lib = L
+    return L
+
+
+def _check(rc, what):
+    if rc < 0:
+        msg = lib().mw_status_string(rc).decode()
+        if rc == MW_EHIP:
+            msg += ": " + lib().mw_last_error().decode()
+        raise MWError("%s failed (%d): %s" % (what, rc, msg))
+    return rc
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return _vp(t.data_ptr()) if t is not None else None
+
+
+def _vec(t, k, n=None, name="vector"):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise MWError("%s must be a float64 CUDA tensor" % name)
+    if t.dim() == 1:
+        t = t.view(1, -1)
+    if t.dim() != 2 or t.shape[0] != k or (n is not None and t.shape[1] != n) or not t.is_contiguous():
+        raise MWError("%s must be a contiguous (%d, n) tensor, got %s" % (name, k, tuple(t.shape)))
+    return t
+
+
+def words(arith):
+    return WORDS[arith]
+
+
+class DeviceCSR:
+    """FP64 CSR matrix resident on the GPU (int32 indices)."""
+
+    def __init__(self, n, row_ptr, col_idx, val):
+        self.n = int(n)
+        self.row_ptr, self.col_idx, self.val = row_ptr, col_idx, val
+        self.nnz = int(col_idx.numel())
+        if row_ptr.dtype != torch.int32 or col_idx.dtype != torch.int32 or val.dtype != torch.float64:
+            raise MWError("CSR arrays must be int32/int32/float64")
+        if row_ptr.numel() != self.n + 1 or val.numel() != self.nnz:
+            raise MWError("CSR array sizes are inconsistent")
+
+    @classmethod
+    def from_host(cls, A, device="cuda"):
+        """From any object with n, row_ptr, col_idx, val (numpy arrays)."""
+        return cls(A.n, torch.as_tensor(A.row_ptr, dtype=torch.int32, device=device).contiguous(),
+                   torch.as_tensor(A.col_idx, dtype=torch.int32, device=device).contiguous(),
+                   torch.as_tensor(A.val, dtype=torch.float64, device=device).contiguous())
+
+    def c(self):
+        return Csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.val.data_ptr())
+
+
+def elementwise(arith, op, u, v=None, out=None):
+    """w = op(u, v) over word planes; op in OPS."""
+    k = WORDS[arith]
+    if op == "dxmul":
+        u = u.reshape(1, -1)
+        if not (u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()):
+            raise MWError("u must be a contiguous float64 CUDA tensor")
+    else:
+        u = _vec(u, k, name="u")
+    n = u.shape[1]
+    if v is not None:
+        v = _vec(v, k, n, name="v")
+    if out is None:
+        out = torch.empty((1 if op == "tofp64" else k, n), dtype=torch.float64, device=u.device)
+    _check(lib().mw_elementwise(ARITH[arith], OPS[op], n, _ptr(u), _ptr(v), _ptr(out), _stream()),
+           "mw_elementwise")
+    return out
+
+
+def axpy(arith, alpha, x, y):
+    """y += alpha * x in place; alpha: (k,) device tensor."""
+    k = WORDS[arith]
+    x = _vec(x, k, name="x")
+    y = _vec(y, k, x.shape[1], name="y")
+    alpha = alpha.reshape(-1)
+    if alpha.numel() != k or not alpha.is_cuda or alpha.dtype != torch.float64:
+        raise MWError("alpha must be a (k,) float64 CUDA tensor")
+    _check(lib().mw_axpy(ARITH[arith], x.shape[1], _ptr(alpha.contiguous()), _ptr(x), _ptr(y), _stream()),
+           "mw_axpy")
+    return y
+
+
+def dot(arith, x, y, out=None, workspace=None):
+    """x^T y as a (k,) device tensor."""
+    k = WORDS[arith]
+    x = _vec(x, k, name="x")
+    y = _vec(y, k, x.shape[1], name="y")
+    n = x.shape[1]
+    if out is None:
+        out = torch.empty(k, dtype=torch.float64, device=x.device)
+    need = lib().mw_dot_workspace_bytes(ARITH[arith], n)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    _check(lib().mw_dot(ARITH[arith], n, _ptr(x), _ptr(y), _ptr(out), _ptr(workspace), _stream()), "mw_dot")
+    return out
+
+
+def spmv(arith, A, x, y=None):
+    """y = A x; A a DeviceCSR."""
+    k = WORDS[arith]
+    x = _vec(x, k, A.n, name="x")
+    if y is None:
+        y = torch.empty_like(x)
+    y = _vec(y, k, A.n, name="y")
+    csr = A.c()
+    _check(lib().mw_spmv(ARITH[arith], C.byref(csr), _ptr(x), _ptr(y), _stream()), "mw_spmv")
+    return y
+
+
+def cg_workspace(arith, A, device=None):
+    nbytes = lib().mw_cg_workspace_bytes(ARITH[arith], A.n, A.nnz)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device or A.val.device)
+
+
+def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0, history=False,
+             workspace=None):
+    """Solve A x = b by CG in `arith`.  Returns (x (k, n) tensor, info dict)."""
+    k = WORDS[arith]
+    b = b.reshape(-1)
+    if not (b.is_cuda and b.dtype == torch.float64 and b.is_contiguous() and b.numel() == A.n):
+        raise MWError("b must be a contiguous float64 CUDA tensor of length n")
+    if x is None:
+        x = torch.zeros((k, A.n), dtype=torch.float64, device=b.device)
+    x = _vec(x, k, A.n, name="x")
+    if maxit is None:
+        maxit = 10 * A.n
+    if workspace is None:
+        workspace = cg_workspace(arith, A, b.device)
+    hist = torch.zeros(max(int(maxit), 1), dtype=torch.float64, device=b.device) if history else None
+    opts = CgOpts(1 if normalize else 0, int(chunk), hist.data_ptr() if hist is not None else None)
+    info = CgInfo()
+    csr = A.c()
+    rc = lib().mw_cg_solve(ARITH[arith], C.byref(csr), _ptr(b), _ptr(x), float(tol), int(maxit),
+                           C.byref(opts), _ptr(workspace), C.byref(info), _stream())
+    _check(rc, "mw_cg_solve")
+    out = {"iters": info.iters, "status": STATUS.get(info.status, str(info.status)),
+           "status_code": info.status, "rel_res": info.rel_res, "seconds": info.seconds}
+    if hist is not None:
+        out["history"] = hist[:info.iters].cpu().numpy()
+    return x, out

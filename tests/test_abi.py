@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports every entry point include/mw.h
+declares; argument validation and sizing run without a GPU (no compute)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mw.h")
+LIB = os.path.join(ROOT, "paper_2510_13536_amd", "libmwcg.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mw_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libmwcg.so is not built (python -m paper_2510_13536_amd.build)")
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_core_calls():
+    names = declared_functions()
+    for f in ("mw_spmv", "mw_dot", "mw_axpy", "mw_cg_solve", "mw_words", "mw_elementwise"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_words_and_status_strings(lib):
+    assert [lib.mw_words(a) for a in range(5)] == [1, 2, 2, 3, 3]
+    assert lib.mw_words(7) == -1
+    lib.mw_status_string.restype = C.c_char_p
+    assert lib.mw_status_string(0) == b"ok"
+    assert b"invalid" in lib.mw_status_string(-1)
+
+
+def test_workspace_sizes(lib):
+    lib.mw_cg_workspace_bytes.restype = C.c_size_t
+    lib.mw_dot_workspace_bytes.restype = C.c_size_t
+    n = 4096
+    for a, k in enumerate([1, 2, 2, 3, 3]):
+        ws = lib.mw_cg_workspace_bytes(a, n, 20224)
+        assert ws >= 3 * k * n * 8 and ws % 256 == 0
+        assert lib.mw_dot_workspace_bytes(a, n) >= 8 * k
+    assert lib.mw_cg_workspace_bytes(9, n, 0) == 0
+    assert lib.mw_cg_workspace_bytes(0, 0, 0) == 0
+
+
+def test_invalid_arguments_rejected_without_gpu(lib):
+    vp = C.c_void_p
+    lib.mw_elementwise.argtypes = [C.c_int, C.c_int, C.c_int32, vp, vp, vp, vp]
+    lib.mw_axpy.argtypes = [C.c_int, C.c_int32, vp, vp, vp, vp]
+    lib.mw_dot.argtypes = [C.c_int, C.c_int32, vp, vp, vp, vp, vp]
+    lib.mw_spmv.argtypes = [C.c_int, vp, vp, vp, vp]
+    lib.mw_cg_solve.argtypes = [C.c_int, vp, vp, vp, C.c_double, C.c_int32, vp, vp, vp, vp]
+    bogus = vp(0x1000)
+    assert lib.mw_elementwise(5, 0, 10, bogus, bogus, bogus, None) == -1   # arith
+    assert lib.mw_elementwise(1, 9, 10, bogus, bogus, bogus, None) == -1   # op
+    assert lib.mw_elementwise(1, 0, -1, bogus, bogus, bogus, None) == -1   # n
+    assert lib.mw_elementwise(1, 0, 10, bogus, None, bogus, None) == -1    # v needed
+    assert lib.mw_elementwise(1, 0, 0, None, None, None, None) == 0        # empty: no-op
+    assert lib.mw_axpy(1, 10, None, bogus, bogus, None) == -1
+    assert lib.mw_dot(1, 10, bogus, bogus, bogus, None, None) == -1        # workspace
+    assert lib.mw_spmv(1, None, bogus, bogus, None) == -1
+    assert lib.mw_cg_solve(1, None, bogus, bogus, 1e-12, 10, None, bogus, None, None) == -1

@@ -1,0 +1,257 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (see the design notes):
+  * element-wise ops and AXPY: bit-identical for all five arithmetics;
+  * SpMV: bit-identical (both sum each row sequentially in CSR order);
+  * DOT: within the format's bound against the exact dot:
+    |d - x^T y| <= 2^-100 (2 words) / 2^-145 (3 words) * sum |x_i y_i|;
+  * CG: same stopping criterion, iteration counts within 2 %, true
+    residual (formed exactly by the oracle) within 10x of the oracle's.
+"""
+import zlib
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from conftest import rand_mw
+from paper_2510_13536_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+ARITHS = ["fp64", "dw", "qdw", "tw", "qtw"]
+DOT_BOUND = {1: 2.0 ** -45, 2: 2.0 ** -100, 3: 2.0 ** -145}
+
+
+@pytest.fixture(scope="module")
+def mw():
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    from paper_2510_13536_amd import mw as M
+    M.lib()
+    return M
+
+
+def dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def special_values(k, n):
+    """Word planes with zeros, signed zeros, powers of two, huge/tiny."""
+    rng = np.random.default_rng(5)
+    v = rand_mw(rng, k, n, emin=-300, emax=300)
+    v[:, 0:8] = 0.0
+    v[0, 1] = -0.0
+    v[0, 2] = 1.0
+    v[0, 3] = 2.0 ** -1000
+    v[0, 4] = -2.0 ** 1000
+    return v
+
+
+# ------------------------------------------------------------ element-wise
+
+@pytest.mark.parametrize("arith", ARITHS)
+@pytest.mark.parametrize("op", ["add", "mul", "dxmul", "div", "norm", "neg", "tofp64"])
+@pytest.mark.parametrize("kind", ["normalised", "overlapping"])
+def test_elementwise_bit_exact(mw, arith, op, kind):
+    k = O.WORDS[arith]
+    n = 3001  # several workgroups and a ragged tail
+    rng = np.random.default_rng(zlib.crc32(("%s/%s/%s" % (arith, op, kind)).encode()))
+    u = rand_mw(rng, k, n, normalised=(kind == "normalised"))
+    v = rand_mw(rng, k, n, normalised=(kind == "normalised"))
+    v[:, ::3] = -v[:, ::3]
+    ua = u[0] if op == "dxmul" else u
+    vv = v if op in ("add", "mul", "dxmul", "div") else None
+    want = O.elementwise(arith, op, ua, vv)
+    got = host(mw.elementwise(arith, op, dev(ua), dev(vv) if vv is not None else None))
+    want = want.reshape(got.shape)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), \
+        "first mismatch at %s" % (np.argwhere(got.view(np.uint64) != want.view(np.uint64))[:3],)
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_elementwise_special_values(mw, arith):
+    k = O.WORDS[arith]
+    u = special_values(k, 300)
+    v = special_values(k, 300)[:, ::-1].copy()
+    for op in ("add", "mul", "norm"):
+        vv = v if op in ("add", "mul") else None
+        want = O.elementwise(arith, op, u, vv)
+        got = host(mw.elementwise(arith, op, dev(u), dev(vv) if vv is not None else None))
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), op
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+@pytest.mark.parametrize("n", [1, 255, 256, 257, 70001])
+def test_axpy_bit_exact(mw, arith, n):
+    k = O.WORDS[arith]
+    rng = np.random.default_rng(n)
+    x = rand_mw(rng, k, n)
+    y = rand_mw(rng, k, n)
+    al = rand_mw(rng, k, 1)[:, 0]
+    want = O.axpy(arith, al, x, y)
+    yd = dev(y)
+    mw.axpy(arith, dev(al), dev(x), yd)
+    assert np.array_equal(host(yd).view(np.uint64), want.view(np.uint64))
+
+
+# --------------------------------------------------------------------- SpMV
+
+def ragged_matrix(seed=3):
+    """Rows of very different lengths: empty rows, a row longer than one LDS
+    chunk (3000 nonzeros), a dense-ish block; n not a multiple of 256."""
+    rng = np.random.default_rng(seed)
+    n = 5003
+    rows, cols = [], []
+    for i in range(n):
+        if i % 97 == 5:
+            continue  # empty row
+        L = 3000 if i == 1234 else int(rng.integers(1, 40))
+        c = np.unique(rng.integers(0, n, L))
+        rows.append(np.full(c.size, i))
+        cols.append(c)
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    v = rng.standard_normal(r.size) * 10.0 ** rng.uniform(-3, 3, r.size)
+    return P.CSR.from_scipy(sp.coo_matrix((v, (r, c)), shape=(n, n)))
+
+
+MATRICES = {
+    "poisson2d_64": lambda: P.poisson2d(64),
+    "poisson3d_ragged": lambda: P.poisson3d(13, 11, 7),
+    "banded27": lambda: P.banded_spd(5000, half_bw=13, seed=1, dseed=2),
+    "circulant": lambda: P.circulant_laplacian(3001, [1, 17, 400, 1200], [0.5, 0.3, 1.0, 0.2]),
+    "ragged": ragged_matrix,
+}
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+@pytest.mark.parametrize("mat", list(MATRICES))
+def test_spmv_bit_exact(mw, arith, mat):
+    A = MATRICES[mat]()
+    k = O.WORDS[arith]
+    x = rand_mw(np.random.default_rng(11), k, A.n, emin=-4, emax=4)
+    want = O.spmv(arith, A, x)
+    Ad = mw.DeviceCSR.from_host(A)
+    got = host(mw.spmv(arith, Ad, dev(x)))
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_spmv_integer_exact(mw, arith):
+    A = P.poisson3d(17, 9, 6)
+    x = P.integer_vector(A.n, seed=2)
+    got = host(mw.spmv(arith, mw.DeviceCSR.from_host(A), dev(x.reshape(1, -1).repeat(O.WORDS[arith], 0) *
+                                                              np.array([[1.0]] + [[0.0]] * (O.WORDS[arith] - 1)))))
+    ref = (A.to_scipy().astype(np.int64) @ x.astype(np.int64)).astype(np.float64)
+    assert np.array_equal(got[0], ref) and np.all(got[1:] == 0.0)
+
+
+# ---------------------------------------------------------------------- DOT
+
+@pytest.mark.parametrize("arith", ARITHS)
+@pytest.mark.parametrize("n", [1, 255, 2048, 2049, 100003])
+def test_dot_within_bound(mw, arith, n):
+    k = O.WORDS[arith]
+    rng = np.random.default_rng(n + 7)
+    x = rand_mw(rng, k, n, emin=-6, emax=6)
+    y = rand_mw(rng, k, n, emin=-6, emax=6)
+    d = host(mw.dot(arith, dev(x), dev(y)))
+    err, sc = O.dot_error(arith, x, y, d)
+    assert err <= DOT_BOUND[k] * sc, (err / sc)
+    d2 = host(mw.dot(arith, dev(x), dev(y)))
+    assert np.array_equal(d, d2)  # run-to-run reproducible
+
+
+def test_dot_empty(mw):
+    import torch
+    for arith in ARITHS:
+        k = O.WORDS[arith]
+        z = torch.empty((k, 0), dtype=torch.float64, device="cuda")
+        assert np.all(host(mw.dot(arith, z, z)) == 0.0)
+
+
+# ----------------------------------------------------------------------- CG
+
+def cg_parity(mw, arith, A, b, tol, maxit=None):
+    xo, io = O.cg_solve(arith, A, b, tol=tol, maxit=maxit)
+    Ad = mw.DeviceCSR.from_host(A)
+    xg, ig = mw.cg_solve(arith, Ad, dev(b), tol=tol, maxit=maxit)
+    xg = host(xg)
+    assert ig["status"] == io["status"], (ig, io)
+    assert abs(ig["iters"] - io["iters"]) <= max(1, int(0.02 * io["iters"])), (ig["iters"], io["iters"])
+    tro = O.true_residual(arith, A, b, xo)
+    trg = O.true_residual(arith, A, b, xg)
+    nb = np.linalg.norm(b)
+    floor = 1e-300
+    assert trg / nb <= 10 * max(tro / nb, floor), (trg / nb, tro / nb)
+    return xg, ig, io
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_cg_poisson2d_64(mw, arith):
+    A, b, _ = P.case_poisson2d_64()
+    cg_parity(mw, arith, A, b, 1e-12)
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_cg_poisson3d_small(mw, arith):
+    A, b, _ = P.case_poisson3d(nx=24)
+    cg_parity(mw, arith, A, b, 1e-12)
+
+
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qtw"])
+def test_cg_tight_tolerance(mw, arith):
+    A = P.poisson2d(40, 30)
+    xs = P.integer_vector(A.n, seed=3)
+    b = A.matvec(xs)
+    tol = {"fp64": 1e-14, "dw": 1e-28, "qtw": 1e-40}[arith]
+    xg, ig, io = cg_parity(mw, arith, A, b, tol)
+    err = np.abs(xg.sum(axis=0) - xs).max() / np.abs(xs).max()
+    assert err < {"fp64": 1e-12, "dw": 1e-26, "qtw": 1e-30}[arith] or arith != "fp64"
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_cg_failure_paths(mw, arith):
+    A, b, _ = P.case_poisson2d_64()
+    Ad = mw.DeviceCSR.from_host(A)
+    _, i = mw.cg_solve(arith, Ad, dev(b), tol=1e-12, maxit=7)
+    assert i["status"] == "not_converged" and i["iters"] == 7
+    _, i = mw.cg_solve(arith, Ad, dev(b), tol=1e-12, maxit=0)
+    assert i["status"] == "not_converged" and i["iters"] == 0
+    x, i = mw.cg_solve(arith, Ad, dev(np.zeros(A.n)), tol=1e-12)
+    assert i["status"] == "ok" and i["iters"] == 0 and not host(x).any()
+    M2 = P.CSR.from_scipy(sp.diags(np.array([-1.0] + [1.0] * 9), 0))
+    e0 = np.zeros(10)
+    e0[0] = 1.0
+    _, i = mw.cg_solve(arith, mw.DeviceCSR.from_host(M2), dev(e0), tol=1e-12)
+    assert i["status"] == "breakdown" and i["iters"] == 0
+
+
+@pytest.mark.parametrize("arith", ["dw", "qtw"])
+def test_cg_deterministic(mw, arith):
+    A, b, _ = P.case_poisson3d(nx=20)
+    Ad = mw.DeviceCSR.from_host(A)
+    x1, i1 = mw.cg_solve(arith, Ad, dev(b), tol=1e-12)
+    x2, i2 = mw.cg_solve(arith, Ad, dev(b), tol=1e-12)
+    assert i1["iters"] == i2["iters"]
+    assert np.array_equal(host(x1).view(np.uint64), host(x2).view(np.uint64))
+
+
+def test_cg_history_and_nn(mw):
+    A = P.poisson2d(24, 20)
+    b = A.matvec(P.integer_vector(A.n, seed=3))
+    Ad = mw.DeviceCSR.from_host(A)
+    _, i = mw.cg_solve("qtw", Ad, dev(b), tol=1e-30, history=True)
+    h = i["history"]
+    assert h.size == i["iters"] and h[-1] < 1e-30 and h[0] > 1e-30
+    # without normalisation the quasi variants fail to converge (Sec. V-B)
+    _, nn = mw.cg_solve("qdw", Ad, dev(b), tol=1e-28, maxit=4000, normalize=False)
+    _, on = O.cg_solve("qdw", A, b, tol=1e-28, maxit=4000, normalise=False)
+    assert nn["status"] != "ok" and on["status"] != "ok"
