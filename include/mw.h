@@ -87,6 +87,25 @@ typedef struct {
     const double *val;
 } mw_csr_t;
 
+/* Storage formats of a SpMV plan. */
+enum {
+    MW_FMT_CSR = 0,     /* the caller's CSR arrays are used as given        */
+    MW_FMT_SELL64 = 1   /* sliced ELLPACK, 64-row slices (see mw_spmv_plan) */
+};
+
+/* A SpMV plan (host struct; the arrays it points to live in the caller's
+ * plan buffer in device memory, plus the caller's CSR arrays). */
+typedef struct {
+    int32_t n, nnz;
+    int32_t format;             /* MW_FMT_SELL64, or MW_FMT_CSR as fallback    */
+    int32_t nslices;            /* ceil(n / 64)                               */
+    int64_t stored;             /* SELL64: entries stored, padding included    */
+    const int32_t *slice_ptr;   /* SELL64: nslices + 1 offsets                */
+    const int32_t *col;         /* SELL64: column of each entry, -1 = padding  */
+    const double *val;          /* SELL64: value of each entry                 */
+    mw_csr_t csr;               /* the source matrix                          */
+} mw_spmv_plan_t;
+
 /* Result of a solve (host memory). */
 typedef struct {
     int32_t iters;    /* CG iterations performed (SpMVs inside the loop)   */
@@ -94,6 +113,27 @@ typedef struct {
     double rel_res;   /* sqrt(fp64(r^T r)) / ||b||_2 at the last test      */
     double seconds;   /* device time of the solve (HIP events)             */
 } mw_cg_info_t;
+
+/* Optional per-kernel timing of a solve (host memory).  When given, the
+ * solver brackets every kernel launch of the iteration loop with HIP events
+ * on `stream` and adds, over the iterations that ran to completion, the
+ * device time (ms) and the number of launches of each kernel class.
+ * Only the classes selected by `mask` are timed (each timed launch adds an
+ * event pair); a timed solve launches its kernels directly instead of
+ * replaying a captured graph.  Leave the pointer NULL otherwise. */
+enum {
+    MW_PROF_SPMV = 0,      /* q = A p and the p^T q partials               */
+    MW_PROF_UPDATE_R = 1,  /* x, r updates, normalisation, r^T r partials  */
+    MW_PROF_UPDATE_P = 2,  /* p = r + beta p                               */
+    MW_PROF_FINAL = 3,     /* scalar finalisers (alpha, beta, test)        */
+    MW_PROF_CLASSES = 4
+};
+typedef struct {
+    double ms[MW_PROF_CLASSES];          /* out: summed device time          */
+    int64_t launches[MW_PROF_CLASSES];   /* out: launches timed              */
+    int32_t mask;                        /* in: bit c times class c; 0 = all */
+    int32_t reserved;
+} mw_cg_prof_t;
 
 /* Solver options (host memory); pass NULL for the defaults. */
 typedef struct {
@@ -106,6 +146,12 @@ typedef struct {
     double *history;    /* optional DEVICE array of maxit doubles: entry i
                            receives the relative residual after iteration
                            i+1.  NULL = not recorded.                      */
+    mw_cg_prof_t *prof; /* optional HOST struct for per-kernel timing      */
+    const mw_spmv_plan_t *plan;  /* optional plan of A from mw_spmv_plan; NULL:
+                           the solver builds one inside its workspace      */
+    int32_t no_graph;   /* nonzero: launch each kernel directly instead of
+                           replaying a captured hipGraph of a chunk       */
+    int32_t reserved;
 } mw_cg_opts_t;
 
 /* Number of FP64 words of an arithmetic: 1, 2, 2, 3, 3; -1 if unknown. */
@@ -134,7 +180,7 @@ int mw_elementwise(mw_arith_t a, int op, int32_t n, const double *u, const doubl
                    double *w, void *stream);
 
 /*
- * y = y + alpha * x (AXPY, Sec. IV-B; Alg. 1 lines 7-8).  alpha: one k-word
+ * y = y + alpha * x (AXPY, Sec. IV-B; the x and r updates of Alg. 1).  alpha: one k-word
  * scalar in device memory; x, y: k planes of n.  FP64: y = fma(alpha, x, y);
  * otherwise y = add(y, mul(alpha, x)).  Bit-identical to the definition.
  * Asynchronous.
@@ -146,7 +192,7 @@ int mw_axpy(mw_arith_t a, int32_t n, const double *alpha, const double *x, doubl
 size_t mw_dot_workspace_bytes(mw_arith_t a, int32_t n);
 
 /*
- * result = x^T y (DOT, Sec. IV-B; Alg. 1 lines 6 and 9).  x, y: k planes of
+ * result = x^T y (DOT, Sec. IV-B; p^T q and r^T r in Alg. 1).  x, y: k planes of
  * n; result: one k-word scalar in device memory.  Products mul(x_i, y_i)
  * are summed with the arithmetic's add in a fixed, run-to-run reproducible
  * order: sequentially over a few elements per thread, then pairwise trees
@@ -160,7 +206,7 @@ int mw_dot(mw_arith_t a, int32_t n, const double *x, const double *y, double *re
            void *workspace, void *stream);
 
 /*
- * y = A x (CSR SpMV, Sec. IV-B; Alg. 1 line 5).  A: FP64 CSR; x, y: k planes
+ * y = A x (CSR SpMV, Sec. IV-B; q = A p in Alg. 1).  A: FP64 CSR; x, y: k planes
  * of A->n (must not alias).  Each row is accumulated from zero in CSR order,
  * acc = add(acc, a_ij * x_j) with an FP64 x multi-word product (FP64:
  * acc = fma(a_ij, x_j, acc)), so every row is bit-identical to that
@@ -168,7 +214,32 @@ int mw_dot(mw_arith_t a, int32_t n, const double *x, const double *y, double *re
  */
 int mw_spmv(mw_arith_t a, const mw_csr_t *A, const double *x, double *y, void *stream);
 
-/* Bytes of device workspace mw_cg_solve needs (256-byte aligned). */
+
+/* Bytes of device memory mw_spmv_plan needs for an n x n matrix with nnz
+ * entries (256-byte aligned); 0 for invalid sizes. */
+size_t mw_spmv_plan_bytes(int32_t n, int32_t nnz);
+
+/*
+ * Re-lays A out for the GPU (a set-up step, not part of the paper's
+ * method): slices of 64 consecutive rows, one per wavefront, each slice
+ * padded to its longest row and stored column-major (entry j of row
+ * 64 s + l at slice_ptr[s] + 64 j + l), so that each lane owns one row and
+ * every wavefront load of values or column indices is contiguous.  The row
+ * contents and their order are kept, so products computed from the plan
+ * are bit-identical to those from the CSR arrays.  When the padding would
+ * exceed the buffer (rows of very uneven length inside one slice) the plan
+ * falls back to format MW_FMT_CSR.  A's arrays must stay valid while the
+ * plan is used.  buffer: device memory of at least mw_spmv_plan_bytes
+ * bytes; plan: host struct filled on success.  Synchronises `stream`.
+ */
+int mw_spmv_plan(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *plan, void *stream);
+
+/* y = A x with a plan: the same result, bit for bit, as mw_spmv.
+ * Asynchronous. */
+int mw_spmv_planned(mw_arith_t a, const mw_spmv_plan_t *plan, const double *x, double *y, void *stream);
+
+/* Bytes of device workspace mw_cg_solve needs (256-byte aligned),
+ * including room for a SpMV plan of A. */
 size_t mw_cg_workspace_bytes(mw_arith_t a, int32_t n, int32_t nnz);
 
 /*
@@ -186,7 +257,13 @@ size_t mw_cg_workspace_bytes(mw_arith_t a, int32_t n, int32_t nnz);
  * the paper's x0 = 0); tol >= 0; maxit >= 0; opts may be NULL; workspace:
  * at least mw_cg_workspace_bytes(a, n, nnz) bytes of device memory; info
  * (host) receives iterations, status, final relative residual and time.
- * Returns the status (>= 0) or a negative error.  Synchronises `stream`.
+ * Returns the status (>= 0) or a negative error.  The solve runs on a
+ * stream of the library's own, ordered after the work already enqueued on
+ * `stream`, and is complete when the call returns.  Iterations are enqueued
+ * in chunks (opts->chunk, default 32) as a captured hipGraph that is reused
+ * by later calls with the same arguments on the same thread; every kernel
+ * exits at once after the stop, and the host checks the stop flag once per
+ * chunk.  The result is run-to-run reproducible.
  */
 int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, double tol,
                 int32_t maxit, const mw_cg_opts_t *opts, void *workspace, mw_cg_info_t *info,

@@ -1,0 +1,596 @@
+// mw_blas.hip -- element-wise operations, AXPY, DOT and SpMV of libmwcg
+// (gfx950).  Method: Mukunoki & Ozaki, arXiv 2510.13536, Sec. III (the
+// multi-word algorithms) and Sec. IV-B (CSR SpMV, DOT, AXPY).
+//
+// SpMV kernels
+//   mw_csr_spmv_kernel   CSR input as given.  A workgroup owns NT rows;
+//                        its nonzeros are streamed through LDS in coalesced
+//                        chunks (each thread forms FP64 x multi-word
+//                        products), then every row's thread adds its own
+//                        products in CSR order.
+//   mw_sell_spmv_kernel  the planned form (SELL-64): slices of 64 rows, one
+//                        wavefront per slice and one lane per row, the
+//                        slice's entries stored column-major so every load
+//                        of values and column indices is one contiguous
+//                        512-byte wavefront access.  Each lane walks its
+//                        row's entries in CSR order; padding entries (col
+//                        -1) are skipped, not added as zeros.
+// Both sum every row sequentially from zero in CSR order, so both are
+// bit-identical to that definition, whatever the launch shape.
+#include "mw_blas.hpp"
+
+#include <cstring>
+
+using namespace mwk;
+
+// ================================================================ host errors
+
+namespace mwh {
+
+thread_local char g_err[256] = "";
+
+int hip_fail(hipError_t e, const char *what)
+{
+    snprintf(g_err, sizeof(g_err), "%s: %s", what, hipGetErrorString(e));
+    return MW_EHIP;
+}
+
+void set_error(const char *msg) { snprintf(g_err, sizeof(g_err), "%s", msg); }
+
+}  // namespace mwh
+
+namespace {
+
+using namespace mwh;
+
+// Loads of the matrix stream in the planned SpMV.  For 3-word vectors the
+// CG working set (four vectors of 24 bytes per row) competes with the
+// matrix stream for the 256 MB Infinity Cache; the matrix entries are used
+// once per SpMV, so they are loaded non-temporally there.  For 1- and
+// 2-word vectors plain loads measured faster.
+template <int A, typename T>
+__device__ __forceinline__ T load_matrix(const T *p)
+{
+    if constexpr (words(A) == 3) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+#define MW_LDM(p) load_matrix<A>(p)
+
+constexpr int DOT_EPT = 8;        // elements per thread in the standalone dot
+constexpr int CSR_NPT = 4;        // nonzeros per thread per LDS chunk (CSR SpMV)
+
+// ------------------------------------------------------------ element-wise
+
+template <int A, int OP>
+__global__ void __launch_bounds__(NT) mw_elementwise_kernel(int n, const double *u, const double *v, double *w)
+{
+    const long i = (long)blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    if constexpr (OP == MW_OP_TOFP64) {
+        const double r = to_fp64<A>(load<A>(u, n, i));
+        w[i] = r;
+    } else if constexpr (OP == MW_OP_DXMUL) {
+        const double a = u[i];
+        const Num<A> r = dxmul<A>(a, load<A>(v, n, i));
+        store<A>(w, n, i, r);
+    } else {
+        const Num<A> a = load<A>(u, n, i);
+        Num<A> r;
+        if constexpr (OP == MW_OP_ADD) r = add<A>(a, load<A>(v, n, i));
+        else if constexpr (OP == MW_OP_MUL) r = mul<A>(a, load<A>(v, n, i));
+        else if constexpr (OP == MW_OP_DIV) r = div<A>(a, load<A>(v, n, i));
+        else if constexpr (OP == MW_OP_NORM) r = normalise<A>(a);
+        else r = neg<A>(a);
+        store<A>(w, n, i, r);
+    }
+}
+
+template <int A>
+__global__ void __launch_bounds__(NT) mw_axpy_kernel(int n, const double *__restrict__ alpha,
+                                                     const double *__restrict__ x, double *__restrict__ y)
+{
+    const long i = (long)xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+    if (i >= n) return;
+    const Num<A> al = load_scalar<A>(alpha);
+    store<A>(y, n, i, axpy_term<A>(al, load<A>(x, n, i), load<A>(y, n, i)));
+}
+
+// --------------------------------------------------------------------- dot
+
+template <int A>
+__global__ void __launch_bounds__(NT) mw_dot_partial_kernel(int n, const double *__restrict__ x,
+                                                            const double *__restrict__ y, double *__restrict__ slots)
+{
+    constexpr int K = words(A);
+    const long base = (long)blockIdx.x * NT * DOT_EPT + threadIdx.x;
+    Num<A> acc = zero<A>();
+#pragma unroll
+    for (int j = 0; j < DOT_EPT; ++j) {
+        const long i = base + (long)j * NT;
+        if (i < n) acc = dot_step<A>(acc, load<A>(x, n, i), load<A>(y, n, i));
+    }
+    const Num<A> s = block_sum<A, NT>(acc);
+    if (threadIdx.x == 0) store_scalar<A>(slots + (long)blockIdx.x * K, s);
+}
+
+template <int A>
+__global__ void __launch_bounds__(FIN_NT) mw_reduce_slots_kernel(int nslots, const double *__restrict__ slots,
+                                                                 double *__restrict__ result)
+{
+    const Num<A> s = reduce_slots<A>(nslots, slots);
+    if (threadIdx.x == 0) store_scalar<A>(result, s);
+}
+
+// --------------------------------------------------------------- CSR SpMV
+//
+// One workgroup owns NT consecutive rows (one per thread).  Its nonzeros
+// [row_ptr[r0], row_ptr[r0 + NT]) are processed in chunks of CH = NT *
+// CSR_NPT: thread t loads nonzeros t, t + NT, ... of the chunk (coalesced
+// val/col streams, gathered x_j) and leaves the FP64 x multi-word product
+// in LDS (FP64: the pair (a_ij, x_j), whose accumulation is one fma); then
+// every thread adds the products of its own row that fall in the chunk, in
+// CSR order, into a register accumulator that persists across chunks.
+// MODE 1 (CG): also the partial of p^T q into slots[logical workgroup].
+template <int A, int MODE>
+__global__ void __launch_bounds__(NT) mw_csr_spmv_kernel(int n, const int32_t *__restrict__ row_ptr,
+                                                         const int32_t *__restrict__ col,
+                                                         const double *__restrict__ val,
+                                                         const double *__restrict__ x, double *__restrict__ y,
+                                                         double *__restrict__ slots, const CgState *__restrict__ st)
+{
+    constexpr int K = words(A);
+    constexpr int CH = NT * CSR_NPT;
+    constexpr int LW = (A == FP64) ? 2 : K;
+    __shared__ double lds[LW][CH];
+
+    if constexpr (MODE == 1) {
+        if (!st->active) return;
+    }
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int r0 = lb * NT;
+    const int r1 = min(r0 + NT, n);
+    const int row = r0 + (int)threadIdx.x;
+    const int z0 = row_ptr[r0];
+    const int z1 = row_ptr[r1];
+    int rs = 0, re = 0;
+    if (row < n) {
+        rs = row_ptr[row];
+        re = row_ptr[row + 1];
+    }
+    Num<A> acc = zero<A>();
+    for (int c0 = z0; c0 < z1; c0 += CH) {
+        const int cn = min(CH, z1 - c0);
+#pragma unroll
+        for (int j = 0; j < CSR_NPT; ++j) {
+            const int t = (int)threadIdx.x + j * NT;
+            if (t < cn) {
+                const double a = val[c0 + t];
+                const Num<A> xj = load<A>(x, n, col[c0 + t]);
+                if constexpr (A == FP64) {
+                    lds[0][t] = a;
+                    lds[1][t] = xj.w[0];
+                } else {
+                    const Num<A> pr = dxmul<A>(a, xj);
+#pragma unroll
+                    for (int w = 0; w < K; ++w) lds[w][t] = pr.w[w];
+                }
+            }
+        }
+        __syncthreads();
+        const int zb = max(rs, c0), ze = min(re, c0 + cn);
+        for (int z = zb; z < ze; ++z) {
+            const int t = z - c0;
+            if constexpr (A == FP64) {
+                acc.w[0] = __builtin_fma(lds[0][t], lds[1][t], acc.w[0]);
+            } else {
+                Num<A> pr;
+#pragma unroll
+                for (int w = 0; w < K; ++w) pr.w[w] = lds[w][t];
+                acc = add<A>(acc, pr);
+            }
+        }
+        __syncthreads();
+    }
+    if (row < n) store<A>(y, n, row, acc);
+    if constexpr (MODE == 1) {
+        Num<A> c = zero<A>();
+        if (row < n) c = dot_step<A>(c, load<A>(x, n, row), acc);
+        const Num<A> sum = block_sum<A, NT>(c);
+        if (threadIdx.x == 0) store_scalar<A>(slots + (long)lb * K, sum);
+    }
+}
+
+// -------------------------------------------------------------- SELL SpMV
+//
+// Persistent workgroups of NWAVE wavefronts walk tiles of NWAVE slices
+// (xcd_tiles); wavefront w of a tile takes slice 4t + w, lane l its row
+// 64 s + l.  Entry j of that row sits at slice_ptr[s] + 64 j + l.
+// MODE 1 (CG): x is p, y is q; each thread accumulates p_i q_i over its
+// rows in tile order, and the workgroup sum goes to slots[blockIdx.x].
+template <int A, int MODE>
+__global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const int32_t *__restrict__ sp,
+                                                          const int32_t *__restrict__ sc,
+                                                          const double *__restrict__ sv,
+                                                          const double *__restrict__ x, double *__restrict__ y,
+                                                          double *__restrict__ slots, const CgState *__restrict__ st)
+{
+    constexpr int K = words(A);
+    if constexpr (MODE == 1) {
+        if (!st->active) return;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const TileRange tr = xcd_tiles((ns + NWAVE - 1) / NWAVE);
+    Num<A> part = zero<A>();
+    for (int t = tr.first; t < tr.end; t += tr.step) {
+        const int s = t * NWAVE + wave;
+        if (s >= ns) continue;  // whole wavefront
+        const int row = s * 64 + lane;
+        const int e = sp[s + 1];
+        int z = sp[s] + lane;
+        Num<A> acc = zero<A>();
+        for (; z + 64 < e; z += 128) {
+            const double a0 = MW_LDM(sv + z), a1 = MW_LDM(sv + z + 64);
+            const int c0 = MW_LDM(sc + z), c1 = MW_LDM(sc + z + 64);
+            const Num<A> x0 = load<A>(x, n, c0 < 0 ? 0 : c0);
+            const Num<A> x1 = load<A>(x, n, c1 < 0 ? 0 : c1);
+            if (c0 >= 0) acc = row_step<A>(acc, a0, x0);
+            if (c1 >= 0) acc = row_step<A>(acc, a1, x1);
+        }
+        if (z < e) {
+            const double a0 = MW_LDM(sv + z);
+            const int c0 = MW_LDM(sc + z);
+            const Num<A> x0 = load<A>(x, n, c0 < 0 ? 0 : c0);
+            if (c0 >= 0) acc = row_step<A>(acc, a0, x0);
+        }
+        if (row < n) {
+            store<A>(y, n, row, acc);
+            if constexpr (MODE == 1) part = dot_step<A>(part, load<A>(x, n, row), acc);
+        }
+    }
+    if constexpr (MODE == 1) {
+        const Num<A> sum = block_sum<A, NT>(part);
+        if (threadIdx.x == 0) store_scalar<A>(slots + (long)blockIdx.x * K, sum);
+    }
+}
+
+// -------------------------------------------------------------- SELL plan
+
+// Width (longest row) of every 64-row slice: one wavefront per slice.
+__global__ void __launch_bounds__(NT) mw_sell_width_kernel(int n, int ns, const int32_t *__restrict__ row_ptr,
+                                                           int32_t *__restrict__ width)
+{
+    const int s = blockIdx.x * NWAVE + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (s >= ns) return;
+    const int row = s * 64 + lane;
+    int len = row < n ? row_ptr[row + 1] - row_ptr[row] : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+    if (lane == 0) width[s] = len;
+}
+
+// Exclusive scan of 64 * width into slice_ptr (one workgroup of FIN_NT
+// threads, each owning a contiguous range of slices).  The 64-bit total is
+// written to *total; slice_ptr is meaningful only if the total fits int32.
+__global__ void __launch_bounds__(FIN_NT) mw_sell_scan_kernel(int ns, const int32_t *__restrict__ width,
+                                                              int32_t *__restrict__ slice_ptr,
+                                                              long long *__restrict__ total)
+{
+    __shared__ long long sums[FIN_NT];
+    const int t = threadIdx.x;
+    const int per = (ns + FIN_NT - 1) / FIN_NT;
+    const int lo = min(t * per, ns), hi = min(lo + per, ns);
+    long long s = 0;
+    for (int i = lo; i < hi; ++i) s += 64LL * width[i];
+    sums[t] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the FIN_NT thread sums
+    for (int off = 1; off < FIN_NT; off <<= 1) {
+        const long long v = (t >= off) ? sums[t - off] : 0;
+        __syncthreads();
+        sums[t] += v;
+        __syncthreads();
+    }
+    long long run = sums[t] - s;
+    for (int i = lo; i < hi; ++i) {
+        slice_ptr[i] = (int32_t)run;
+        run += 64LL * width[i];
+    }
+    if (t == FIN_NT - 1) {
+        slice_ptr[ns] = (int32_t)sums[t];
+        *total = sums[t];
+    }
+}
+
+// Scatter the CSR rows into the slices (column-major inside a slice).
+__global__ void __launch_bounds__(NT) mw_sell_fill_kernel(int n, int ns, const int32_t *__restrict__ row_ptr,
+                                                          const int32_t *__restrict__ col,
+                                                          const double *__restrict__ val,
+                                                          const int32_t *__restrict__ slice_ptr,
+                                                          int32_t *__restrict__ scol, double *__restrict__ sval)
+{
+    const int s = blockIdx.x * NWAVE + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (s >= ns) return;
+    const int row = s * 64 + lane;
+    const int b = slice_ptr[s];
+    const int w = (slice_ptr[s + 1] - b) / 64;
+    const int rs = row < n ? row_ptr[row] : 0;
+    const int len = row < n ? row_ptr[row + 1] - rs : 0;
+    for (int j = 0; j < w; ++j) {
+        const int pos = b + 64 * j + lane;
+        if (j < len) {
+            sval[pos] = val[rs + j];
+            scol[pos] = col[rs + j];
+        } else {
+            sval[pos] = 0.0;
+            scol[pos] = -1;
+        }
+    }
+}
+
+// Plan buffer layout.
+struct PlanLayout {
+    size_t slice_ptr, width, total, col, val, bytes;
+    long long cap;  // entries the buffer can hold
+};
+
+PlanLayout plan_layout(int32_t n, int32_t nnz)
+{
+    const long long ns = (n + 63) / 64;
+    PlanLayout L;
+    L.cap = (long long)nnz + (long long)nnz / 4 + 64 * ns;
+    L.slice_ptr = 0;
+    L.width = align256(sizeof(int32_t) * (ns + 1));
+    L.total = L.width + align256(sizeof(int32_t) * ns);
+    L.col = L.total + 256;
+    L.val = L.col + align256(sizeof(int32_t) * L.cap);
+    L.bytes = L.val + align256(sizeof(double) * L.cap);
+    return L;
+}
+
+long long *pinned_total()
+{
+    thread_local long long *buf = nullptr;
+    if (!buf && hipHostMalloc((void **)&buf, 64, hipHostMallocDefault) != hipSuccess) buf = nullptr;
+    return buf;
+}
+
+}  // namespace
+
+// ============================================================ internal API
+
+namespace mwh {
+
+int spmv_max_slots(int32_t n)
+{
+    const int csr = blocks_for(n, NT);
+    return csr > MAX_GRID ? csr : MAX_GRID;
+}
+
+template <int A>
+int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, double *y, double *slots,
+                const CgState *st, int mode, hipStream_t s, int *nslots)
+{
+    if (plan && plan->format == MW_FMT_SELL64) {
+        const int ns = plan->nslices;
+        const int g = persistent_grid(blocks_for(ns, NWAVE));
+        if (mode == 0)
+            hipLaunchKernelGGL((mw_sell_spmv_kernel<A, 0>), dim3(g), dim3(NT), 0, s, M->n, ns, plan->slice_ptr,
+                               plan->col, plan->val, x, y, slots, st);
+        else
+            hipLaunchKernelGGL((mw_sell_spmv_kernel<A, 1>), dim3(g), dim3(NT), 0, s, M->n, ns, plan->slice_ptr,
+                               plan->col, plan->val, x, y, slots, st);
+        if (nslots) *nslots = g;
+    } else {
+        const int nb = blocks_for(M->n, NT);
+        if (mode == 0)
+            hipLaunchKernelGGL((mw_csr_spmv_kernel<A, 0>), dim3(nb), dim3(NT), 0, s, M->n, M->row_ptr, M->col_idx,
+                               M->val, x, y, slots, st);
+        else
+            hipLaunchKernelGGL((mw_csr_spmv_kernel<A, 1>), dim3(nb), dim3(NT), 0, s, M->n, M->row_ptr, M->col_idx,
+                               M->val, x, y, slots, st);
+        if (nslots) *nslots = nb;
+    }
+    HIP_TRY(hipGetLastError());
+    return MW_OK;
+}
+
+template int spmv_launch<FP64>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
+                               const CgState *, int, hipStream_t, int *);
+template int spmv_launch<DW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
+                             const CgState *, int, hipStream_t, int *);
+template int spmv_launch<QDW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
+                              const CgState *, int, hipStream_t, int *);
+template int spmv_launch<TW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
+                             const CgState *, int, hipStream_t, int *);
+template int spmv_launch<QTW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
+                              const CgState *, int, hipStream_t, int *);
+
+size_t plan_bytes(int32_t n, int32_t nnz) { return plan_layout(n, nnz).bytes; }
+
+int plan_build(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *plan, hipStream_t s)
+{
+    const int n = A->n;
+    const int ns = (n + 63) / 64;
+    const PlanLayout L = plan_layout(n, A->nnz);
+    if (bytes < L.bytes) return MW_EINVAL;
+    char *base = (char *)buffer;
+    int32_t *sp = (int32_t *)(base + L.slice_ptr);
+    int32_t *width = (int32_t *)(base + L.width);
+    long long *total = (long long *)(base + L.total);
+    int32_t *scol = (int32_t *)(base + L.col);
+    double *sval = (double *)(base + L.val);
+    long long *htot = pinned_total();
+    if (!htot) return hip_fail(hipErrorOutOfMemory, "hipHostMalloc");
+
+    memset(plan, 0, sizeof(*plan));
+    plan->n = n;
+    plan->nnz = A->nnz;
+    plan->nslices = ns;
+    plan->csr = *A;
+    plan->format = MW_FMT_CSR;
+
+    const int nbw = blocks_for(ns, NWAVE);
+    hipLaunchKernelGGL(mw_sell_width_kernel, dim3(nbw), dim3(NT), 0, s, n, ns, A->row_ptr, width);
+    hipLaunchKernelGGL(mw_sell_scan_kernel, dim3(1), dim3(FIN_NT), 0, s, ns, width, sp, total);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(htot, total, sizeof(long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const long long stored = *htot;
+    if (stored > L.cap || stored > 0x7fffffffLL) return MW_OK;  // CSR fallback
+    hipLaunchKernelGGL(mw_sell_fill_kernel, dim3(nbw), dim3(NT), 0, s, n, ns, A->row_ptr, A->col_idx, A->val, sp,
+                       scol, sval);
+    HIP_TRY(hipGetLastError());
+    plan->format = MW_FMT_SELL64;
+    plan->stored = stored;
+    plan->slice_ptr = sp;
+    plan->col = scol;
+    plan->val = sval;
+    return MW_OK;
+}
+
+}  // namespace mwh
+
+namespace {
+
+template <int A, int OP>
+int launch_elementwise(int32_t n, const double *u, const double *v, double *w, hipStream_t s)
+{
+    hipLaunchKernelGGL((mw_elementwise_kernel<A, OP>), dim3(blocks_for(n, NT)), dim3(NT), 0, s, n, u, v, w);
+    HIP_TRY(hipGetLastError());
+    return MW_OK;
+}
+
+template <int A>
+int elementwise_a(int op, int32_t n, const double *u, const double *v, double *w, hipStream_t s)
+{
+    switch (op) {
+    case MW_OP_ADD: return launch_elementwise<A, MW_OP_ADD>(n, u, v, w, s);
+    case MW_OP_MUL: return launch_elementwise<A, MW_OP_MUL>(n, u, v, w, s);
+    case MW_OP_DXMUL: return launch_elementwise<A, MW_OP_DXMUL>(n, u, v, w, s);
+    case MW_OP_DIV: return launch_elementwise<A, MW_OP_DIV>(n, u, v, w, s);
+    case MW_OP_NORM: return launch_elementwise<A, MW_OP_NORM>(n, u, v, w, s);
+    case MW_OP_NEG: return launch_elementwise<A, MW_OP_NEG>(n, u, v, w, s);
+    default: return launch_elementwise<A, MW_OP_TOFP64>(n, u, v, w, s);
+    }
+}
+
+template <int A>
+int axpy_a(int32_t n, const double *alpha, const double *x, double *y, hipStream_t s)
+{
+    hipLaunchKernelGGL((mw_axpy_kernel<A>), dim3(blocks_for(n, NT)), dim3(NT), 0, s, n, alpha, x, y);
+    HIP_TRY(hipGetLastError());
+    return MW_OK;
+}
+
+template <int A>
+int dot_a(int32_t n, const double *x, const double *y, double *res, void *ws, hipStream_t s)
+{
+    const int nb = n > 0 ? blocks_for(n, (long)NT * DOT_EPT) : 0;
+    double *slots = (double *)ws;
+    if (nb > 0) {
+        hipLaunchKernelGGL((mw_dot_partial_kernel<A>), dim3(nb), dim3(NT), 0, s, n, x, y, slots);
+        HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL((mw_reduce_slots_kernel<A>), dim3(1), dim3(FIN_NT), 0, s, nb, slots, res);
+    HIP_TRY(hipGetLastError());
+    return MW_OK;
+}
+
+template <int A>
+int spmv_csr_a(const mw_csr_t *M, const double *x, double *y, hipStream_t s)
+{
+    return mwh::spmv_launch<A>(M, nullptr, x, y, nullptr, nullptr, 0, s);
+}
+
+template <int A>
+int spmv_planned_a(const mw_spmv_plan_t *P, const double *x, double *y, hipStream_t s)
+{
+    return mwh::spmv_launch<A>(&P->csr, P, x, y, nullptr, nullptr, 0, s);
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+int mw_words(mw_arith_t a) { return mwh::valid_arith(a) ? words(a) : -1; }
+
+const char *mw_status_string(int code)
+{
+    switch (code) {
+    case MW_OK: return "ok";
+    case MW_NOT_CONVERGED: return "not converged (maxit reached)";
+    case MW_BREAKDOWN: return "breakdown (p^T A p <= 0 or non-finite scalar)";
+    case MW_EINVAL: return "invalid argument";
+    case MW_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+const char *mw_last_error(void) { return mwh::g_err; }
+
+int mw_elementwise(mw_arith_t a, int op, int32_t n, const double *u, const double *v, double *w, void *stream)
+{
+    if (!valid_arith(a) || op < MW_OP_ADD || op > MW_OP_TOFP64 || n < 0 || (n > 0 && (!u || !w)))
+        return MW_EINVAL;
+    const bool needs_v = (op == MW_OP_ADD || op == MW_OP_MUL || op == MW_OP_DXMUL || op == MW_OP_DIV);
+    if (needs_v && n > 0 && !v) return MW_EINVAL;
+    if (n == 0) return MW_OK;
+    hipStream_t s = (hipStream_t)stream;
+    MW_DISPATCH(a, elementwise_a, op, n, u, v, w, s);
+}
+
+int mw_axpy(mw_arith_t a, int32_t n, const double *alpha, const double *x, double *y, void *stream)
+{
+    if (!valid_arith(a) || n < 0 || (n > 0 && (!alpha || !x || !y))) return MW_EINVAL;
+    if (n == 0) return MW_OK;
+    hipStream_t s = (hipStream_t)stream;
+    MW_DISPATCH(a, axpy_a, n, alpha, x, y, s);
+}
+
+size_t mw_dot_workspace_bytes(mw_arith_t a, int32_t n)
+{
+    if (!valid_arith(a) || n < 0) return 0;
+    const size_t nb = (size_t)(n > 0 ? blocks_for(n, (long)NT * DOT_EPT) : 0);
+    return align256(sizeof(double) * words(a) * (nb > 0 ? nb : 1));
+}
+
+int mw_dot(mw_arith_t a, int32_t n, const double *x, const double *y, double *result, void *workspace,
+           void *stream)
+{
+    if (!valid_arith(a) || n < 0 || !result || !workspace || (n > 0 && (!x || !y))) return MW_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    MW_DISPATCH(a, dot_a, n, x, y, result, workspace, s);
+}
+
+int mw_spmv(mw_arith_t a, const mw_csr_t *A, const double *x, double *y, void *stream)
+{
+    if (!valid_arith(a) || !valid_csr(A) || !x || !y || x == y) return MW_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    MW_DISPATCH(a, spmv_csr_a, A, x, y, s);
+}
+
+size_t mw_spmv_plan_bytes(int32_t n, int32_t nnz)
+{
+    if (n <= 0 || nnz < 0) return 0;
+    return mwh::plan_bytes(n, nnz);
+}
+
+int mw_spmv_plan(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *plan, void *stream)
+{
+    if (!valid_csr(A) || !buffer || !plan) return MW_EINVAL;
+    return mwh::plan_build(A, buffer, bytes, plan, (hipStream_t)stream);
+}
+
+int mw_spmv_planned(mw_arith_t a, const mw_spmv_plan_t *plan, const double *x, double *y, void *stream)
+{
+    if (!valid_arith(a) || !plan || !valid_csr(&plan->csr) || !x || !y || x == y) return MW_EINVAL;
+    if (plan->format == MW_FMT_SELL64 && (!plan->slice_ptr || !plan->col || !plan->val)) return MW_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    MW_DISPATCH(a, spmv_planned_a, plan, x, y, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// mw_common.hpp -- launch geometry, reductions and host helpers shared by
+// the libmwcg kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "mw.h"
+#include "mw_arith.hpp"
+
+namespace mwk {
+
+constexpr int NT = 256;          // threads per workgroup of the streaming kernels
+constexpr int NWAVE = NT / 64;   // wavefronts per workgroup
+constexpr int FIN_NT = 1024;     // threads of the one-workgroup finalisers
+constexpr int MAX_GRID = 2048;   // workgroups of the persistent streaming kernels
+constexpr int NXCD = 8;          // XCDs per MI355X; workgroups are dealt to them round-robin
+
+// ------------------------------------------------------- tile scheduling
+//
+// Persistent streaming kernels walk "tiles" (units of NT rows).  The tile
+// range is split into NXCD contiguous parts; workgroup b runs on XCD b % 8
+// and takes the tiles of that XCD's part with a stride equal to the number
+// of workgroups on that XCD.  Neighbouring rows are thus handled inside one
+// XCD and share its L2.  The assignment is static, so any per-workgroup
+// partial sum has a fixed association.  Requires gridDim.x >= min(8, ntiles).
+struct TileRange {
+    int first, end, step;
+};
+
+__device__ __forceinline__ TileRange xcd_tiles(int ntiles)
+{
+    const int G = gridDim.x;
+    const int xcd = blockIdx.x & (NXCD - 1), j = blockIdx.x / NXCD;
+    const int nbx = G / NXCD + (xcd < (G & (NXCD - 1)) ? 1 : 0);
+    const int q = ntiles / NXCD, rem = ntiles & (NXCD - 1);
+    const int t0 = xcd * q + (xcd < rem ? xcd : rem);
+    const int t1 = t0 + q + (xcd < rem ? 1 : 0);
+    return TileRange{t0 + j, t1, nbx};
+}
+
+// Grid size of a persistent streaming kernel over ntiles tiles.
+inline int persistent_grid(long ntiles)
+{
+    return (int)(ntiles < MAX_GRID ? (ntiles > 0 ? ntiles : 1) : MAX_GRID);
+}
+
+// Workgroup index remap for one-tile-per-workgroup kernels: XCD x gets the
+// x-th contiguous range of logical workgroups.
+__device__ __forceinline__ int xcd_remap(int bid, int nb)
+{
+    const int q = nb / NXCD, rem = nb & (NXCD - 1);
+    const int x = bid & (NXCD - 1), j = bid / NXCD;
+    return x * q + (x < rem ? x : rem) + j;
+}
+
+// ------------------------------------------------------------ reductions
+
+// Sum over a workgroup of NTHR threads; result valid in thread 0.  Order:
+// shuffle tree inside each wavefront (offsets 32, 16, ..., 1), then the
+// wavefront sums pairwise (a fixed binary tree over wavefront index).
+template <int A, int NTHR>
+__device__ __forceinline__ Num<A> block_sum(Num<A> v)
+{
+    constexpr int NW = NTHR / 64;
+    __shared__ Num<A> part[NW];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = add<A>(v, shfl_down<A>(v, off));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) part[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int s = 1; s < NW; s <<= 1)
+#pragma unroll
+            for (int i = 0; i + s < NW; i += 2 * s) part[i] = add<A>(part[i], part[i + s]);
+        v = part[0];
+    }
+    __syncthreads();
+    return v;
+}
+
+// Sum of nslots k-word partials (slot s at slots + s*K) by one FIN_NT
+// workgroup: thread t adds slots t, t + FIN_NT, ... in order (loads issued
+// ahead of the dependent adds), then block_sum.
+template <int A>
+__device__ __forceinline__ Num<A> reduce_slots(int nslots, const double *__restrict__ slots)
+{
+    constexpr int K = words(A);
+    constexpr int B = 4;
+    Num<A> acc = zero<A>();
+    for (int s0 = threadIdx.x; s0 < nslots; s0 += FIN_NT * B) {
+        Num<A> v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int s = s0 + u * FIN_NT;
+            v[u] = (s < nslots) ? load_scalar<A>(slots + (long)s * K) : zero<A>();
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (s0 + u * FIN_NT < nslots) acc = add<A>(acc, v[u]);
+    }
+    return block_sum<A, FIN_NT>(acc);
+}
+
+// acc + x*y as a dot-product step (FP64: one fma).
+template <int A>
+__device__ __forceinline__ Num<A> dot_step(const Num<A> &acc, const Num<A> &x, const Num<A> &y)
+{
+    if constexpr (A == FP64) return promote<A>(__builtin_fma(x.w[0], y.w[0], acc.w[0]));
+    else return add<A>(acc, mul<A>(x, y));
+}
+
+// One step of a row sum: acc + a*x (FP64: fma; else FP64 x multi-word).
+template <int A>
+__device__ __forceinline__ Num<A> row_step(const Num<A> &acc, double a, const Num<A> &x)
+{
+    if constexpr (A == FP64) return promote<A>(__builtin_fma(a, x.w[0], acc.w[0]));
+    else return add<A>(acc, dxmul<A>(a, x));
+}
+
+}  // namespace mwk
+
+// ------------------------------------------------------------ host side
+
+namespace mwh {
+
+int hip_fail(hipError_t e, const char *what);
+void set_error(const char *msg);
+
+inline int blocks_for(long n, long per) { return (int)((n + per - 1) / per); }
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+inline bool valid_arith(int a) { return a >= MW_FP64 && a <= MW_QTW; }
+inline bool valid_csr(const mw_csr_t *A)
+{
+    return A && A->n > 0 && A->nnz >= 0 && A->row_ptr && A->col_idx && A->val;
+}
+
+}  // namespace mwh
+
+#define HIP_TRY(call)                                              \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) return mwh::hip_fail(e_, #call);     \
+    } while (0)
+
+#define MW_DISPATCH(a, fn, ...)                          \
+    switch (a) {                                         \
+    case MW_FP64: return fn<mwk::FP64>(__VA_ARGS__);     \
+    case MW_DW: return fn<mwk::DW>(__VA_ARGS__);         \
+    case MW_QDW: return fn<mwk::QDW>(__VA_ARGS__);       \
+    case MW_TW: return fn<mwk::TW>(__VA_ARGS__);         \
+    default: return fn<mwk::QTW>(__VA_ARGS__);           \
+    }

@@ -34,8 +34,38 @@ class CgInfo(C.Structure):
                 ("seconds", C.c_double)]
 
 
+PROF_CLASSES = ("spmv", "update_r", "update_p", "final")
+
+
+class CgProf(C.Structure):
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4), ("mask", C.c_int32),
+                ("reserved", C.c_int32)]
+
+    @classmethod
+    def of(cls, *classes):
+        """A timing request for the named classes (none named: all)."""
+        p = cls()
+        p.mask = sum(1 << PROF_CLASSES.index(c) for c in classes)
+        return p
+
+    def as_dict(self):
+        return {c: {"ms": self.ms[i], "launches": self.launches[i],
+                    "avg_us": 1e3 * self.ms[i] / self.launches[i] if self.launches[i] else None}
+                for i, c in enumerate(PROF_CLASSES)}
+
+
+FMT = {0: "csr", 1: "sell64"}
+
+
+class SpmvPlan(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("format", C.c_int32), ("nslices", C.c_int32),
+                ("stored", C.c_int64), ("slice_ptr", _vp), ("col", _vp), ("val", _vp), ("csr", Csr)]
+
+
 class CgOpts(C.Structure):
-    _fields_ = [("normalize", C.c_int32), ("chunk", C.c_int32), ("history", _vp)]
+    _fields_ = [("normalize", C.c_int32), ("chunk", C.c_int32), ("history", _vp),
+                ("prof", C.POINTER(CgProf)), ("plan", C.POINTER(SpmvPlan)), ("no_graph", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class MWError(RuntimeError):
@@ -77,6 +107,10 @@ def lib():
     L.mw_dot_workspace_bytes.restype = C.c_size_t
     L.mw_dot.argtypes = [C.c_int, C.c_int32, _vp, _vp, _vp, _vp, _vp]
     L.mw_spmv.argtypes = [C.c_int, C.POINTER(Csr), _vp, _vp, _vp]
+    L.mw_spmv_plan_bytes.argtypes = [C.c_int32, C.c_int32]
+    L.mw_spmv_plan_bytes.restype = C.c_size_t
+    L.mw_spmv_plan.argtypes = [C.POINTER(Csr), _vp, C.c_size_t, C.POINTER(SpmvPlan), _vp]
+    L.mw_spmv_planned.argtypes = [C.c_int, C.POINTER(SpmvPlan), _vp, _vp, _vp]
     L.mw_cg_workspace_bytes.argtypes = [C.c_int, C.c_int32, C.c_int32]
     L.mw_cg_workspace_bytes.restype = C.c_size_t
     L.mw_cg_solve.argtypes = [C.c_int, C.POINTER(Csr), _vp, _vp, C.c_double, C.c_int32,
@@ -198,14 +232,50 @@ def spmv(arith, A, x, y=None):
     return y
 
 
+class Plan:
+    """A SpMV plan of a DeviceCSR (SELL-64 layout, or the CSR fallback)."""
+
+    def __init__(self, A):
+        self.A = A
+        nbytes = lib().mw_spmv_plan_bytes(A.n, A.nnz)
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=A.val.device)
+        self.c = SpmvPlan()
+        self._csr = A.c()
+        _check(lib().mw_spmv_plan(C.byref(self._csr), _ptr(self.buffer), nbytes, C.byref(self.c), _stream()),
+               "mw_spmv_plan")
+
+    @property
+    def format(self):
+        return FMT[self.c.format]
+
+    @property
+    def stored(self):
+        return int(self.c.stored)
+
+
+def spmv_planned(arith, plan, x, y=None):
+    """y = A x with a Plan (bit-identical to spmv)."""
+    k = WORDS[arith]
+    x = _vec(x, k, plan.A.n, name="x")
+    if y is None:
+        y = torch.empty_like(x)
+    y = _vec(y, k, plan.A.n, name="y")
+    _check(lib().mw_spmv_planned(ARITH[arith], C.byref(plan.c), _ptr(x), _ptr(y), _stream()), "mw_spmv_planned")
+    return y
+
+
 def cg_workspace(arith, A, device=None):
     nbytes = lib().mw_cg_workspace_bytes(ARITH[arith], A.n, A.nnz)
     return torch.empty(nbytes, dtype=torch.uint8, device=device or A.val.device)
 
 
 def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0, history=False,
-             workspace=None):
-    """Solve A x = b by CG in `arith`.  Returns (x (k, n) tensor, info dict)."""
+             workspace=None, prof=None, plan=None, graph=True):
+    """Solve A x = b by CG in `arith`.  Returns (x (k, n) tensor, info dict).
+
+    prof: a CgProf to accumulate per-kernel device times into (optional);
+    plan: a Plan of A to reuse (optional; else one is built per call);
+    graph: replay captured chunks (True) or launch kernels directly."""
     k = WORDS[arith]
     b = b.reshape(-1)
     if not (b.is_cuda and b.dtype == torch.float64 and b.is_contiguous() and b.numel() == A.n):
@@ -218,7 +288,9 @@ def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0
     if workspace is None:
         workspace = cg_workspace(arith, A, b.device)
     hist = torch.zeros(max(int(maxit), 1), dtype=torch.float64, device=b.device) if history else None
-    opts = CgOpts(1 if normalize else 0, int(chunk), hist.data_ptr() if hist is not None else None)
+    opts = CgOpts(1 if normalize else 0, int(chunk), hist.data_ptr() if hist is not None else None,
+                  C.pointer(prof) if prof is not None else None,
+                  C.pointer(plan.c) if plan is not None else None, 0 if graph else 1, 0)
     info = CgInfo()
     csr = A.c()
     rc = lib().mw_cg_solve(ARITH[arith], C.byref(csr), _ptr(b), _ptr(x), float(tol), int(maxit),

@@ -255,3 +255,70 @@ def test_cg_history_and_nn(mw):
     _, nn = mw.cg_solve("qdw", Ad, dev(b), tol=1e-28, maxit=4000, normalize=False)
     _, on = O.cg_solve("qdw", A, b, tol=1e-28, maxit=4000, normalise=False)
     assert nn["status"] != "ok" and on["status"] != "ok"
+
+
+# ----------------------------------------------------------- planned SpMV
+
+@pytest.mark.parametrize("arith", ARITHS)
+@pytest.mark.parametrize("mat", list(MATRICES))
+def test_spmv_planned_bit_exact(mw, arith, mat):
+    A = MATRICES[mat]()
+    k = O.WORDS[arith]
+    x = rand_mw(np.random.default_rng(12), k, A.n, emin=-4, emax=4)
+    want = O.spmv(arith, A, x)
+    plan = mw.Plan(mw.DeviceCSR.from_host(A))
+    # a row far longer than its slice-mates makes the padding too large:
+    # the plan falls back to the CSR kernel
+    assert plan.format == ("csr" if mat == "ragged" else "sell64")
+    if plan.format == "sell64":
+        assert plan.stored >= A.nnz and plan.stored % 64 == 0
+    got = host(mw.spmv_planned(arith, plan, dev(x)))
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def test_spmv_planned_tiny_and_ragged_tail(mw):
+    # n smaller than one slice, and n one past a slice boundary
+    for n in (1, 5, 65, 64 * 8 + 1):
+        A = P.poisson1d(n)
+        for arith in ("fp64", "qtw"):
+            x = rand_mw(np.random.default_rng(n), O.WORDS[arith], n)
+            want = O.spmv(arith, A, x)
+            plan = mw.Plan(mw.DeviceCSR.from_host(A))
+            got = host(mw.spmv_planned(arith, plan, dev(x)))
+            assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), (n, arith)
+
+
+# --------------------------------------------- graphs, plans and timing
+
+@pytest.mark.parametrize("arith", ["fp64", "qtw"])
+def test_cg_graph_replays_match_direct_launches(mw, arith):
+    import torch
+    A, b, _ = P.case_poisson3d(nx=20)
+    Ad = mw.DeviceCSR.from_host(A)
+    bd = dev(b)
+    ws = mw.cg_workspace(arith, Ad)
+    k = O.WORDS[arith]
+    x = torch.zeros((k, A.n), dtype=torch.float64, device="cuda")
+    _, ref = mw.cg_solve(arith, Ad, bd, x=x, tol=1e-12, workspace=ws, graph=False)
+    xref = host(x).copy()
+    for rep in range(3):  # the captured chunk is reused by every solve
+        x.zero_()
+        junk = torch.ones(1000, device="cuda").cumsum(0)  # eager work between replays
+        _, info = mw.cg_solve(arith, Ad, bd, x=x, tol=1e-12, workspace=ws, chunk=8)
+        assert junk[-1].item() == 1000.0
+        assert info["iters"] == ref["iters"] and info["status"] == "ok"
+        assert np.array_equal(host(x).view(np.uint64), xref.view(np.uint64)), rep
+
+
+def test_cg_with_plan_and_timing(mw):
+    A, b, _ = P.case_poisson3d(nx=24)
+    Ad = mw.DeviceCSR.from_host(A)
+    plan = mw.Plan(Ad)
+    x1, i1 = mw.cg_solve("dw", Ad, dev(b), tol=1e-12)
+    prof = mw.CgProf.of("spmv")
+    x2, i2 = mw.cg_solve("dw", Ad, dev(b), tol=1e-12, plan=plan, prof=prof)
+    assert i1["iters"] == i2["iters"]
+    assert np.array_equal(host(x1).view(np.uint64), host(x2).view(np.uint64))
+    d = prof.as_dict()
+    assert d["spmv"]["launches"] == i2["iters"] - 1 and d["spmv"]["ms"] > 0
+    assert d["update_r"]["launches"] == 0
