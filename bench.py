@@ -35,6 +35,34 @@ def spmv_bytes(n, nnz, k):
     return 12 * nnz + 4 * (n + 1) + 16 * k * n
 
 
+def kernel_source_hash():
+    """Hash of the HIP sources and the ABI header: stored traffic figures
+    are reported only while the kernels are the ones that were profiled."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2510_13536_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "mw.h"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when absent
+    or taken on other kernel sources."""
+    p = os.path.join(ROOT, "profiles", "cg_qtw_poisson3d_128_traffic.json")
+    try:
+        rec = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return round(k["traffic_bytes"]) if k else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -48,6 +76,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the per-arithmetic extras")
     ap.add_argument("--cpu-iters", type=int, default=16)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 256 MiB device copy first (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -61,6 +91,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t = time.time()
     A, b, _ = P.case_poisson3d(args.nx)
     log("problem: 3D Poisson %d^3 n=%d nnz=%d (%.1fs)" % (args.nx, A.n, A.nnz, time.time() - t))
@@ -79,7 +115,7 @@ def main():
         log("warmup solve: %s" % info)
     torch.cuda.synchronize()
 
-    prof = mw.CgProf()
+    prof = mw.CgProf.of("spmv")
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -99,8 +135,8 @@ def main():
     sp_bytes = spmv_bytes(A.n, A.nnz, k)
     achieved = sp_bytes / (sp_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "mw_spmv_kernel<QTW, CG mode>", "bytes_per_launch": sp_bytes,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic("mw_sell_spmv_kernel<4, 1>"),
+                "kernel": "mw_sell_spmv_kernel<QTW, CG mode>", "bytes_per_launch": sp_bytes,
                 "avg_launch_us": round(sp_us, 2), "launches": pd["spmv"]["launches"]}
 
     extra = {"iterations": iters, "device_seconds": infos[-1]["seconds"],
@@ -108,28 +144,34 @@ def main():
              "kernel_avg_us": {c: (round(v["avg_us"], 2) if v["avg_us"] else None) for c, v in pd.items()}}
 
     if not args.quick:
-        # SpMV bandwidth for every arithmetic, MALL flushed between repetitions
-        flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        gbs = {}
+        # Standalone SpMV bandwidth for every arithmetic, planned (SELL-64)
+        # and plain CSR.  Before each repetition the 256 MB Infinity Cache is
+        # flushed by READING a 1 GiB buffer (a write flush would leave dirty
+        # lines whose write-back lands inside the timed kernel).
+        flush = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        sink = torch.zeros(1, dtype=torch.float64, device=dev)
+        plan = mw.Plan(Ad)
+        gbs, gbs_csr = {}, {}
         for ar in WORDS:
             kk = WORDS[ar]
             xv = torch.rand((kk, A.n), dtype=torch.float64, device=dev)
             yv = torch.empty_like(xv)
-            ts = []
-            for rep in range(25):
-                flush.zero_()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                mw.spmv(ar, Ad, xv, yv)
-                e1.record()
-                torch.cuda.synchronize()
-                if rep >= 3:
-                    ts.append(e0.elapsed_time(e1))
-            med = statistics.median(ts)
-            gbs[ar] = round(spmv_bytes(A.n, A.nnz, kk) / (med * 1e-3) / 1e9, 1)
-        del flush
-        extra["spmv_GBps_flushed"] = gbs
-        log("SpMV GB/s: %s" % gbs)
+            for fn, dst in ((lambda: mw.spmv_planned(ar, plan, xv, yv), gbs), (lambda: mw.spmv(ar, Ad, xv, yv), gbs_csr)):
+                ts = []
+                for rep in range(15):
+                    sink.copy_(flush.sum().reshape(1))
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    fn()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    if rep >= 3:
+                        ts.append(e0.elapsed_time(e1))
+                dst[ar] = round(spmv_bytes(A.n, A.nnz, kk) / (statistics.median(ts) * 1e-3) / 1e9, 1)
+        del flush, plan
+        extra["spmv_GBps_planned_flushed"] = gbs
+        extra["spmv_GBps_csr_flushed"] = gbs_csr
+        log("SpMV GB/s planned: %s  csr: %s" % (gbs, gbs_csr))
         # time to solution of every arithmetic (one solve each, after warm-up)
         tts = {}
         for ar in WORDS:

@@ -136,7 +136,8 @@ __global__ void __launch_bounds__(NT) mw_csr_spmv_kernel(int n, const int32_t *_
                                                          const int32_t *__restrict__ col,
                                                          const double *__restrict__ val,
                                                          const double *__restrict__ x, double *__restrict__ y,
-                                                         double *__restrict__ slots, const CgState *__restrict__ st)
+                                                         double *__restrict__ slots, const int32_t *__restrict__ run_prev,
+                                                         int32_t *__restrict__ run_cur)
 {
     constexpr int K = words(A);
     constexpr int CH = NT * CSR_NPT;
@@ -144,7 +145,10 @@ __global__ void __launch_bounds__(NT) mw_csr_spmv_kernel(int n, const int32_t *_
     __shared__ double lds[LW][CH];
 
     if constexpr (MODE == 1) {
-        if (!st->active) return;
+        if (!*run_prev) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) *run_cur = 0;
+            return;
+        }
     }
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int r0 = lb * NT;
@@ -212,11 +216,15 @@ __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const i
                                                           const int32_t *__restrict__ sc,
                                                           const double *__restrict__ sv,
                                                           const double *__restrict__ x, double *__restrict__ y,
-                                                          double *__restrict__ slots, const CgState *__restrict__ st)
+                                                          double *__restrict__ slots, const int32_t *__restrict__ run_prev,
+                                                          int32_t *__restrict__ run_cur)
 {
     constexpr int K = words(A);
     if constexpr (MODE == 1) {
-        if (!st->active) return;
+        if (!*run_prev) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) *run_cur = 0;
+            return;
+        }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const TileRange tr = xcd_tiles((ns + NWAVE - 1) / NWAVE);
@@ -368,28 +376,34 @@ int spmv_max_slots(int32_t n)
     return csr > MAX_GRID ? csr : MAX_GRID;
 }
 
+int spmv_slots(const mw_csr_t *M, const mw_spmv_plan_t *plan)
+{
+    if (plan && plan->format == MW_FMT_SELL64) return persistent_grid(blocks_for(plan->nslices, NWAVE));
+    return blocks_for(M->n, NT);
+}
+
 template <int A>
 int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, double *y, double *slots,
-                const CgState *st, int mode, hipStream_t s, int *nslots)
+                const int32_t *run_prev, int32_t *run_cur, int mode, hipStream_t s, int *nslots)
 {
     if (plan && plan->format == MW_FMT_SELL64) {
         const int ns = plan->nslices;
         const int g = persistent_grid(blocks_for(ns, NWAVE));
         if (mode == 0)
             hipLaunchKernelGGL((mw_sell_spmv_kernel<A, 0>), dim3(g), dim3(NT), 0, s, M->n, ns, plan->slice_ptr,
-                               plan->col, plan->val, x, y, slots, st);
+                               plan->col, plan->val, x, y, slots, run_prev, run_cur);
         else
             hipLaunchKernelGGL((mw_sell_spmv_kernel<A, 1>), dim3(g), dim3(NT), 0, s, M->n, ns, plan->slice_ptr,
-                               plan->col, plan->val, x, y, slots, st);
+                               plan->col, plan->val, x, y, slots, run_prev, run_cur);
         if (nslots) *nslots = g;
     } else {
         const int nb = blocks_for(M->n, NT);
         if (mode == 0)
             hipLaunchKernelGGL((mw_csr_spmv_kernel<A, 0>), dim3(nb), dim3(NT), 0, s, M->n, M->row_ptr, M->col_idx,
-                               M->val, x, y, slots, st);
+                               M->val, x, y, slots, run_prev, run_cur);
         else
             hipLaunchKernelGGL((mw_csr_spmv_kernel<A, 1>), dim3(nb), dim3(NT), 0, s, M->n, M->row_ptr, M->col_idx,
-                               M->val, x, y, slots, st);
+                               M->val, x, y, slots, run_prev, run_cur);
         if (nslots) *nslots = nb;
     }
     HIP_TRY(hipGetLastError());
@@ -397,15 +411,15 @@ int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, 
 }
 
 template int spmv_launch<FP64>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                               const CgState *, int, hipStream_t, int *);
+                               const int32_t *, int32_t *, int, hipStream_t, int *);
 template int spmv_launch<DW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                             const CgState *, int, hipStream_t, int *);
+                             const int32_t *, int32_t *, int, hipStream_t, int *);
 template int spmv_launch<QDW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                              const CgState *, int, hipStream_t, int *);
+                              const int32_t *, int32_t *, int, hipStream_t, int *);
 template int spmv_launch<TW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                             const CgState *, int, hipStream_t, int *);
+                             const int32_t *, int32_t *, int, hipStream_t, int *);
 template int spmv_launch<QTW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                              const CgState *, int, hipStream_t, int *);
+                              const int32_t *, int32_t *, int, hipStream_t, int *);
 
 size_t plan_bytes(int32_t n, int32_t nnz) { return plan_layout(n, nnz).bytes; }
 
@@ -501,13 +515,13 @@ int dot_a(int32_t n, const double *x, const double *y, double *res, void *ws, hi
 template <int A>
 int spmv_csr_a(const mw_csr_t *M, const double *x, double *y, hipStream_t s)
 {
-    return mwh::spmv_launch<A>(M, nullptr, x, y, nullptr, nullptr, 0, s);
+    return mwh::spmv_launch<A>(M, nullptr, x, y, nullptr, nullptr, nullptr, 0, s);
 }
 
 template <int A>
 int spmv_planned_a(const mw_spmv_plan_t *P, const double *x, double *y, hipStream_t s)
 {
-    return mwh::spmv_launch<A>(&P->csr, P, x, y, nullptr, nullptr, 0, s);
+    return mwh::spmv_launch<A>(&P->csr, P, x, y, nullptr, nullptr, nullptr, 0, s);
 }
 
 }  // namespace

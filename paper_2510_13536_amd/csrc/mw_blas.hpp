@@ -6,24 +6,29 @@
 
 namespace mwk {
 
-// Device-resident state of one CG solve.
+// Device-resident state of one CG solve.  Values an iteration produces are
+// kept per iteration parity (index i & 1 for iteration i, parity 0 holding
+// the initial values): iteration i reads only the other parity's entries,
+// which the previous iteration wrote before a kernel boundary, so no
+// workgroup ever reads an entry another workgroup of the same kernel
+// writes.
 struct CgState {
-    double rho[3];    // r^T r of the current iterate
-    double alpha[3];
-    double beta[3];
-    double nb;        // ||b||_2
+    double rho[2][3];    // r^T r after the iteration of each parity
+    double alpha[2][3];  // alpha of the iteration of each parity
+    double nb;           // ||b||_2
     double tol;
-    double rel_res;   // last relative residual
-    double *history;  // optional per-iteration relative residuals
-    int32_t active;   // 1 while iterating
-    int32_t status;   // MW_OK / MW_NOT_CONVERGED / MW_BREAKDOWN
-    int32_t iters;
+    double rel_res;      // relative residual at the stop (or the last test)
+    double *history;     // optional per-iteration relative residuals
+    int32_t run[2];      // the iteration of this parity left the solve running
+    int32_t iters[2];    // iteration count after the iteration of this parity
+    int32_t brk[2];      // the alpha step of this parity broke down
     int32_t maxit;
     int32_t normalize;
-    int32_t x_due;    // the stopping iteration's x update is still to be applied
-    int32_t pad[2];
+    int32_t stopped;     // set once, when the solve stops (polled by the host)
+    int32_t status;      // final status (valid once stopped)
+    int32_t iters_final; // final iteration count (valid once stopped)
+    int32_t pad;
 };
-
 }  // namespace mwk
 
 namespace mwh {
@@ -39,10 +44,13 @@ int spmv_max_slots(int32_t n);
 
 // y = A x.  plan == nullptr or plan->format == MW_FMT_CSR: CSR kernel on M;
 // else the SELL-64 kernel.  mode 1 (CG): x is p, y is q, the workgroup
-// partials of p^T q go to `slots` (their count to *nslots) and the launch
-// is skipped on the device once st->active is 0.
+// partials of p^T q go to `slots` (their count to *nslots); the launch does
+// nothing but pass the stop on (*run_cur = 0) when *run_prev is 0.
 template <int A>
 int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, double *y, double *slots,
-                const mwk::CgState *st, int mode, hipStream_t s, int *nslots = nullptr);
+                const int32_t *run_prev, int32_t *run_cur, int mode, hipStream_t s, int *nslots = nullptr);
+
+// Number of slots a CG-mode SpMV launch writes (see spmv_launch).
+int spmv_slots(const mw_csr_t *M, const mw_spmv_plan_t *plan);
 
 }  // namespace mwh

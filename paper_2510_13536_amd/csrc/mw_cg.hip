@@ -4,30 +4,62 @@
 // FP64; x, vectors and scalars in the arithmetic; FP64 residual test) and
 // Sec. IV-D (QDW/QTW normalise r after its update, once per iteration).
 //
-// One iteration is five kernels on one stream; kernel boundaries are the
+// One iteration is three kernels on one stream; kernel boundaries are the
 // only grid-wide synchronisation (cheaper on this GPU than a software grid
 // barrier or a fence-and-counter "last workgroup" reduction):
 //   1. q = A p and the workgroup partials of p^T q   (SpMV, SELL-64 plan)
-//   2. alpha = rho / p^T q, breakdown test           (one workgroup)
-//   3. r = r - alpha q, normalise r (quasi types), partials of r^T r
-//   4. rho' = r^T r, FP64 residual test, beta         (one workgroup)
-//   5. x = x + alpha p, p = r + beta p
-// The x update of iteration i runs in kernel 5 with the p that kernel 1
-// read (x is not read by anything else), which saves a pass over p; when
-// the solve stops in kernel 4, the stopping iteration's x update is applied
-// by one closing kernel.  Every kernel first reads the device flag and
-// exits at once after the stop, so a chunk of iterations can be enqueued
-// (or replayed from a captured hipGraph) and the host checks the flag once
-// per chunk.  Partial sums use fixed slots and a fixed order: the solve is
-// run-to-run reproducible.
+//   2. every workgroup reduces those partials to the same sigma and
+//      alpha = rho / sigma (breakdown test); r = r - alpha q; quasi types
+//      normalise r; partials of r^T r
+//   3. every workgroup reduces those to the same rho', counts the iteration,
+//      runs the FP64 residual test and forms beta; x = x + alpha p and,
+//      unless the solve stops here, p = r + beta p
+// The x update rides in step 3 with the p that step 1 read, which saves a
+// pass over p.  Scalars and flags an iteration produces are stored per
+// iteration parity, so no workgroup reads what another workgroup of the
+// same kernel writes; the parity of each launch is a kernel argument.
+// After the stop every kernel only passes the stop flag on and exits, so a
+// chunk of iterations is enqueued (or replayed from a captured hipGraph)
+// and the host checks the flag once per chunk.  All reductions use fixed
+// slots and a fixed order: the solve is run-to-run reproducible.
 #include "mw_blas.hpp"
 
+#include <cstdlib>
 #include <cstring>
 
 using namespace mwk;
 using namespace mwh;
 
 namespace {
+
+// Launch shape of the two vector-update kernels: UNT threads per
+// workgroup (a template argument: 256, 512 or 1024) and at most `ugrid`
+// workgroups.  Each workgroup reduces all partials of the kernel before it.
+constexpr int UGRID_MAX = 2048;
+
+struct UpdateShape {
+    int unt, ugrid;
+};
+
+// Default shape: 256 threads, at most 1024 workgroups (best of the swept
+// 256/512/1024-thread, 256..2048-workgroup shapes for all five arithmetics
+// on MI355X, 3D Poisson 128^3), overridable with MW_UNT / MW_UGRID.
+UpdateShape update_shape(int a)
+{
+    UpdateShape u{256, 1024};
+    (void)a;
+    if (const char *e = getenv("MW_UNT")) u.unt = atoi(e);
+    if (const char *e = getenv("MW_UGRID")) u.ugrid = atoi(e);
+    if (u.unt != 256 && u.unt != 512 && u.unt != 1024) u.unt = 256;
+    if (u.ugrid < 8 || u.ugrid > UGRID_MAX) u.ugrid = 1024;
+    return u;
+}
+
+inline int update_grid(int n, const UpdateShape &u)
+{
+    const int t = blocks_for(n, u.unt);
+    return t < u.ugrid ? t : u.ugrid;
+}
 
 // r = b - q (q = A x0), p = r, partials of r^T r and b^T b.
 template <int A>
@@ -59,6 +91,7 @@ __global__ void __launch_bounds__(NT) mw_cg_init_kernel(int n, const double *__r
     }
 }
 
+// rho0, ||b|| and the initial flags (parity 0).
 template <int A>
 __global__ void __launch_bounds__(FIN_NT) mw_cg_init_final_kernel(int nslots, const double *__restrict__ slots_rr,
                                                                   const double *__restrict__ slots_bb,
@@ -67,130 +100,139 @@ __global__ void __launch_bounds__(FIN_NT) mw_cg_init_final_kernel(int nslots, co
     const Num<A> rho = reduce_slots<A>(nslots, slots_rr);
     const Num<A> bb = reduce_slots<A>(nslots, slots_bb);
     if (threadIdx.x == 0) {
-        store_scalar<A>(st->rho, rho);
+        store_scalar<A>(st->rho[0], rho);
         st->nb = sqrt(to_fp64<A>(bb));
-        st->iters = 0;
+        st->iters[0] = 0;
+        st->iters_final = 0;
         st->status = MW_OK;
-        st->x_due = 0;
         const double r64 = to_fp64<A>(rho);
+        int run = 1;
         if (r64 == 0.0) {
             st->rel_res = 0.0;
-            st->active = 0;
+            run = 0;
         } else {
             st->rel_res = sqrt(r64) / st->nb;
             if (st->maxit == 0) {
                 st->status = MW_NOT_CONVERGED;
-                st->active = 0;
+                run = 0;
+            }
+        }
+        st->run[0] = run;
+        st->stopped = !run;
+    }
+}
+
+// Iteration step 2 (parity par): every workgroup reduces the p^T q partials
+// in the same fixed order, so all derive the same sigma and
+// alpha = rho / sigma; breakdown (sigma <= 0 or a non-finite value) stops
+// the solve before any vector changes.  Then r = r - alpha q, quasi types
+// normalise r, and the workgroup partial of r^T r goes to slots_out.
+template <int A, int UNT>
+__global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in, const double *__restrict__ slots_in,
+                                                           const double *__restrict__ q, double *__restrict__ r,
+                                                           double *__restrict__ slots_out, CgState *__restrict__ st,
+                                                           int par)
+{
+    constexpr int K = words(A);
+    __shared__ Num<A> s_alpha;
+    __shared__ int s_brk;
+    if (!st->run[par ^ 1]) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->run[par] = 0;
+        return;
+    }
+    const Num<A> sigma = reduce_slots<A, UNT>(nslots_in, slots_in);
+    if (threadIdx.x == 0) {
+        const double s64 = to_fp64<A>(sigma);
+        int brk = !(s64 > 0.0) || !isfinite(s64);
+        Num<A> al = zero<A>();
+        if (!brk) {
+            al = div<A>(load_scalar<A>(st->rho[par ^ 1]), sigma);
+            brk = !isfinite(to_fp64<A>(al));
+        }
+        s_alpha = al;
+        s_brk = brk;
+        if (blockIdx.x == 0) {
+            st->brk[par] = brk;
+            if (brk) {
+                st->run[par] = 0;
+                st->status = MW_BREAKDOWN;
+                st->iters_final = st->iters[par ^ 1];
+                st->stopped = 1;
             } else {
-                st->active = 1;
+                store_scalar<A>(st->alpha[par], al);
             }
         }
     }
-}
-
-// alpha = rho / sigma with the breakdown tests on sigma and alpha.
-template <int A>
-__global__ void __launch_bounds__(FIN_NT) mw_cg_final_alpha_kernel(int nslots, const double *__restrict__ slots,
-                                                                   CgState *__restrict__ st)
-{
-    if (!st->active) return;
-    const Num<A> sigma = reduce_slots<A>(nslots, slots);
-    if (threadIdx.x == 0) {
-        const double s64 = to_fp64<A>(sigma);
-        if (!(s64 > 0.0) || !isfinite(s64)) {
-            st->status = MW_BREAKDOWN;
-            st->active = 0;
-            return;
-        }
-        const Num<A> al = div<A>(load_scalar<A>(st->rho), sigma);
-        if (!isfinite(to_fp64<A>(al))) {
-            st->status = MW_BREAKDOWN;
-            st->active = 0;
-            return;
-        }
-        store_scalar<A>(st->alpha, al);
-    }
-}
-
-// r = r - alpha q; quasi: r = normalise(r); partials of r^T r.
-template <int A>
-__global__ void __launch_bounds__(NT) mw_cg_update_r_kernel(int n, const double *__restrict__ q, double *__restrict__ r,
-                                                            double *__restrict__ slots, const CgState *__restrict__ st)
-{
-    constexpr int K = words(A);
-    if (!st->active) return;
-    const TileRange tr = xcd_tiles((n + NT - 1) / NT);
-    const Num<A> al = load_scalar<A>(st->alpha);
+    __syncthreads();
+    if (s_brk) return;
+    const Num<A> al = s_alpha;
     const bool norm = is_quasi(A) && st->normalize;
+    const TileRange tr = xcd_tiles((n + UNT - 1) / UNT);
     Num<A> rr = zero<A>();
     for (int t = tr.first; t < tr.end; t += tr.step) {
-        const long i = (long)t * NT + threadIdx.x;
+        const long i = (long)t * UNT + threadIdx.x;
         if (i >= n) continue;
         Num<A> ri = axmy_term<A>(al, load<A>(q, n, i), load<A>(r, n, i));
         if (norm) ri = normalise<A>(ri);
         store<A>(r, n, i, ri);
         rr = dot_step<A>(rr, ri, ri);
     }
-    const Num<A> s = block_sum<A, NT>(rr);
-    if (threadIdx.x == 0) store_scalar<A>(slots + (long)blockIdx.x * K, s);
+    const Num<A> sum = block_sum<A, UNT>(rr);
+    if (threadIdx.x == 0) store_scalar<A>(slots_out + (long)blockIdx.x * K, sum);
 }
 
-// rho' = sum of partials; iteration count; FP64 test; beta.
-template <int A>
-__global__ void __launch_bounds__(FIN_NT) mw_cg_final_beta_kernel(int nslots, const double *__restrict__ slots,
-                                                                  CgState *__restrict__ st)
+// Iteration step 3 (parity par): every workgroup reduces the r^T r
+// partials to the same rho', counts the iteration, runs the FP64 residual
+// test and derives beta = rho' / rho.  Then x = x + alpha p, and, unless
+// the solve stops here, p = r + beta p (both with this iteration's p).
+template <int A, int UNT>
+__global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in, const double *__restrict__ slots_in,
+                                                           const double *__restrict__ r, double *__restrict__ p,
+                                                           double *__restrict__ x, CgState *__restrict__ st, int par)
 {
-    if (!st->active) return;
-    const Num<A> rho_new = reduce_slots<A>(nslots, slots);
-    if (threadIdx.x == 0) {
-        const int it = st->iters + 1;
-        st->iters = it;
-        const double rr = to_fp64<A>(rho_new);
-        if (!isfinite(rr)) {
-            st->status = MW_BREAKDOWN;
-            st->active = 0;
-            st->x_due = 1;
-            return;
-        }
-        const double rel = sqrt(rr) / st->nb;
-        st->rel_res = rel;
-        if (st->history) st->history[it - 1] = rel;
-        if (rel < st->tol || it >= st->maxit) {
-            st->status = (rel < st->tol) ? MW_OK : MW_NOT_CONVERGED;
-            st->active = 0;
-            st->x_due = 1;
-            return;
-        }
-        store_scalar<A>(st->beta, div<A>(rho_new, load_scalar<A>(st->rho)));
-        store_scalar<A>(st->rho, rho_new);
+    __shared__ Num<A> s_beta;
+    __shared__ int s_stop;
+    if (!st->run[par ^ 1] || st->brk[par]) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->run[par] = 0;
+        return;
     }
-}
-
-// x = x + alpha p;  p = r + beta p  (both with the p of this iteration).
-template <int A>
-__global__ void __launch_bounds__(NT) mw_cg_update_p_kernel(int n, const double *__restrict__ r, double *__restrict__ p,
-                                                            double *__restrict__ x, const CgState *__restrict__ st)
-{
-    if (!st->active) return;
-    const long i = (long)xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
-    if (i >= n) return;
-    const Num<A> al = load_scalar<A>(st->alpha);
-    const Num<A> be = load_scalar<A>(st->beta);
-    const Num<A> pi = load<A>(p, n, i);
-    store<A>(x, n, i, axpy_term<A>(al, pi, load<A>(x, n, i)));
-    store<A>(p, n, i, axpy_term<A>(be, pi, load<A>(r, n, i)));
-}
-
-// The stopping iteration's x = x + alpha p.
-template <int A>
-__global__ void __launch_bounds__(NT) mw_cg_final_x_kernel(int n, const double *__restrict__ p, double *__restrict__ x,
-                                                           const CgState *__restrict__ st)
-{
-    if (!st->x_due) return;
-    const long i = (long)xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
-    if (i >= n) return;
-    const Num<A> al = load_scalar<A>(st->alpha);
-    store<A>(x, n, i, axpy_term<A>(al, load<A>(p, n, i), load<A>(x, n, i)));
+    const Num<A> rho_new = reduce_slots<A, UNT>(nslots_in, slots_in);
+    if (threadIdx.x == 0) {
+        const int it = st->iters[par ^ 1] + 1;
+        const double rr = to_fp64<A>(rho_new);
+        const bool fin = isfinite(rr);
+        const double rel = fin ? sqrt(rr) / st->nb : rr;
+        const bool conv = fin && rel < st->tol;
+        const bool stop = !fin || conv || it >= st->maxit;
+        Num<A> be = zero<A>();
+        if (!stop) be = div<A>(rho_new, load_scalar<A>(st->rho[par ^ 1]));
+        s_beta = be;
+        s_stop = stop;
+        if (blockIdx.x == 0) {
+            st->iters[par] = it;
+            store_scalar<A>(st->rho[par], rho_new);
+            st->rel_res = rel;
+            if (st->history) st->history[it - 1] = rel;
+            st->run[par] = !stop;
+            if (stop) {
+                st->status = !fin ? MW_BREAKDOWN : (conv ? MW_OK : MW_NOT_CONVERGED);
+                st->iters_final = it;
+                st->stopped = 1;
+            }
+        }
+    }
+    __syncthreads();
+    const bool stop = s_stop;
+    const Num<A> be = s_beta;
+    const Num<A> al = load_scalar<A>(st->alpha[par]);
+    const TileRange tr = xcd_tiles((n + UNT - 1) / UNT);
+    for (int t = tr.first; t < tr.end; t += tr.step) {
+        const long i = (long)t * UNT + threadIdx.x;
+        if (i >= n) continue;
+        const Num<A> pi = load<A>(p, n, i);
+        store<A>(x, n, i, axpy_term<A>(al, pi, load<A>(x, n, i)));
+        if (!stop) store<A>(p, n, i, axpy_term<A>(be, pi, load<A>(r, n, i)));
+    }
 }
 
 // ------------------------------------------------------------ host side
@@ -203,7 +245,8 @@ CgLayout cg_layout(int a, int32_t n, int32_t nnz)
 {
     const size_t K = (size_t)words(a);
     const size_t plane = align256(sizeof(double) * (size_t)n * K);
-    const size_t slots = align256(sizeof(double) * (size_t)spmv_max_slots(n) * K);
+    const size_t nsl = (size_t)(spmv_max_slots(n) > UGRID_MAX ? spmv_max_slots(n) : UGRID_MAX);
+    const size_t slots = align256(sizeof(double) * nsl * K);
     CgLayout L;
     L.r = 0;
     L.p = L.r + plane;
@@ -216,10 +259,15 @@ CgLayout cg_layout(int a, int32_t n, int32_t nnz)
     return L;
 }
 
-int *pinned_flags()
+// Host copy of the integer part of CgState (from `run` on).
+struct Flags {
+    int32_t run[2], iters[2], brk[2], maxit, normalize, stopped, status, iters_final, pad;
+};
+
+Flags *pinned_flags()
 {
-    thread_local int *buf = nullptr;
-    if (!buf && hipHostMalloc((void **)&buf, 64, hipHostMallocDefault) != hipSuccess) buf = nullptr;
+    thread_local Flags *buf = nullptr;
+    if (!buf && hipHostMalloc((void **)&buf, sizeof(Flags), hipHostMallocDefault) != hipSuccess) buf = nullptr;
     return buf;
 }
 
@@ -249,62 +297,64 @@ struct EventPool {
         e = nullptr;
         n = 0;
     }
-    ~EventPool() { release(); }
 };
 
-constexpr int NKERN = 5;  // kernels per iteration
-constexpr int KCLASS[NKERN] = {MW_PROF_SPMV, MW_PROF_FINAL, MW_PROF_UPDATE_R, MW_PROF_FINAL, MW_PROF_UPDATE_P};
+constexpr int NKERN = 3;  // kernels per iteration
+constexpr int KCLASS[NKERN] = {MW_PROF_SPMV, MW_PROF_UPDATE_R, MW_PROF_UPDATE_P};
 
 // Everything one chunk of iterations needs.
 struct ChunkArgs {
-    int arith, n, nslots_sp, nslots_up, chunk, timed_mask;
+    int arith, n, nslots_sp, nslots_up, chunk, timed_mask, unt, ugrid;
     const mw_csr_t *M;
     const mw_spmv_plan_t *plan;
-    double *r, *p, *q, *x, *slots;
+    double *r, *p, *q, *x, *slots_a, *slots_b;
     CgState *st;
 };
 
 bool same_key(const ChunkArgs &a, const ChunkArgs &b)
 {
     return a.arith == b.arith && a.n == b.n && a.nslots_sp == b.nslots_sp && a.nslots_up == b.nslots_up &&
-           a.chunk == b.chunk && a.timed_mask == b.timed_mask && a.r == b.r && a.p == b.p && a.q == b.q &&
-           a.x == b.x && a.slots == b.slots && a.st == b.st && a.plan && b.plan &&
-           a.plan->format == b.plan->format && a.plan->slice_ptr == b.plan->slice_ptr &&
-           a.plan->col == b.plan->col && a.plan->val == b.plan->val && a.M->row_ptr == b.M->row_ptr &&
-           a.M->col_idx == b.M->col_idx && a.M->val == b.M->val && a.M->n == b.M->n;
+           a.chunk == b.chunk && a.timed_mask == b.timed_mask && a.unt == b.unt && a.ugrid == b.ugrid && a.r == b.r && a.p == b.p && a.q == b.q &&
+           a.x == b.x && a.slots_a == b.slots_a && a.slots_b == b.slots_b && a.st == b.st && a.plan && b.plan &&
+           a.plan->format == b.plan->format && a.plan->nslices == b.plan->nslices &&
+           a.plan->slice_ptr == b.plan->slice_ptr && a.plan->col == b.plan->col && a.plan->val == b.plan->val &&
+           a.M->row_ptr == b.M->row_ptr && a.M->col_idx == b.M->col_idx && a.M->val == b.M->val &&
+           a.M->n == b.M->n;
 }
 
-// Enqueues one chunk; with a mask, records events around the timed classes.
+// Enqueues one chunk (even length; iteration j of the chunk has parity
+// (j + 1) & 1, since chunks start after an even number of iterations).
+// With a mask, records events around the timed classes.
+template <int A, int UNT>
+void launch_steps(const ChunkArgs &c, int k, int par, hipStream_t s)
+{
+    const int gu = c.nslots_up;
+    if (k == 1)
+        hipLaunchKernelGGL((mw_cg_step_r_kernel<A, UNT>), dim3(gu), dim3(UNT), 0, s, c.n, c.nslots_sp, c.slots_a, c.q,
+                           c.r, c.slots_b, c.st, par);
+    else
+        hipLaunchKernelGGL((mw_cg_step_p_kernel<A, UNT>), dim3(gu), dim3(UNT), 0, s, c.n, c.nslots_up, c.slots_b, c.r,
+                           c.p, c.x, c.st, par);
+}
+
 template <int A>
 int enqueue_chunk(const ChunkArgs &c, EventPool *ev, hipStream_t s)
 {
-    const int nbp = blocks_for(c.n, NT);
-    const int gup = persistent_grid(blocks_for(c.n, NT));
     for (int it = 0; it < c.chunk; ++it) {
+        const int par = (it + 1) & 1;
         for (int k = 0; k < NKERN; ++k) {
             const bool timed = ev && (c.timed_mask & (1 << KCLASS[k]));
             if (timed) HIP_TRY(hipEventRecord(ev->e[(it * NKERN + k) * 2], s));
-            switch (k) {
-            case 0: {
-                const int rc = spmv_launch<A>(c.M, c.plan, c.p, c.q, c.slots, c.st, 1, s);
+            if (k == 0) {
+                const int rc = spmv_launch<A>(c.M, c.plan, c.p, c.q, c.slots_a, &c.st->run[par ^ 1], &c.st->run[par],
+                                              1, s);
                 if (rc) return rc;
-                break;
-            }
-            case 1:
-                hipLaunchKernelGGL((mw_cg_final_alpha_kernel<A>), dim3(1), dim3(FIN_NT), 0, s, c.nslots_sp, c.slots,
-                                   c.st);
-                break;
-            case 2:
-                hipLaunchKernelGGL((mw_cg_update_r_kernel<A>), dim3(gup), dim3(NT), 0, s, c.n, c.q, c.r, c.slots,
-                                   c.st);
-                break;
-            case 3:
-                hipLaunchKernelGGL((mw_cg_final_beta_kernel<A>), dim3(1), dim3(FIN_NT), 0, s, c.nslots_up, c.slots,
-                                   c.st);
-                break;
-            default:
-                hipLaunchKernelGGL((mw_cg_update_p_kernel<A>), dim3(nbp), dim3(NT), 0, s, c.n, c.r, c.p, c.x, c.st);
-                break;
+            } else if (c.unt == 1024) {
+                launch_steps<A, 1024>(c, k, par, s);
+            } else if (c.unt == 512) {
+                launch_steps<A, 512>(c, k, par, s);
+            } else {
+                launch_steps<A, 256>(c, k, par, s);
             }
             if (timed) HIP_TRY(hipEventRecord(ev->e[(it * NKERN + k) * 2 + 1], s));
         }
@@ -321,14 +371,12 @@ struct GraphCache {
     mw_spmv_plan_t plan{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    EventPool ev;
     void release()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
-        ev.release();
         valid = false;
     }
 };
@@ -354,16 +402,18 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     double *sa = (double *)(base + L.slots_a);
     double *sb = (double *)(base + L.slots_b);
     CgState *st = (CgState *)(base + L.state);
-    const int chunk = (opts && opts->chunk > 0) ? opts->chunk : 32;
+    int chunk = (opts && opts->chunk > 0) ? opts->chunk : 32;
+    chunk += chunk & 1;  // even: the parity pattern repeats per chunk
     mw_cg_prof_t *prof = opts ? opts->prof : nullptr;
     const int mask = prof ? (prof->mask ? prof->mask : 0xF) : 0;
     // events recorded by graph nodes cannot be read back: timing uses direct launches
     const bool use_graph = !(opts && opts->no_graph) && !prof;
 
     hipStream_t s = own_stream();
-    int *flags = pinned_flags();
-    if (!s || !flags) return hip_fail(hipErrorOutOfMemory, "stream/pinned buffer");
+    Flags *fl = pinned_flags();
+    if (!s || !fl) return hip_fail(hipErrorOutOfMemory, "stream/pinned buffer");
 
+    EventPool ev;
     hipEvent_t e_in, e0, e1;
     HIP_TRY(hipEventCreateWithFlags(&e_in, hipEventDisableTiming));
     HIP_TRY(hipEventCreate(&e0));
@@ -390,13 +440,13 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     HIP_TRY(hipMemcpyAsync(st, &h, sizeof(CgState), hipMemcpyHostToDevice, s));
 
     // r0 = b - A x0, p0 = r0, rho0, ||b||
-    int rc = spmv_launch<A>(M, plan, x, q, nullptr, nullptr, 0, s);
+    int rc = spmv_launch<A>(M, plan, x, q, nullptr, nullptr, nullptr, 0, s);
     if (rc) return rc;
     const int gi = persistent_grid(blocks_for(n, NT));
     hipLaunchKernelGGL((mw_cg_init_kernel<A>), dim3(gi), dim3(NT), 0, s, n, b, q, r, p, sa, sb);
     hipLaunchKernelGGL((mw_cg_init_final_kernel<A>), dim3(1), dim3(FIN_NT), 0, s, gi, sa, sb, st);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(flags, &st->active, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(fl, &st->run[0], sizeof(Flags), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
 
     ChunkArgs c{};
@@ -410,22 +460,22 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     c.p = p;
     c.q = q;
     c.x = x;
-    c.slots = sa;
+    c.slots_a = sa;
+    c.slots_b = sb;
     c.st = st;
-    c.nslots_up = persistent_grid(blocks_for(n, NT));
-    c.nslots_sp = (plan->format == MW_FMT_SELL64) ? persistent_grid(blocks_for(plan->nslices, NWAVE))
-                                                  : blocks_for(n, NT);
+    const UpdateShape us = update_shape(A);
+    c.unt = us.unt;
+    c.ugrid = us.ugrid;
+    c.nslots_sp = spmv_slots(M, plan);
+    c.nslots_up = update_grid(n, us);
 
-    EventPool local_ev;
-    EventPool *ev = nullptr;
-    if (flags[0]) {
+    if (!fl->stopped) {
         if (use_graph) {
             GraphCache &G = graph_cache();
             if (!(G.valid && same_key(G.key, c))) {
                 G.release();
-                if (mask && (rc = G.ev.init(2 * NKERN * chunk))) return rc;
                 HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                rc = enqueue_chunk<A>(c, mask ? &G.ev : nullptr, s);
+                rc = enqueue_chunk<A>(c, nullptr, s);
                 hipGraph_t g = nullptr;
                 const hipError_t ce = hipStreamEndCapture(s, &g);
                 if (rc) return rc;
@@ -439,40 +489,37 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
                 G.key.plan = &G.plan;
                 G.valid = true;
             }
-            ev = mask ? &G.ev : nullptr;
         } else if (mask) {
-            if ((rc = local_ev.init(2 * NKERN * chunk))) return rc;
-            ev = &local_ev;
+            if ((rc = ev.init(2 * NKERN * chunk))) return rc;
         }
     }
 
     int iters_before = 0;
-    while (flags[0]) {
+    while (!fl->stopped) {
         if (use_graph) {
             HIP_TRY(hipGraphLaunch(graph_cache().exec, s));
         } else {
-            rc = enqueue_chunk<A>(c, ev, s);
+            rc = enqueue_chunk<A>(c, mask ? &ev : nullptr, s);
             if (rc) return rc;
         }
-        HIP_TRY(hipMemcpyAsync(flags, &st->active, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(fl, &st->run[0], sizeof(Flags), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (ev) {
+        const int now = fl->stopped ? fl->iters_final : (fl->iters[0] > fl->iters[1] ? fl->iters[0] : fl->iters[1]);
+        if (mask) {
             // iterations of this chunk that ran to completion (the one that
-            // stopped the solve is left out: part of its launches exited)
-            const int done = flags[2] - iters_before - (flags[0] ? 0 : 1);
+            // stopped the solve is left out: part of its work was skipped)
+            const int done = now - iters_before - (fl->stopped ? 1 : 0);
             for (int it = 0; it < done && it < chunk; ++it)
                 for (int k = 0; k < NKERN; ++k) {
                     if (!(mask & (1 << KCLASS[k]))) continue;
                     float ms = 0.f;
-                    HIP_TRY(hipEventElapsedTime(&ms, ev->e[(it * NKERN + k) * 2], ev->e[(it * NKERN + k) * 2 + 1]));
+                    HIP_TRY(hipEventElapsedTime(&ms, ev.e[(it * NKERN + k) * 2], ev.e[(it * NKERN + k) * 2 + 1]));
                     prof->ms[KCLASS[k]] += ms;
                     prof->launches[KCLASS[k]] += 1;
                 }
         }
-        iters_before = flags[2];
+        iters_before = now;
     }
-    hipLaunchKernelGGL((mw_cg_final_x_kernel<A>), dim3(blocks_for(n, NT)), dim3(NT), 0, s, n, p, x, st);
-    HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(&h, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(e1, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -482,7 +529,7 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (info) {
-        info->iters = h.iters;
+        info->iters = h.iters_final;
         info->status = h.status;
         info->rel_res = h.rel_res;
         info->seconds = ms * 1e-3;

@@ -85,24 +85,24 @@ __device__ __forceinline__ Num<A> block_sum(Num<A> v)
 // Sum of nslots k-word partials (slot s at slots + s*K) by one FIN_NT
 // workgroup: thread t adds slots t, t + FIN_NT, ... in order (loads issued
 // ahead of the dependent adds), then block_sum.
-template <int A>
+template <int A, int NTHR = FIN_NT>
 __device__ __forceinline__ Num<A> reduce_slots(int nslots, const double *__restrict__ slots)
 {
     constexpr int K = words(A);
     constexpr int B = 4;
     Num<A> acc = zero<A>();
-    for (int s0 = threadIdx.x; s0 < nslots; s0 += FIN_NT * B) {
+    for (int s0 = threadIdx.x; s0 < nslots; s0 += NTHR * B) {
         Num<A> v[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            const int s = s0 + u * FIN_NT;
+            const int s = s0 + u * NTHR;
             v[u] = (s < nslots) ? load_scalar<A>(slots + (long)s * K) : zero<A>();
         }
 #pragma unroll
         for (int u = 0; u < B; ++u)
-            if (s0 + u * FIN_NT < nslots) acc = add<A>(acc, v[u]);
+            if (s0 + u * NTHR < nslots) acc = add<A>(acc, v[u]);
     }
-    return block_sum<A, FIN_NT>(acc);
+    return block_sum<A, NTHR>(acc);
 }
 
 // acc + x*y as a dot-product step (FP64: one fma).
