@@ -269,6 +269,37 @@ int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, dou
                 int32_t maxit, const mw_cg_opts_t *opts, void *workspace, mw_cg_info_t *info,
                 void *stream);
 
+/* Bytes of device workspace mw_cg_solve_batched needs for nsys systems of
+ * n rows and nnz entries in total (256-byte aligned). */
+size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int32_t nnz);
+
+/*
+ * Solves nsys independent SPD systems together: the CG of mw_cg_solve
+ * (Alg. 1, Sec. IV-C/IV-D) runs for every system with its own scalars,
+ * iteration count, FP64 stopping test and status.  A is the block-diagonal
+ * matrix of the systems (each row's columns inside its own system's
+ * rows); system s owns rows sys_row_off[s] .. sys_row_off[s+1]-1.
+ * sys_row_off: HOST array of nsys + 1 nondecreasing offsets, [0] = 0,
+ * [nsys] = A->n (empty systems are allowed and finish at once).  b: FP64[n];
+ * x: k planes of n, in/out; tol, maxit: as mw_cg_solve, for every system.
+ * iters, status: DEVICE int32[nsys] outputs (may be NULL); rel_res: DEVICE
+ * double[nsys] output, each system's last relative residual (may be NULL).
+ * info (host, may be NULL): iters = the largest count, status = the worst
+ * status (MW_OK < MW_NOT_CONVERGED < MW_BREAKDOWN), seconds.  opts: normalize,
+ * chunk (default 16) and no_graph are honoured.  All systems advance in
+ * lockstep, five kernels per iteration replayed from a captured hipGraph;
+ * a converged system's rows cost a flag test per 64-row slice afterwards.
+ * Each system gives the same results whatever the other systems are, but
+ * its dots are summed per 64-row slice, so they need not be bit-identical
+ * to a single-system mw_cg_solve.  Returns the worst status or a negative
+ * error (MW_EINVAL also when a slice's padding would exceed the workspace).
+ * Synchronises `stream`.
+ */
+int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, const mw_csr_t *A,
+                        const double *b, double *x, double tol, int32_t maxit, const mw_cg_opts_t *opts,
+                        void *workspace, int32_t *iters, int32_t *status, double *rel_res,
+                        mw_cg_info_t *info, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

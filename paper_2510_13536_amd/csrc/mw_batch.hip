@@ -1,0 +1,623 @@
+// mw_batch.hip -- many independent SPD systems solved together (gfx950).
+//
+// Each system runs exactly the CG of Alg. 1 (with Sec. IV-C/IV-D), in the
+// chosen arithmetic, with its own scalars, iteration count, stopping test
+// and status.  The systems are the diagonal blocks of one block-diagonal
+// CSR matrix; system s owns rows sys_row_off[s] .. sys_row_off[s+1]-1.
+//
+// Layout: a SELL-64 copy of the matrix whose slices never straddle two
+// systems (each system's rows start a new slice), so every wavefront works
+// for exactly one system.  Per-system reductions use one partial per slice
+// (a wavefront shuffle tree, no workgroup barrier), summed in slice order by
+// one workgroup per system.
+//
+// One lockstep iteration of the whole batch is five kernels, replayed from
+// a captured hipGraph in chunks:
+//   1. q = A p over the slices of running systems; p^T q per slice
+//   2. one workgroup per running system: sigma, alpha = rho / sigma
+//   3. r = r - alpha q, quasi normalisation, r^T r per slice
+//   4. one workgroup per running system: rho', FP64 test, beta; a system
+//      that stops here is masked out from now on
+//   5. x = x + alpha p and p = r + beta p (x only for a system that
+//      stopped in step 4 of this iteration)
+// Converged systems cost only a flag test per slice.  The host polls the
+// number of running systems once per chunk.  All orders are fixed, so the
+// batch is run-to-run reproducible.
+#include "mw_blas.hpp"
+
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+using namespace mwk;
+using namespace mwh;
+
+namespace {
+
+// Device view of the batch bookkeeping (passed by value).
+struct BatchDev {
+    const int32_t *sys_slice_off;  // nsys + 1
+    const int32_t *slice_sys;      // ns
+    const int32_t *slice_row0;     // ns
+    const int32_t *slice_rows;     // ns (1..64)
+    const int32_t *sp;             // SELL slice offsets, ns + 1
+    const int32_t *sc;             // SELL columns (-1 = padding)
+    const double *sv;              // SELL values
+    double *rho, *alpha, *beta;    // nsys * K each
+    double *nb, *rel;              // nsys each
+    int32_t *active, *xdue, *iters, *status;  // nsys each
+    int32_t *n_active;             // running systems
+    const double *tol;             // solve parameters in device memory
+    const int32_t *maxit, *normalize;
+    int nsys, ns, n;
+};
+
+constexpr int BNT = NT;  // workgroup of the slice kernels: NWAVE slices
+
+__device__ __forceinline__ TileRange slice_tiles(int ns) { return xcd_tiles((ns + NWAVE - 1) / NWAVE); }
+
+// ------------------------------------------------------------ plan build
+
+__global__ void __launch_bounds__(BNT) mw_batch_width_kernel(BatchDev d, const int32_t *__restrict__ row_ptr,
+                                                             int32_t *__restrict__ width)
+{
+    const int s = blockIdx.x * NWAVE + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (s >= d.ns) return;
+    int len = 0;
+    if (lane < d.slice_rows[s]) {
+        const int row = d.slice_row0[s] + lane;
+        len = row_ptr[row + 1] - row_ptr[row];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+    if (lane == 0) width[s] = len;
+}
+
+__global__ void __launch_bounds__(BNT) mw_batch_fill_kernel(BatchDev d, const int32_t *__restrict__ row_ptr,
+                                                            const int32_t *__restrict__ col,
+                                                            const double *__restrict__ val,
+                                                            const int32_t *__restrict__ slice_ptr,
+                                                            int32_t *__restrict__ scol, double *__restrict__ sval)
+{
+    const int s = blockIdx.x * NWAVE + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (s >= d.ns) return;
+    const int b = slice_ptr[s];
+    const int w = (slice_ptr[s + 1] - b) / 64;
+    int rs = 0, len = 0;
+    if (lane < d.slice_rows[s]) {
+        const int row = d.slice_row0[s] + lane;
+        rs = row_ptr[row];
+        len = row_ptr[row + 1] - rs;
+    }
+    for (int j = 0; j < w; ++j) {
+        const int pos = b + 64 * j + lane;
+        if (j < len) {
+            sval[pos] = val[rs + j];
+            scol[pos] = col[rs + j];
+        } else {
+            sval[pos] = 0.0;
+            scol[pos] = -1;
+        }
+    }
+}
+
+// ------------------------------------------------------------- kernels
+
+// y = A x over the slices; MODE 1 (CG) skips stopped systems and leaves
+// the slice partial of p^T q in slots[s].
+template <int A, int MODE>
+__global__ void __launch_bounds__(BNT) mw_batch_spmv_kernel(BatchDev d, const double *__restrict__ x,
+                                                            double *__restrict__ y, double *__restrict__ slots)
+{
+    constexpr int K = words(A);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const TileRange tr = slice_tiles(d.ns);
+    for (int t = tr.first; t < tr.end; t += tr.step) {
+        const int s = t * NWAVE + wave;
+        if (s >= d.ns) continue;
+        if constexpr (MODE == 1) {
+            if (!d.active[d.slice_sys[s]]) continue;
+        }
+        const Num<A> acc = sell_row_sum<A>(d.sp[s] + lane, d.sp[s + 1], d.sc, d.sv, x, d.n);
+        const bool valid = lane < d.slice_rows[s];
+        const long row = (long)d.slice_row0[s] + lane;
+        if (valid) store<A>(y, d.n, row, acc);
+        if constexpr (MODE == 1) {
+            Num<A> c = zero<A>();
+            if (valid) c = dot_step<A>(c, load<A>(x, d.n, row), acc);
+            c = wave_sum<A>(c);
+            if (lane == 0) store_scalar<A>(slots + (long)s * K, c);
+        }
+    }
+}
+
+// r = b - q, p = r, slice partials of r^T r and b^T b.
+template <int A>
+__global__ void __launch_bounds__(BNT) mw_batch_init_kernel(BatchDev d, const double *__restrict__ b,
+                                                            const double *__restrict__ q, double *__restrict__ r,
+                                                            double *__restrict__ p, double *__restrict__ slots_rr,
+                                                            double *__restrict__ slots_bb)
+{
+    constexpr int K = words(A);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const TileRange tr = slice_tiles(d.ns);
+    for (int t = tr.first; t < tr.end; t += tr.step) {
+        const int s = t * NWAVE + wave;
+        if (s >= d.ns) continue;
+        Num<A> rr = zero<A>(), bb = zero<A>();
+        if (lane < d.slice_rows[s]) {
+            const long i = (long)d.slice_row0[s] + lane;
+            const Num<A> bi = promote<A>(b[i]);
+            Num<A> ri;
+            if constexpr (A == FP64) ri = promote<A>(bi.w[0] - q[i]);
+            else ri = add<A>(bi, neg<A>(load<A>(q, d.n, i)));
+            store<A>(r, d.n, i, ri);
+            store<A>(p, d.n, i, ri);
+            rr = dot_step<A>(rr, ri, ri);
+            bb = dot_step<A>(bb, bi, bi);
+        }
+        rr = wave_sum<A>(rr);
+        bb = wave_sum<A>(bb);
+        if (lane == 0) {
+            store_scalar<A>(slots_rr + (long)s * K, rr);
+            store_scalar<A>(slots_bb + (long)s * K, bb);
+        }
+    }
+}
+
+// Sum of a system's slice partials, slice order, by one workgroup.
+template <int A>
+__device__ __forceinline__ Num<A> system_sum(const BatchDev &d, int sys, const double *__restrict__ slots)
+{
+    constexpr int K = words(A);
+    const int s0 = d.sys_slice_off[sys], s1 = d.sys_slice_off[sys + 1];
+    return reduce_slots<A, BNT>(s1 - s0, slots + (long)s0 * K);
+}
+
+template <int A>
+__global__ void __launch_bounds__(BNT) mw_batch_init_final_kernel(BatchDev d, const double *__restrict__ slots_rr,
+                                                                  const double *__restrict__ slots_bb)
+{
+    constexpr int K = words(A);
+    const int sys = blockIdx.x;
+    const Num<A> rho = system_sum<A>(d, sys, slots_rr);
+    const Num<A> bb = system_sum<A>(d, sys, slots_bb);
+    if (threadIdx.x == 0) {
+        store_scalar<A>(d.rho + (long)sys * K, rho);
+        d.nb[sys] = sqrt(to_fp64<A>(bb));
+        d.iters[sys] = 0;
+        d.xdue[sys] = 0;
+        const double r64 = to_fp64<A>(rho);
+        int run = 1, status = MW_OK;
+        if (r64 == 0.0) {
+            d.rel[sys] = 0.0;
+            run = 0;
+        } else {
+            d.rel[sys] = sqrt(r64) / d.nb[sys];
+            if (*d.maxit == 0) {
+                status = MW_NOT_CONVERGED;
+                run = 0;
+            }
+        }
+        d.status[sys] = status;
+        d.active[sys] = run;
+        if (run) atomicAdd(d.n_active, 1);
+    }
+}
+
+// alpha per running system; a stopped system drops its pending x flag.
+template <int A>
+__global__ void __launch_bounds__(BNT) mw_batch_alpha_kernel(BatchDev d, const double *__restrict__ slots)
+{
+    constexpr int K = words(A);
+    const int sys = blockIdx.x;
+    if (!d.active[sys]) {
+        if (threadIdx.x == 0) d.xdue[sys] = 0;
+        return;
+    }
+    const Num<A> sigma = system_sum<A>(d, sys, slots);
+    if (threadIdx.x == 0) {
+        const double s64 = to_fp64<A>(sigma);
+        bool brk = !(s64 > 0.0) || !isfinite(s64);
+        Num<A> al = zero<A>();
+        if (!brk) {
+            al = div<A>(load_scalar<A>(d.rho + (long)sys * K), sigma);
+            brk = !isfinite(to_fp64<A>(al));
+        }
+        if (brk) {
+            d.status[sys] = MW_BREAKDOWN;
+            d.active[sys] = 0;
+            atomicSub(d.n_active, 1);
+        } else {
+            store_scalar<A>(d.alpha + (long)sys * K, al);
+        }
+    }
+}
+
+template <int A>
+__global__ void __launch_bounds__(BNT) mw_batch_step_r_kernel(BatchDev d, const double *__restrict__ q,
+                                                              double *__restrict__ r, double *__restrict__ slots)
+{
+    constexpr int K = words(A);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool norm = is_quasi(A) && *d.normalize;
+    const TileRange tr = slice_tiles(d.ns);
+    for (int t = tr.first; t < tr.end; t += tr.step) {
+        const int s = t * NWAVE + wave;
+        if (s >= d.ns) continue;
+        const int sys = d.slice_sys[s];
+        if (!d.active[sys]) continue;
+        const Num<A> al = load_scalar<A>(d.alpha + (long)sys * K);
+        Num<A> rr = zero<A>();
+        if (lane < d.slice_rows[s]) {
+            const long i = (long)d.slice_row0[s] + lane;
+            Num<A> ri = axmy_term<A>(al, load<A>(q, d.n, i), load<A>(r, d.n, i));
+            if (norm) ri = normalise<A>(ri);
+            store<A>(r, d.n, i, ri);
+            rr = dot_step<A>(rr, ri, ri);
+        }
+        rr = wave_sum<A>(rr);
+        if (lane == 0) store_scalar<A>(slots + (long)s * K, rr);
+    }
+}
+
+// rho', the FP64 test and beta per running system.
+template <int A>
+__global__ void __launch_bounds__(BNT) mw_batch_beta_kernel(BatchDev d, const double *__restrict__ slots)
+{
+    constexpr int K = words(A);
+    const int sys = blockIdx.x;
+    if (!d.active[sys]) return;
+    const Num<A> rho_new = system_sum<A>(d, sys, slots);
+    if (threadIdx.x == 0) {
+        const int it = d.iters[sys] + 1;
+        d.iters[sys] = it;
+        const double rr = to_fp64<A>(rho_new);
+        const bool fin = isfinite(rr);
+        const double rel = fin ? sqrt(rr) / d.nb[sys] : rr;
+        const bool conv = fin && rel < *d.tol;
+        if (fin) d.rel[sys] = rel;
+        if (!fin || conv || it >= *d.maxit) {
+            d.status[sys] = !fin ? MW_BREAKDOWN : (conv ? MW_OK : MW_NOT_CONVERGED);
+            d.active[sys] = 0;
+            d.xdue[sys] = 1;
+            atomicSub(d.n_active, 1);
+        } else {
+            store_scalar<A>(d.beta + (long)sys * K, div<A>(rho_new, load_scalar<A>(d.rho + (long)sys * K)));
+            store_scalar<A>(d.rho + (long)sys * K, rho_new);
+        }
+    }
+}
+
+template <int A>
+__global__ void __launch_bounds__(BNT) mw_batch_step_p_kernel(BatchDev d, const double *__restrict__ r,
+                                                              double *__restrict__ p, double *__restrict__ x)
+{
+    constexpr int K = words(A);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const TileRange tr = slice_tiles(d.ns);
+    for (int t = tr.first; t < tr.end; t += tr.step) {
+        const int s = t * NWAVE + wave;
+        if (s >= d.ns) continue;
+        const int sys = d.slice_sys[s];
+        const bool run = d.active[sys];
+        if (!run && !d.xdue[sys]) continue;
+        if (lane >= d.slice_rows[s]) continue;
+        const long i = (long)d.slice_row0[s] + lane;
+        const Num<A> al = load_scalar<A>(d.alpha + (long)sys * K);
+        const Num<A> pi = load<A>(p, d.n, i);
+        store<A>(x, d.n, i, axpy_term<A>(al, pi, load<A>(x, d.n, i)));
+        if (run) {
+            const Num<A> be = load_scalar<A>(d.beta + (long)sys * K);
+            store<A>(p, d.n, i, axpy_term<A>(be, pi, load<A>(r, d.n, i)));
+        }
+    }
+}
+
+// ------------------------------------------------------------ host side
+
+struct BatchLayout {
+    size_t r, p, q, slots_a, slots_b, sys_slice_off, slice_sys, slice_row0, slice_rows, dscal, iscal, params, width,
+        slice_ptr, total, col, val, bytes;
+    long long ns_max, cap;
+};
+
+BatchLayout batch_layout(int a, int32_t nsys, int32_t n, int32_t nnz)
+{
+    const size_t K = (size_t)words(a);
+    BatchLayout L;
+    L.ns_max = (long long)(n + 63) / 64 + nsys;
+    L.cap = (long long)nnz + (long long)nnz / 4 + 64 * L.ns_max;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    L.r = take(sizeof(double) * K * n);
+    L.p = take(sizeof(double) * K * n);
+    L.q = take(sizeof(double) * K * n);
+    L.slots_a = take(sizeof(double) * K * L.ns_max);
+    L.slots_b = take(sizeof(double) * K * L.ns_max);
+    L.sys_slice_off = take(sizeof(int32_t) * (nsys + 1));
+    L.slice_sys = take(sizeof(int32_t) * L.ns_max);
+    L.slice_row0 = take(sizeof(int32_t) * L.ns_max);
+    L.slice_rows = take(sizeof(int32_t) * L.ns_max);
+    L.dscal = take(sizeof(double) * (3 * K + 2) * nsys);
+    L.iscal = take(sizeof(int32_t) * (4 * nsys + 1));
+    L.params = take(64);
+    L.width = take(sizeof(int32_t) * L.ns_max);
+    L.slice_ptr = take(sizeof(int32_t) * (L.ns_max + 1));
+    L.total = take(sizeof(long long));
+    L.col = take(sizeof(int32_t) * L.cap);
+    L.val = take(sizeof(double) * L.cap);
+    L.bytes = o;
+    return L;
+}
+
+struct BatchParams {
+    double tol;
+    int32_t maxit, normalize;
+};
+
+hipStream_t batch_stream()
+{
+    thread_local hipStream_t s = nullptr;
+    if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    return s;
+}
+
+int32_t *pinned_count()
+{
+    thread_local int32_t *buf = nullptr;
+    if (!buf && hipHostMalloc((void **)&buf, 64, hipHostMallocDefault) != hipSuccess) buf = nullptr;
+    return buf;
+}
+
+struct BatchKey {
+    int arith, nsys, ns, n, chunk;
+    const void *ptrs[8];
+    bool operator==(const BatchKey &o) const
+    {
+        if (arith != o.arith || nsys != o.nsys || ns != o.ns || n != o.n || chunk != o.chunk) return false;
+        for (int i = 0; i < 8; ++i)
+            if (ptrs[i] != o.ptrs[i]) return false;
+        return true;
+    }
+};
+
+struct BatchGraph {
+    bool valid = false;
+    BatchKey key{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void release()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        valid = false;
+    }
+};
+
+// Heap-allocated and never freed (no HIP call during process teardown).
+BatchGraph &batch_graph()
+{
+    thread_local BatchGraph *g = new BatchGraph();
+    return *g;
+}
+
+template <int A>
+int enqueue_batch_chunk(const BatchDev &d, int chunk, double *r, double *p, double *q, double *x, double *sa,
+                        double *sb, hipStream_t s)
+{
+    const int g = persistent_grid(blocks_for(d.ns, NWAVE));
+    for (int it = 0; it < chunk; ++it) {
+        hipLaunchKernelGGL((mw_batch_spmv_kernel<A, 1>), dim3(g), dim3(BNT), 0, s, d, p, q, sa);
+        hipLaunchKernelGGL((mw_batch_alpha_kernel<A>), dim3(d.nsys), dim3(BNT), 0, s, d, sa);
+        hipLaunchKernelGGL((mw_batch_step_r_kernel<A>), dim3(g), dim3(BNT), 0, s, d, q, r, sb);
+        hipLaunchKernelGGL((mw_batch_beta_kernel<A>), dim3(d.nsys), dim3(BNT), 0, s, d, sb);
+        hipLaunchKernelGGL((mw_batch_step_p_kernel<A>), dim3(g), dim3(BNT), 0, s, d, r, p, x);
+    }
+    HIP_TRY(hipGetLastError());
+    return MW_OK;
+}
+
+template <int A>
+int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double *b, double *x, double tol,
+              int32_t maxit, const mw_cg_opts_t *opts, void *ws, int32_t *iters_out, int32_t *status_out,
+              double *rel_out, mw_cg_info_t *info, hipStream_t user)
+{
+    constexpr int K = words(A);
+    const int n = M->n;
+    const BatchLayout L = batch_layout(A, nsys, n, M->nnz);
+    char *base = (char *)ws;
+    int chunk = (opts && opts->chunk > 0) ? opts->chunk : 16;
+    const bool use_graph = !(opts && opts->no_graph);
+
+    // slices: each system starts a new 64-row slice
+    std::vector<int32_t> h_sso(nsys + 1), h_sys, h_row0, h_rows;
+    h_sys.reserve(L.ns_max);
+    h_row0.reserve(L.ns_max);
+    h_rows.reserve(L.ns_max);
+    for (int s = 0; s < nsys; ++s) {
+        h_sso[s] = (int32_t)h_sys.size();
+        for (int r0 = off[s]; r0 < off[s + 1]; r0 += 64) {
+            h_sys.push_back(s);
+            h_row0.push_back(r0);
+            h_rows.push_back(off[s + 1] - r0 < 64 ? off[s + 1] - r0 : 64);
+        }
+    }
+    h_sso[nsys] = (int32_t)h_sys.size();
+    const int ns = (int)h_sys.size();
+
+    hipStream_t s = batch_stream();
+    int32_t *hcount = pinned_count();
+    if (!s || !hcount) return hip_fail(hipErrorOutOfMemory, "stream/pinned buffer");
+    hipEvent_t e_in, e0, e1;
+    HIP_TRY(hipEventCreateWithFlags(&e_in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e_in, user));
+    HIP_TRY(hipStreamWaitEvent(s, e_in, 0));
+    HIP_TRY(hipEventRecord(e0, s));
+
+    BatchDev d{};
+    d.sys_slice_off = (int32_t *)(base + L.sys_slice_off);
+    d.slice_sys = (int32_t *)(base + L.slice_sys);
+    d.slice_row0 = (int32_t *)(base + L.slice_row0);
+    d.slice_rows = (int32_t *)(base + L.slice_rows);
+    d.sp = (int32_t *)(base + L.slice_ptr);
+    d.sc = (int32_t *)(base + L.col);
+    d.sv = (double *)(base + L.val);
+    double *dscal = (double *)(base + L.dscal);
+    d.rho = dscal;
+    d.alpha = d.rho + (size_t)K * nsys;
+    d.beta = d.alpha + (size_t)K * nsys;
+    d.nb = d.beta + (size_t)K * nsys;
+    d.rel = d.nb + nsys;
+    int32_t *iscal = (int32_t *)(base + L.iscal);
+    d.active = iscal;
+    d.xdue = iscal + nsys;
+    d.iters = iscal + 2 * nsys;
+    d.status = iscal + 3 * nsys;
+    d.n_active = iscal + 4 * nsys;
+    BatchParams *prm = (BatchParams *)(base + L.params);
+    d.tol = &prm->tol;
+    d.maxit = &prm->maxit;
+    d.normalize = &prm->normalize;
+    d.nsys = nsys;
+    d.ns = ns;
+    d.n = n;
+    double *r = (double *)(base + L.r);
+    double *p = (double *)(base + L.p);
+    double *q = (double *)(base + L.q);
+    double *sa = (double *)(base + L.slots_a);
+    double *sb = (double *)(base + L.slots_b);
+    int32_t *width = (int32_t *)(base + L.width);
+    long long *total = (long long *)(base + L.total);
+
+    const BatchParams hp{tol, maxit, opts ? opts->normalize : 1};
+    HIP_TRY(hipMemcpyAsync(prm, &hp, sizeof(hp), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync((void *)d.sys_slice_off, h_sso.data(), sizeof(int32_t) * (nsys + 1),
+                           hipMemcpyHostToDevice, s));
+    if (ns > 0) {
+        HIP_TRY(hipMemcpyAsync((void *)d.slice_sys, h_sys.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void *)d.slice_row0, h_row0.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void *)d.slice_rows, h_rows.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+    }
+    // system-aligned SELL-64 plan
+    const int nbw = blocks_for(ns > 0 ? ns : 1, NWAVE);
+    hipLaunchKernelGGL(mw_batch_width_kernel, dim3(nbw), dim3(BNT), 0, s, d, M->row_ptr, width);
+    HIP_TRY(hipGetLastError());
+    int rc = launch_sell_scan(ns, width, (int32_t *)d.sp, total, s);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(hcount, total, sizeof(long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));  // also retires the host-array uploads above
+    const long long stored = *(long long *)hcount;
+    if (stored > L.cap || stored > 0x7fffffffLL) {
+        set_error("batched solve: SELL-64 padding exceeds the workspace (rows of very uneven length)");
+        return MW_EINVAL;
+    }
+    hipLaunchKernelGGL(mw_batch_fill_kernel, dim3(nbw), dim3(BNT), 0, s, d, M->row_ptr, M->col_idx, M->val, d.sp,
+                       (int32_t *)d.sc, (double *)d.sv);
+    HIP_TRY(hipGetLastError());
+
+    // r0 = b - A x0, p0 = r0, per-system rho0, ||b||, flags
+    const int g = persistent_grid(blocks_for(ns > 0 ? ns : 1, NWAVE));
+    HIP_TRY(hipMemsetAsync(d.n_active, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL((mw_batch_spmv_kernel<A, 0>), dim3(g), dim3(BNT), 0, s, d, x, q, sa);
+    hipLaunchKernelGGL((mw_batch_init_kernel<A>), dim3(g), dim3(BNT), 0, s, d, b, q, r, p, sa, sb);
+    hipLaunchKernelGGL((mw_batch_init_final_kernel<A>), dim3(nsys), dim3(BNT), 0, s, d, sa, sb);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(hcount, d.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+
+    int chunks = 0;
+    if (*hcount > 0 && use_graph) {
+        BatchGraph &G = batch_graph();
+        BatchKey key{A, nsys, ns, n, chunk, {r, p, q, x, sa, sb, d.sp, base}};
+        if (!(G.valid && G.key == key)) {
+            G.release();
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            rc = enqueue_batch_chunk<A>(d, chunk, r, p, q, x, sa, sb, s);
+            hipGraph_t gr = nullptr;
+            const hipError_t ce = hipStreamEndCapture(s, &gr);
+            if (rc) return rc;
+            if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+            G.graph = gr;
+            HIP_TRY(hipGraphInstantiate(&G.exec, gr, nullptr, nullptr, 0));
+            G.key = key;
+            G.valid = true;
+        }
+    }
+    while (*hcount > 0) {
+        if (use_graph) {
+            HIP_TRY(hipGraphLaunch(batch_graph().exec, s));
+        } else {
+            rc = enqueue_batch_chunk<A>(d, chunk, r, p, q, x, sa, sb, s);
+            if (rc) return rc;
+        }
+        ++chunks;
+        HIP_TRY(hipMemcpyAsync(hcount, d.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    // (a system that stops in step 4 gets its last x update in step 5 of the
+    // same iteration; step 2 of the next iteration clears its pending flag)
+    if (iters_out) HIP_TRY(hipMemcpyAsync(iters_out, d.iters, sizeof(int32_t) * nsys, hipMemcpyDeviceToDevice, s));
+    if (status_out) HIP_TRY(hipMemcpyAsync(status_out, d.status, sizeof(int32_t) * nsys, hipMemcpyDeviceToDevice, s));
+    if (rel_out) HIP_TRY(hipMemcpyAsync(rel_out, d.rel, sizeof(double) * nsys, hipMemcpyDeviceToDevice, s));
+    std::vector<int32_t> hi(2 * (size_t)nsys);
+    HIP_TRY(hipMemcpyAsync(hi.data(), d.iters, sizeof(int32_t) * 2 * nsys, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e_in);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int worst = MW_OK, maxit_seen = 0;
+    for (int i = 0; i < nsys; ++i) {
+        if (hi[i] > maxit_seen) maxit_seen = hi[i];
+        if (hi[nsys + i] > worst) worst = hi[nsys + i];
+    }
+    if (info) {
+        info->iters = maxit_seen;
+        info->status = worst;
+        info->rel_res = 0.0;
+        info->seconds = ms * 1e-3;
+    }
+    (void)chunks;
+    return worst;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int32_t nnz)
+{
+    if (!valid_arith(a) || nsys <= 0 || n <= 0 || nnz < 0) return 0;
+    return batch_layout(a, nsys, n, nnz).bytes;
+}
+
+int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, const mw_csr_t *A, const double *b,
+                        double *x, double tol, int32_t maxit, const mw_cg_opts_t *opts, void *workspace,
+                        int32_t *iters, int32_t *status, double *rel_res, mw_cg_info_t *info, void *stream)
+{
+    if (!valid_arith(a) || nsys <= 0 || !sys_row_off || !valid_csr(A) || !b || !x || !workspace || !(tol >= 0.0) ||
+        maxit < 0)
+        return MW_EINVAL;
+    if (sys_row_off[0] != 0 || sys_row_off[nsys] != A->n) return MW_EINVAL;
+    for (int s = 0; s < nsys; ++s)
+        if (sys_row_off[s + 1] < sys_row_off[s]) return MW_EINVAL;
+    MW_DISPATCH(a, batched_a, nsys, sys_row_off, A, b, x, tol, maxit, opts, workspace, iters, status, rel_res, info,
+                (hipStream_t)stream);
+}
+
+}  // extern "C"

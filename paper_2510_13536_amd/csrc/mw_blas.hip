@@ -43,18 +43,6 @@ namespace {
 
 using namespace mwh;
 
-// Loads of the matrix stream in the planned SpMV.  For 3-word vectors the
-// CG working set (four vectors of 24 bytes per row) competes with the
-// matrix stream for the 256 MB Infinity Cache; the matrix entries are used
-// once per SpMV, so they are loaded non-temporally there.  For 1- and
-// 2-word vectors plain loads measured faster.
-template <int A, typename T>
-__device__ __forceinline__ T load_matrix(const T *p)
-{
-    if constexpr (words(A) == 3) return __builtin_nontemporal_load(p);
-    else return *p;
-}
-#define MW_LDM(p) load_matrix<A>(p)
 
 constexpr int DOT_EPT = 8;        // elements per thread in the standalone dot
 constexpr int CSR_NPT = 4;        // nonzeros per thread per LDS chunk (CSR SpMV)
@@ -233,23 +221,7 @@ __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const i
         const int s = t * NWAVE + wave;
         if (s >= ns) continue;  // whole wavefront
         const int row = s * 64 + lane;
-        const int e = sp[s + 1];
-        int z = sp[s] + lane;
-        Num<A> acc = zero<A>();
-        for (; z + 64 < e; z += 128) {
-            const double a0 = MW_LDM(sv + z), a1 = MW_LDM(sv + z + 64);
-            const int c0 = MW_LDM(sc + z), c1 = MW_LDM(sc + z + 64);
-            const Num<A> x0 = load<A>(x, n, c0 < 0 ? 0 : c0);
-            const Num<A> x1 = load<A>(x, n, c1 < 0 ? 0 : c1);
-            if (c0 >= 0) acc = row_step<A>(acc, a0, x0);
-            if (c1 >= 0) acc = row_step<A>(acc, a1, x1);
-        }
-        if (z < e) {
-            const double a0 = MW_LDM(sv + z);
-            const int c0 = MW_LDM(sc + z);
-            const Num<A> x0 = load<A>(x, n, c0 < 0 ? 0 : c0);
-            if (c0 >= 0) acc = row_step<A>(acc, a0, x0);
-        }
+        const Num<A> acc = sell_row_sum<A>(sp[s] + lane, sp[s + 1], sc, sv, x, n);
         if (row < n) {
             store<A>(y, n, row, acc);
             if constexpr (MODE == 1) part = dot_step<A>(part, load<A>(x, n, row), acc);
@@ -369,6 +341,13 @@ long long *pinned_total()
 // ============================================================ internal API
 
 namespace mwh {
+
+int launch_sell_scan(int ns, const int32_t *width, int32_t *slice_ptr, long long *total, hipStream_t s)
+{
+    hipLaunchKernelGGL(mw_sell_scan_kernel, dim3(1), dim3(FIN_NT), 0, s, ns, width, slice_ptr, total);
+    HIP_TRY(hipGetLastError());
+    return MW_OK;
+}
 
 int spmv_max_slots(int32_t n)
 {

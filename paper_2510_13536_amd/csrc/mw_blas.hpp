@@ -29,9 +29,62 @@ struct CgState {
     int32_t iters_final; // final iteration count (valid once stopped)
     int32_t pad;
 };
+// Loads of the matrix stream in the planned SpMV.  For 3-word vectors the
+// CG working set (four vectors of 24 bytes per row) competes with the
+// matrix stream for the 256 MB Infinity Cache; the matrix entries are used
+// once per SpMV, so they are loaded non-temporally there.  For 1- and
+// 2-word vectors plain loads measured faster.
+template <int A, typename T>
+__device__ __forceinline__ T load_matrix(const T *p)
+{
+    if constexpr (words(A) == 3) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+// Sum of one row of a SELL-64 slice: entries z0, z0 + 64, ... < z1 (the
+// lane's column of the slice), in order, from zero; padding (col < 0) is
+// skipped.  Two entries are loaded ahead of their dependent adds.
+template <int A>
+__device__ __forceinline__ Num<A> sell_row_sum(int z0, int z1, const int32_t *__restrict__ sc,
+                                               const double *__restrict__ sv, const double *__restrict__ x, long n)
+{
+    Num<A> acc = zero<A>();
+    int z = z0;
+    for (; z + 64 < z1; z += 128) {
+        const double a0 = load_matrix<A>(sv + z), a1 = load_matrix<A>(sv + z + 64);
+        const int c0 = load_matrix<A>(sc + z), c1 = load_matrix<A>(sc + z + 64);
+        const Num<A> x0 = load<A>(x, n, c0 < 0 ? 0 : c0);
+        const Num<A> x1 = load<A>(x, n, c1 < 0 ? 0 : c1);
+        if (c0 >= 0) acc = row_step<A>(acc, a0, x0);
+        if (c1 >= 0) acc = row_step<A>(acc, a1, x1);
+    }
+    if (z < z1) {
+        const double a0 = load_matrix<A>(sv + z);
+        const int c0 = load_matrix<A>(sc + z);
+        const Num<A> x0 = load<A>(x, n, c0 < 0 ? 0 : c0);
+        if (c0 >= 0) acc = row_step<A>(acc, a0, x0);
+    }
+    return acc;
+}
+
+// Sum over the 64 lanes of a wavefront (shuffle tree, offsets 32 .. 1);
+// valid in lane 0.
+template <int A>
+__device__ __forceinline__ Num<A> wave_sum(Num<A> v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = add<A>(v, shfl_down<A>(v, off));
+    return v;
+}
+
 }  // namespace mwk
 
 namespace mwh {
+
+// Exclusive scan of 64 * width[0..ns) into slice_ptr[0..ns], 64-bit total
+// into *total (one workgroup).
+int launch_sell_scan(int ns, const int32_t *width, int32_t *slice_ptr, long long *total, hipStream_t s);
+
 
 // Bytes of a SpMV plan buffer for an n x n matrix with nnz entries.
 size_t plan_bytes(int32_t n, int32_t nnz);

@@ -115,6 +115,11 @@ def lib():
     L.mw_cg_workspace_bytes.restype = C.c_size_t
     L.mw_cg_solve.argtypes = [C.c_int, C.POINTER(Csr), _vp, _vp, C.c_double, C.c_int32,
                               C.POINTER(CgOpts), _vp, C.POINTER(CgInfo), _vp]
+    L.mw_cg_batched_workspace_bytes.argtypes = [C.c_int, C.c_int32, C.c_int32, C.c_int32]
+    L.mw_cg_batched_workspace_bytes.restype = C.c_size_t
+    L.mw_cg_solve_batched.argtypes = [C.c_int, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Csr), _vp, _vp,
+                                      C.c_double, C.c_int32, C.POINTER(CgOpts), _vp, _vp, _vp, _vp,
+                                      C.POINTER(CgInfo), _vp]
     _lib = L
     return L
 
@@ -301,3 +306,38 @@ def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0
     if hist is not None:
         out["history"] = hist[:info.iters].cpu().numpy()
     return x, out
+
+
+def cg_solve_batched(arith, A, sys_row_off, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0,
+                     graph=True, workspace=None):
+    """Solve the independent systems on the diagonal blocks of A (a DeviceCSR)
+    together; sys_row_off: host sequence of nsys + 1 row offsets.
+
+    Returns (x (k, n) tensor, iters, status, rel_res (numpy arrays), info)."""
+    import numpy as np
+    k = WORDS[arith]
+    off = np.ascontiguousarray(np.asarray(sys_row_off, dtype=np.int32))
+    nsys = off.size - 1
+    b = b.reshape(-1)
+    if not (b.is_cuda and b.dtype == torch.float64 and b.is_contiguous() and b.numel() == A.n):
+        raise MWError("b must be a contiguous float64 CUDA tensor of length n")
+    if x is None:
+        x = torch.zeros((k, A.n), dtype=torch.float64, device=b.device)
+    x = _vec(x, k, A.n, name="x")
+    if maxit is None:
+        maxit = 10 * int(np.max(np.diff(off))) if nsys > 0 else 0
+    if workspace is None:
+        nbytes = lib().mw_cg_batched_workspace_bytes(ARITH[arith], nsys, A.n, A.nnz)
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    iters = torch.zeros(nsys, dtype=torch.int32, device=b.device)
+    status = torch.zeros(nsys, dtype=torch.int32, device=b.device)
+    rel = torch.zeros(nsys, dtype=torch.float64, device=b.device)
+    opts = CgOpts(1 if normalize else 0, int(chunk), None, None, None, 0 if graph else 1, 0)
+    info = CgInfo()
+    csr = A.c()
+    rc = lib().mw_cg_solve_batched(ARITH[arith], nsys, off.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(csr),
+                                   _ptr(b), _ptr(x), float(tol), int(maxit), C.byref(opts), _ptr(workspace),
+                                   _ptr(iters), _ptr(status), _ptr(rel), C.byref(info), _stream())
+    _check(rc, "mw_cg_solve_batched")
+    return (x, iters.cpu().numpy(), status.cpu().numpy(), rel.cpu().numpy(),
+            {"iters": info.iters, "status": STATUS.get(info.status, str(info.status)), "seconds": info.seconds})

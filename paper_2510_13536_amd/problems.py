@@ -196,6 +196,16 @@ class Batch:
         return sub, self.b[r0:r1].copy()
 
 
+def batch_from_systems(mats, bs, kinds=None):
+    """A Batch from a list of CSR systems and their right-hand sides."""
+    A = CSR.from_scipy(sp.block_diag([m.to_scipy() for m in mats], format="csr"))
+    off = np.zeros(len(mats) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([m.n for m in mats])
+    b = np.concatenate([np.asarray(v, dtype=np.float64) for v in bs])
+    return Batch(A=A, sys_row_off=off.astype(np.int32), b=b, x_true=np.full(A.n, np.nan),
+                 kinds=kinds or ["given"] * len(mats))
+
+
 def batch_systems(nsys=512, seed=4, nmin=1024, nmax=65536):
     """Uneven batch: n_s = round(exp(U(ln nmin, ln nmax))).  Even s: Poisson,
     2D for s % 4 == 0 (nx = round(sqrt n), ny = round(n / nx)), 3D for

@@ -1,0 +1,95 @@
+"""Batched CG (many independent systems in one lockstep solve) on the GPU,
+against the CPU oracle run system by system and against the single-system
+GPU solver.  Bars as for CG: same status, iterations within 2 %, true
+residual within 10x of the oracle's."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from paper_2510_13536_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mw():
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    from paper_2510_13536_amd import mw as M
+    M.lib()
+    return M
+
+
+def dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    """20 uneven systems (Poisson 2D/3D, circulant) plus: a zero right-hand
+    side, a single-row system, and an indefinite system (breaks down)."""
+    B = P.batch_systems(nsys=20, seed=11, nmin=100, nmax=3000)
+    mats = [B.system(s)[0] for s in range(B.nsys)]
+    bs = [B.system(s)[1] for s in range(B.nsys)]
+    bs[3] = np.zeros_like(bs[3])
+    mats.append(P.CSR.from_scipy(sp.identity(1) * 2.0))
+    bs.append(np.array([3.0]))
+    M = P.poisson2d(12).to_scipy().tolil()
+    M[0, 0] = -4.0
+    mats.append(P.CSR.from_scipy(M))
+    e0 = np.zeros(144)
+    e0[0] = 1.0
+    bs.append(e0)
+    return mats, bs, P.batch_from_systems(mats, bs)
+
+
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qdw", "tw", "qtw"])
+def test_batched_matches_oracle_per_system(mw, small_batch, arith):
+    mats, bs, B = small_batch
+    Ad = mw.DeviceCSR.from_host(B.A)
+    x, iters, status, rel, info = mw.cg_solve_batched(arith, Ad, B.sys_row_off, dev(B.b), tol=1e-12, maxit=20000)
+    x = x.cpu().numpy()
+    off = B.sys_row_off
+    for s, (A, b) in enumerate(zip(mats, bs)):
+        xo, io = O.cg_solve(arith, A, b, tol=1e-12, maxit=20000)
+        st = {0: "ok", 1: "not_converged", 2: "breakdown"}[int(status[s])]
+        assert st == io["status"], (s, st, io)
+        assert abs(int(iters[s]) - io["iters"]) <= max(1, int(0.02 * io["iters"])), (s, iters[s], io["iters"])
+        if io["status"] == "ok" and np.any(b):
+            xs = x[:, off[s]:off[s + 1]]
+            nb = np.linalg.norm(b)
+            trg = O.true_residual(arith, A, b, xs) / nb
+            tro = O.true_residual(arith, A, b, xo) / nb
+            assert trg <= 10 * max(tro, 1e-300), (s, trg, tro)
+    assert int(iters[3]) == 0 and int(status[3]) == 0          # b = 0
+    assert int(status[-1]) == 2                                 # indefinite system
+    assert info["status"] == "breakdown"
+
+
+def test_batched_matches_single_solver_and_is_deterministic(mw, small_batch):
+    mats, bs, B = small_batch
+    Ad = mw.DeviceCSR.from_host(B.A)
+    x1, it1, st1, _, _ = mw.cg_solve_batched("qtw", Ad, B.sys_row_off, dev(B.b), tol=1e-12)
+    x2, it2, st2, _, _ = mw.cg_solve_batched("qtw", Ad, B.sys_row_off, dev(B.b), tol=1e-12, graph=False)
+    assert np.array_equal(it1, it2) and np.array_equal(st1, st2)
+    assert np.array_equal(x1.cpu().numpy().view(np.uint64), x2.cpu().numpy().view(np.uint64))
+    for s in range(0, len(mats), 4):
+        _, i = mw.cg_solve("qtw", mw.DeviceCSR.from_host(mats[s]), dev(bs[s]), tol=1e-12)
+        assert abs(i["iters"] - int(it1[s])) <= max(1, int(0.02 * i["iters"])), (s, i, it1[s])
+
+
+def test_batched_maxit(mw, small_batch):
+    mats, bs, B = small_batch
+    Ad = mw.DeviceCSR.from_host(B.A)
+    _, iters, status, _, info = mw.cg_solve_batched("dw", Ad, B.sys_row_off, dev(B.b), tol=1e-12, maxit=5)
+    for s in range(len(mats)):
+        if s == 3:
+            assert iters[s] == 0 and status[s] == 0
+        elif s == len(mats) - 2:          # 1x1 system converges in one step
+            assert iters[s] == 1 and status[s] == 0
+        elif s == len(mats) - 1:
+            assert status[s] == 2
+        else:
+            assert iters[s] == 5 and status[s] == 1
