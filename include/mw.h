@@ -238,6 +238,18 @@ int mw_spmv_plan(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *
  * Asynchronous. */
 int mw_spmv_planned(mw_arith_t a, const mw_spmv_plan_t *plan, const double *x, double *y, void *stream);
 
+/*
+ * Gradient of a loss with respect to the stored entries of A, for
+ * x = A^-1 b and lam = A^-T (dL/dx) (the adjoint solve; for SPD A the same
+ * CG as the forward solve): grad_val[k] = -(lam_i * x_j) for the k-th
+ * stored entry (i, j), the product formed in the arithmetic and rounded to
+ * FP64.  dL/db is lam itself.  (The adjoint is a pattern added beside the
+ * paper's method; each of its solves is Alg. 1.)  lam, x: k planes of n;
+ * grad_val: FP64[nnz], CSR order.  Asynchronous.
+ */
+int mw_csr_grad(mw_arith_t a, const mw_csr_t *A, const double *lam, const double *x, double *grad_val,
+                void *stream);
+
 /* Bytes of device workspace mw_cg_solve needs (256-byte aligned),
  * including room for a SpMV plan of A. */
 size_t mw_cg_workspace_bytes(mw_arith_t a, int32_t n, int32_t nnz);

@@ -1,0 +1,49 @@
+"""Differentiable multi-word CG solve (torch.autograd.Function).
+
+Forward: x = A^-1 b by the library's CG in the chosen arithmetic (Alg. 1),
+returned rounded to FP64.  Backward: lam = A^-T g (g = dL/dx) by the same
+CG (A is SPD, so A^T = A); dL/db = lam; dL/dA_ij = -lam_i x_j on A's
+pattern (mw_csr_grad).  Gradients reach any parameter the values depend
+on through ordinary autograd (e.g. dL/dtheta_i = -lam_i x_i for
+A = L + diag(theta)).  Every step runs in libmwcg; this module only wires
+the calls into autograd.
+"""
+import torch
+
+from . import mw
+
+
+class MWCGSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, val, b, row_ptr, col_idx, arith, tol, maxit, info_out):
+        A = mw.DeviceCSR(b.numel(), row_ptr, col_idx, val.detach().contiguous())
+        x, info = mw.cg_solve(arith, A, b.detach().contiguous(), tol=tol, maxit=maxit)
+        if info["status"] != "ok":
+            raise mw.MWError("forward solve did not converge: %s" % info)
+        ctx.A, ctx.arith, ctx.tol, ctx.maxit, ctx.info_out = A, arith, tol, maxit, info_out
+        ctx.x = x
+        if info_out is not None:
+            info_out["forward"] = info
+        return mw.elementwise(arith, "tofp64", x).reshape(-1)
+
+    @staticmethod
+    def backward(ctx, grad_x):
+        A, arith = ctx.A, ctx.arith
+        lam, info = mw.cg_solve(arith, A, grad_x.detach().contiguous().reshape(-1), tol=ctx.tol, maxit=ctx.maxit)
+        if info["status"] != "ok":
+            raise mw.MWError("adjoint solve did not converge: %s" % info)
+        if ctx.info_out is not None:
+            ctx.info_out["adjoint"] = info
+            ctx.info_out["lam"] = lam
+            ctx.info_out["x"] = ctx.x
+        grad_b = mw.elementwise(arith, "tofp64", lam).reshape(-1)
+        grad_val = mw.csr_grad(arith, A, lam, ctx.x)
+        return grad_val, grad_b, None, None, None, None, None, None
+
+
+def cg_solve(A, val, b, arith="qtw", tol=1e-12, maxit=None, info=None):
+    """x = A(val)^-1 b, differentiable in val and b.  A supplies n, row_ptr
+    and col_idx (a DeviceCSR); val: FP64 values on A's pattern."""
+    if maxit is None:
+        maxit = 10 * A.n
+    return MWCGSolve.apply(val, b, A.row_ptr, A.col_idx, arith, tol, maxit, info)

@@ -233,6 +233,24 @@ __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const i
     }
 }
 
+// ------------------------------------------------- gradient on a pattern
+//
+// grad_val[k] = -(lam_i * x_j) for the k-th stored entry (i, j): the
+// derivative of a loss with respect to A_ij when x = A^-1 b and lam solves
+// A^T lam = dL/dx.  The product is formed in the arithmetic and rounded
+// to FP64 (FP64: -(lam_i * x_j), one rounding).  One thread per row.
+template <int A>
+__global__ void __launch_bounds__(NT) mw_csr_grad_kernel(int n, const int32_t *__restrict__ row_ptr,
+                                                         const int32_t *__restrict__ col,
+                                                         const double *__restrict__ lam,
+                                                         const double *__restrict__ x, double *__restrict__ grad)
+{
+    const long i = (long)xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+    if (i >= n) return;
+    const Num<A> li = load<A>(lam, n, i);
+    for (int z = row_ptr[i]; z < row_ptr[i + 1]; ++z) grad[z] = -to_fp64<A>(mul<A>(li, load<A>(x, n, col[z])));
+}
+
 // -------------------------------------------------------------- SELL plan
 
 // Width (longest row) of every 64-row slice: one wavefront per slice.
@@ -492,6 +510,15 @@ int dot_a(int32_t n, const double *x, const double *y, double *res, void *ws, hi
 }
 
 template <int A>
+int grad_a(const mw_csr_t *M, const double *lam, const double *x, double *grad, hipStream_t s)
+{
+    hipLaunchKernelGGL((mw_csr_grad_kernel<A>), dim3(blocks_for(M->n, NT)), dim3(NT), 0, s, M->n, M->row_ptr,
+                       M->col_idx, lam, x, grad);
+    HIP_TRY(hipGetLastError());
+    return MW_OK;
+}
+
+template <int A>
 int spmv_csr_a(const mw_csr_t *M, const double *x, double *y, hipStream_t s)
 {
     return mwh::spmv_launch<A>(M, nullptr, x, y, nullptr, nullptr, nullptr, 0, s);
@@ -564,6 +591,14 @@ int mw_spmv(mw_arith_t a, const mw_csr_t *A, const double *x, double *y, void *s
     if (!valid_arith(a) || !valid_csr(A) || !x || !y || x == y) return MW_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     MW_DISPATCH(a, spmv_csr_a, A, x, y, s);
+}
+
+int mw_csr_grad(mw_arith_t a, const mw_csr_t *A, const double *lam, const double *x, double *grad_val,
+                void *stream)
+{
+    if (!valid_arith(a) || !valid_csr(A) || !lam || !x || !grad_val) return MW_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    MW_DISPATCH(a, grad_a, A, lam, x, grad_val, s);
 }
 
 size_t mw_spmv_plan_bytes(int32_t n, int32_t nnz)

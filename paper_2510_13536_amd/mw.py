@@ -115,6 +115,7 @@ def lib():
     L.mw_cg_workspace_bytes.restype = C.c_size_t
     L.mw_cg_solve.argtypes = [C.c_int, C.POINTER(Csr), _vp, _vp, C.c_double, C.c_int32,
                               C.POINTER(CgOpts), _vp, C.POINTER(CgInfo), _vp]
+    L.mw_csr_grad.argtypes = [C.c_int, C.POINTER(Csr), _vp, _vp, _vp, _vp]
     L.mw_cg_batched_workspace_bytes.argtypes = [C.c_int, C.c_int32, C.c_int32, C.c_int32]
     L.mw_cg_batched_workspace_bytes.restype = C.c_size_t
     L.mw_cg_solve_batched.argtypes = [C.c_int, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Csr), _vp, _vp,
@@ -267,6 +268,18 @@ def spmv_planned(arith, plan, x, y=None):
     y = _vec(y, k, plan.A.n, name="y")
     _check(lib().mw_spmv_planned(ARITH[arith], C.byref(plan.c), _ptr(x), _ptr(y), _stream()), "mw_spmv_planned")
     return y
+
+
+def csr_grad(arith, A, lam, x, out=None):
+    """grad_val[k] = -(lam_i x_j) on A's pattern (FP64, CSR order)."""
+    k = WORDS[arith]
+    lam = _vec(lam, k, A.n, name="lam")
+    x = _vec(x, k, A.n, name="x")
+    if out is None:
+        out = torch.empty(A.nnz, dtype=torch.float64, device=x.device)
+    csr = A.c()
+    _check(lib().mw_csr_grad(ARITH[arith], C.byref(csr), _ptr(lam), _ptr(x), _ptr(out), _stream()), "mw_csr_grad")
+    return out
 
 
 def cg_workspace(arith, A, device=None):

@@ -1,0 +1,120 @@
+"""Adjoint (differentiable) CG: dL/db = lam, dL/dA_ij = -lam_i x_j with
+lam = A^-T dL/dx, both solves in multi-word CG.
+
+* the gradient kernel is bit-identical to the oracle's element-wise ops;
+* gradients with respect to theta (A = L + diag(theta)) and b match
+  central finite differences, with the loss and its differences carried in
+  QTW (the FD quotient needs the loss to far better than FP64);
+* they match the gradient assembled from oracle solves.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import rand_mw
+from paper_2510_13536_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    from paper_2510_13536_amd import adjoint, mw
+    mw.lib()
+    return torch, mw, adjoint
+
+
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qdw", "tw", "qtw"])
+def test_grad_kernel_bit_exact(mods, arith):
+    torch, mw, _ = mods
+    A = P.poisson3d(9, 8, 7)
+    k = O.WORDS[arith]
+    rng = np.random.default_rng(3)
+    lam = rand_mw(rng, k, A.n)
+    x = rand_mw(rng, k, A.n)
+    got = mw.csr_grad(arith, mw.DeviceCSR.from_host(A), torch.as_tensor(lam, device="cuda"),
+                      torch.as_tensor(x, device="cuda")).cpu().numpy()
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    prod = O.elementwise(arith, "mul", lam[:, rows], x[:, A.col_idx])
+    want = -O.elementwise(arith, "tofp64", prod)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def _problem(nx=12):
+    Q = P.adjoint_problem(nx=nx, seed=5, bseed=555, tseed=55)
+    return Q
+
+
+def _loss_qtw(mw, torch, Q, theta, b, tol):
+    """0.5 ||x - x_target||^2 carried in QTW (3 words)."""
+    A = mw.DeviceCSR.from_host(Q.matrix(theta))
+    x, info = mw.cg_solve("qtw", A, torch.as_tensor(b, device="cuda"), tol=tol)
+    assert info["status"] == "ok"
+    t = torch.zeros_like(x)
+    t[0] = -torch.as_tensor(Q.x_target, device="cuda")
+    d = mw.elementwise("qtw", "add", x, t)
+    return mw.dot("qtw", d, d) * 0.5  # scaling by 1/2 is exact word by word
+
+
+def _diff(mw, torch, a, b):
+    """fp64(a - b) for two QTW scalars."""
+    return float(mw.elementwise("qtw", "tofp64", mw.elementwise("qtw", "add", a.reshape(3, 1),
+                                                                  -b.reshape(3, 1)))[0, 0])
+
+
+def test_adjoint_matches_finite_differences(mods):
+    torch, mw, adjoint = mods
+    Q = _problem(12)
+    Ad = mw.DeviceCSR.from_host(Q.lap)
+    lap_val = torch.as_tensor(Q.lap.val, device="cuda")
+    pos = torch.as_tensor(Q.diag_pos, device="cuda")
+    theta = torch.as_tensor(Q.theta, device="cuda").requires_grad_(True)
+    b = torch.as_tensor(Q.b, device="cuda").requires_grad_(True)
+    xt = torch.as_tensor(Q.x_target, device="cuda")
+    val = lap_val.index_add(0, pos, theta)
+    x = adjoint.cg_solve(Ad, val, b, arith="qtw", tol=1e-28)
+    loss = 0.5 * ((x - xt) ** 2).sum()
+    loss.backward()
+    g_theta = theta.grad.cpu().numpy()
+    g_b = b.grad.cpu().numpy()
+    rng = np.random.default_rng(5555)
+    for which, g, base in (("theta", g_theta, Q.theta), ("b", g_b, Q.b)):
+        gmax = np.abs(g).max()
+        for i in rng.choice(Q.lap.n, 8, replace=False):
+            h = 1e-4 * max(abs(base[i]), 1e-2) if which == "theta" else 1e-4
+            th_p, th_m, b_p, b_m = Q.theta.copy(), Q.theta.copy(), Q.b.copy(), Q.b.copy()
+            if which == "theta":
+                th_p[i] += h
+                th_m[i] -= h
+            else:
+                b_p[i] += h
+                b_m[i] -= h
+            Lp = _loss_qtw(mw, torch, Q, th_p, b_p, 1e-30)
+            Lm = _loss_qtw(mw, torch, Q, th_m, b_m, 1e-30)
+            # the perturbed coordinate moved by exactly the FP64 step
+            step = ((th_p[i] - th_m[i]) if which == "theta" else (b_p[i] - b_m[i]))
+            fd = _diff(mw, torch, Lp, Lm) / step
+            assert abs(g[i] - fd) <= 1e-6 * abs(fd) + 1e-9 * gmax, (which, i, g[i], fd)
+
+
+def test_adjoint_matches_oracle_gradient(mods):
+    torch, mw, adjoint = mods
+    Q = _problem(10)
+    Ad = mw.DeviceCSR.from_host(Q.lap)
+    theta = torch.as_tensor(Q.theta, device="cuda").requires_grad_(True)
+    b = torch.as_tensor(Q.b, device="cuda").requires_grad_(True)
+    val = torch.as_tensor(Q.lap.val, device="cuda").index_add(0, torch.as_tensor(Q.diag_pos, device="cuda"), theta)
+    x = adjoint.cg_solve(Ad, val, b, arith="qtw", tol=1e-26)
+    (0.5 * ((x - torch.as_tensor(Q.x_target, device="cuda")) ** 2).sum()).backward()
+    # the same gradient from oracle solves
+    A = Q.matrix()
+    xo, io = O.cg_solve("qtw", A, Q.b, tol=1e-26)
+    g = O.elementwise("qtw", "tofp64", xo) - Q.x_target
+    lo, il = O.cg_solve("qtw", A, g, tol=1e-26)
+    assert io["status"] == "ok" and il["status"] == "ok"
+    gt = -O.elementwise("qtw", "tofp64", O.elementwise("qtw", "mul", lo, xo))
+    gb = O.elementwise("qtw", "tofp64", lo)
+    np.testing.assert_allclose(theta.grad.cpu().numpy(), gt, rtol=1e-10, atol=1e-12 * np.abs(gt).max())
+    np.testing.assert_allclose(b.grad.cpu().numpy(), gb, rtol=1e-10, atol=1e-12 * np.abs(gb).max())
