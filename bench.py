@@ -67,6 +67,78 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def bench_batched(mw, P, torch, dev, nsys=512):
+    """512 uneven SPD systems (Poisson 2D/3D and circulant Laplacians, n in
+    [1024, 65536]): one batched solve vs a loop of single solves, QTW and
+    DW, tol 1e-12."""
+    import numpy as np
+    B = P.batch_systems(nsys=nsys)
+    Ad = mw.DeviceCSR.from_host(B.A, dev)
+    bd = torch.as_tensor(B.b, device=dev)
+    subs = [B.system(s) for s in range(B.nsys)]
+    devs = [(mw.DeviceCSR.from_host(A, dev), torch.as_tensor(b, device=dev)) for A, b in subs]
+    out = {"workload": "%d systems, n=%d, nnz=%d" % (B.nsys, B.A.n, B.A.nnz)}
+    for ar in ("qtw", "dw"):
+        k = WORDS[ar]
+        x = torch.zeros((k, B.A.n), dtype=torch.float64, device=dev)
+        mw.cg_solve_batched(ar, Ad, B.sys_row_off, bd, x=x, tol=1e-12, maxit=100)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, iters, status, rel, info = mw.cg_solve_batched(ar, Ad, B.sys_row_off, bd, x=x, tol=1e-12)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = []
+        for (A, b) in devs:
+            its.append(mw.cg_solve(ar, A, b, tol=1e-12)[1]["iters"])
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t0
+        its = np.array(its)
+        out[ar] = {"batched_s": round(tb, 4), "loop_s": round(tl, 4), "speedup": round(tl / tb, 2),
+                   "max_iters": int(iters.max()), "mean_iters": round(float(iters.mean()), 1),
+                   "all_converged": bool((status == 0).all()),
+                   "iters_within_2pct_of_loop": float(np.mean(np.abs(its - iters) <= np.maximum(1, 0.02 * its)))}
+        log("batched %s: %s" % (ar, out[ar]))
+    return out
+
+
+def bench_adjoint(mw, P, torch, dev):
+    """A(theta) = 3D Laplacian 100^3 + diag(theta), loss 0.5||x - x_t||^2,
+    QTW: forward + adjoint solve (all 2n gradient entries) vs the cost of
+    central finite differences (2 solves per coordinate)."""
+    from paper_2510_13536_amd import adjoint
+    Q = P.adjoint_problem(nx=100)
+    Ad = mw.DeviceCSR.from_host(Q.lap, dev)
+    lap_val = torch.as_tensor(Q.lap.val, device=dev)
+    pos = torch.as_tensor(Q.diag_pos, device=dev)
+    xt = torch.as_tensor(Q.x_target, device=dev)
+    out = {"workload": "3D Laplacian 100^3 + diag(theta), n=%d, nnz=%d, QTW" % (Q.lap.n, Q.lap.nnz)}
+    for tol in (1e-12, 1e-24):
+        times = []
+        for rep in range(2):
+            theta = torch.as_tensor(Q.theta, device=dev).requires_grad_(True)
+            b = torch.as_tensor(Q.b, device=dev).requires_grad_(True)
+            info = {}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x = adjoint.cg_solve(Ad, lap_val.index_add(0, pos, theta), b, arith="qtw", tol=tol, info=info)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            (0.5 * ((x - xt) ** 2).sum()).backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            times.append((t1 - t0, t2 - t1, info["forward"]["iters"], info["adjoint"]["iters"]))
+        fwd, bwd, itf, itb = times[-1]
+        out["tol_%g" % tol] = {"forward_s": round(fwd, 4), "backward_s": round(bwd, 4),
+                               "backward_over_forward": round(bwd / fwd, 3), "forward_iters": itf,
+                               "adjoint_iters": itb, "fd_s_per_coordinate": round(2 * fwd, 4),
+                               "fd_s_for_all_2n_coordinates": round(2 * fwd * 2 * Q.lap.n, 1)}
+        log("adjoint tol %g: %s" % (tol, out["tol_%g" % tol]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +260,10 @@ def main():
             log("%s: %s" % (ar, tts[ar]))
         extra["time_to_solution"] = tts
         extra["qtw_over_dw"] = round(tts["qtw"]["seconds"] / tts["dw"]["seconds"], 3)
+
+    if not args.quick:
+        extra["batched"] = bench_batched(mw, P, torch, dev)
+        extra["adjoint"] = bench_adjoint(mw, P, torch, dev)
 
     cpu = None
     if not args.no_cpu:

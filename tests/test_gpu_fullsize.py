@@ -1,0 +1,165 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark uses (planned SELL-64 SpMV, graph-replayed CG chunks):
+
+* 3D Poisson 128^3 and the banded ill-conditioned matrix (n = 2^20,
+  27 per row): the whole SpMV bit-identical to the oracle, all arithmetics;
+* the first 5 CG iterations match the oracle's iterate to near the
+  format's precision (only the dot association differs);
+* complete 128^3 solves: iterations within 2 % of the oracle's FP64 solve,
+  exact true residual consistent with the recursive one;
+* the 512-system batch: sampled systems against oracle solves;
+* the adjoint problem at 100^3: gradients against central differences.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2510_13536_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+ARITHS = ["fp64", "dw", "qdw", "tw", "qtw"]
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    from paper_2510_13536_amd import mw
+    mw.lib()
+    return torch, mw
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return P.case_poisson3d(128)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return P.case_banded_illcond()
+
+
+def _rand_words(k, n, seed):
+    rng = np.random.default_rng(seed)
+    x = [rng.uniform(-1, 1, n)]
+    for _ in range(1, k):
+        x.append(x[-1] * rng.uniform(-1, 1, n) * 2.0 ** -54)
+    return np.ascontiguousarray(np.stack(x))
+
+
+@pytest.mark.parametrize("case", ["c2", "c3"])
+@pytest.mark.parametrize("arith", ARITHS)
+def test_full_spmv_bit_exact(mods, request, case, arith):
+    torch, mw = mods
+    A = request.getfixturevalue(case)[0]
+    x = _rand_words(O.WORDS[arith], A.n, 21)
+    plan = mw.Plan(mw.DeviceCSR.from_host(A))
+    assert plan.format == "sell64"
+    got = mw.spmv_planned(arith, plan, torch.as_tensor(x, device="cuda")).cpu().numpy()
+    want = O.spmv(arith, A, x)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def _word_diff(arith, a, b):
+    """max_i |a_i - b_i| (exact word sums rounded) and max |b_i|."""
+    d = O.elementwise(arith, "add", a, -b)
+    return np.abs(O.elementwise(arith, "tofp64", d)).max(), np.abs(O.elementwise(arith, "tofp64", b)).max()
+
+
+@pytest.mark.parametrize("case", ["c2", "c3"])
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qtw"])
+def test_first_iterations_match_oracle(mods, request, case, arith):
+    torch, mw = mods
+    A, b, _ = request.getfixturevalue(case)
+    xg, ig = mw.cg_solve(arith, mw.DeviceCSR.from_host(A), torch.as_tensor(b, device="cuda"), tol=1e-30, maxit=5)
+    xo, io = O.cg_solve(arith, A, b, tol=1e-30, maxit=5)
+    assert ig["status"] == io["status"] == "not_converged" and ig["iters"] == io["iters"] == 5
+    diff, scale = _word_diff(arith, xg.cpu().numpy(), xo)
+    # The iterates differ only through the association of the dots (tree on
+    # the GPU, sequential in the oracle): an error of about n u^k
+    # sum|p_i q_i| / |p^T q| in alpha and beta.  On the D A D-scaled banded
+    # matrix the terms of p^T q span ~12 decades and cancel heavily, so its
+    # bounds are wider; both stay far below the next-lower format's unit
+    # round-off (multi-word differences are ~1e-20 below FP64's).
+    bound = {"c2": {"fp64": 1e-12, "dw": 1e-26, "qtw": 1e-36},
+             "c3": {"fp64": 1e-10, "dw": 1e-24, "qtw": 1e-34}}[case][arith]
+    assert diff <= bound * scale, (diff / scale)
+
+
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qtw"])
+def test_c2_full_solve(mods, c2, arith):
+    torch, mw = mods
+    A, b, _ = c2
+    xg, ig = mw.cg_solve(arith, mw.DeviceCSR.from_host(A), torch.as_tensor(b, device="cuda"), tol=1e-12)
+    assert ig["status"] == "ok" and ig["rel_res"] < 1e-12
+    # the oracle's FP64 solve of the same system (multi-word oracle solves
+    # at this size take minutes; at 1e-12 on this kappa ~ 7e3 problem all
+    # arithmetics take the same iteration count at every size tested)
+    _, io = O.cg_solve("fp64", A, b, tol=1e-12)
+    assert abs(ig["iters"] - io["iters"]) <= max(1, int(0.02 * io["iters"])), (ig, io)
+    nb = np.linalg.norm(b)
+    tr = O.true_residual(arith, A, b, xg.cpu().numpy()) / nb
+    assert tr < 10 * max(ig["rel_res"], 1e-15), (tr, ig["rel_res"])
+
+
+def test_c4_batch_sampled_systems(mods):
+    torch, mw = mods
+    B = P.batch_systems()
+    Ad = mw.DeviceCSR.from_host(B.A)
+    x, iters, status, rel, info = mw.cg_solve_batched("qtw", Ad, B.sys_row_off, torch.as_tensor(B.b, device="cuda"),
+                                                      tol=1e-12)
+    assert (status == 0).all()
+    x = x.cpu().numpy()
+    sizes = np.diff(B.sys_row_off)
+    small = [s for s in range(B.nsys) if sizes[s] <= 2500]
+    for s in small[:: max(1, len(small) // 12)]:
+        A, b = B.system(s)
+        xo, io = O.cg_solve("qtw", A, b, tol=1e-12)
+        assert io["status"] == "ok"
+        assert abs(int(iters[s]) - io["iters"]) <= max(1, int(0.02 * io["iters"])), (s, iters[s], io)
+        r0, r1 = B.sys_row_off[s], B.sys_row_off[s + 1]
+        nb = np.linalg.norm(b)
+        assert O.true_residual("qtw", A, b, x[:, r0:r1]) / nb <= 10 * max(O.true_residual("qtw", A, b, xo) / nb, 1e-300)
+
+
+def test_c5_adjoint_finite_differences(mods):
+    torch, mw = mods
+    from paper_2510_13536_amd import adjoint
+    Q = P.adjoint_problem(nx=100)
+    Ad = mw.DeviceCSR.from_host(Q.lap)
+    theta = torch.as_tensor(Q.theta, device="cuda").requires_grad_(True)
+    b = torch.as_tensor(Q.b, device="cuda").requires_grad_(True)
+    xt = torch.as_tensor(Q.x_target, device="cuda")
+    pos = torch.as_tensor(Q.diag_pos, device="cuda")
+    val = torch.as_tensor(Q.lap.val, device="cuda").index_add(0, pos, theta)
+    x = adjoint.cg_solve(Ad, val, b, arith="qtw", tol=1e-26)
+    (0.5 * ((x - xt) ** 2).sum()).backward()
+    g = theta.grad.cpu().numpy()
+    gb = b.grad.cpu().numpy()
+
+    def loss(th, bb):
+        A = mw.DeviceCSR.from_host(Q.matrix(th))
+        xs, info = mw.cg_solve("qtw", A, torch.as_tensor(bb, device="cuda"), tol=1e-30)
+        assert info["status"] == "ok"
+        t = torch.zeros_like(xs)
+        t[0] = -xt
+        d = mw.elementwise("qtw", "add", xs, t)
+        return mw.dot("qtw", d, d) * 0.5
+
+    def diff(a, c):
+        return float(mw.elementwise("qtw", "tofp64", mw.elementwise("qtw", "add", a.reshape(3, 1), -c.reshape(3, 1)))[0, 0])
+
+    rng = np.random.default_rng(5555)
+    for i in rng.choice(Q.lap.n, 3, replace=False):
+        h = 1e-4 * max(abs(Q.theta[i]), 1e-2)
+        tp, tm = Q.theta.copy(), Q.theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = diff(loss(tp, Q.b), loss(tm, Q.b)) / (tp[i] - tm[i])
+        assert abs(g[i] - fd) <= 1e-6 * abs(fd) + 1e-9 * np.abs(g).max(), (i, g[i], fd)
+        bp, bm = Q.b.copy(), Q.b.copy()
+        bp[i] += 1e-4
+        bm[i] -= 1e-4
+        fd = diff(loss(Q.theta, bp), loss(Q.theta, bm)) / (bp[i] - bm[i])
+        assert abs(gb[i] - fd) <= 1e-6 * abs(fd) + 1e-9 * np.abs(gb).max(), (i, gb[i], fd)
