@@ -309,6 +309,62 @@ __device__ __forceinline__ void store_scalar(double *__restrict__ s, const Num<A
     for (int w = 0; w < words(A); ++w) s[w] = x.w[w];
 }
 
+// Word-interleaved vectors (element i's k words at v[k i .. k i + k)): the
+// solvers keep p, the only vector the SpMV gathers, in this layout so one
+// gathered element is one or two wide loads instead of k narrow ones.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+template <int A>
+__device__ __forceinline__ Num<A> load_il(const double *__restrict__ v, long i)
+{
+    Num<A> r;
+    if constexpr (words(A) == 1) {
+        r.w[0] = v[i];
+    } else if constexpr (words(A) == 2) {
+        const dvec2 t = *(const dvec2 *)(v + 2 * i);
+        r.w[0] = t.x;
+        r.w[1] = t.y;
+    } else {
+        struct W3 {
+            double a, b, c;
+        } t;
+        __builtin_memcpy(&t, v + 3 * i, sizeof(t));
+        r.w[0] = t.a;
+        r.w[1] = t.b;
+        r.w[2] = t.c;
+    }
+    return r;
+}
+
+template <int A>
+__device__ __forceinline__ void store_il(double *__restrict__ v, long i, const Num<A> &x)
+{
+    if constexpr (words(A) == 2) {
+        dvec2 t;
+        t.x = x.w[0];
+        t.y = x.w[1];
+        *(dvec2 *)(v + 2 * i) = t;
+    } else {
+#pragma unroll
+        for (int w = 0; w < words(A); ++w) v[words(A) * i + w] = x.w[w];
+    }
+}
+
+// Load of element i in word planes (IL = 0) or interleaved (IL = 1).
+template <int A, int IL>
+__device__ __forceinline__ Num<A> load_v(const double *__restrict__ v, long n, long i)
+{
+    if constexpr (IL) return load_il<A>(v, i);
+    else return load<A>(v, n, i);
+}
+
+template <int A, int IL>
+__device__ __forceinline__ void store_v(double *__restrict__ v, long n, long i, const Num<A> &x)
+{
+    if constexpr (IL) store_il<A>(v, i, x);
+    else store<A>(v, n, i, x);
+}
+
 // Lane-to-lane move of a whole value (wavefront of 64).
 template <int A>
 __device__ __forceinline__ Num<A> shfl_down(const Num<A> &v, int off)

@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_fill_kernel(BatchDev d, const in
         len = row_ptr[row + 1] - rs;
     }
     for (int j = 0; j < w; ++j) {
-        const int pos = b + 64 * j + lane;
+        const int pos = sell_pos(b, w, j, lane);
         if (j < len) {
             sval[pos] = val[rs + j];
             scol[pos] = col[rs + j];
@@ -120,13 +120,14 @@ __global__ void __launch_bounds__(BNT) mw_batch_spmv_kernel(BatchDev d, const do
         if constexpr (MODE == 1) {
             if (!d.active[d.slice_sys[s]]) continue;
         }
-        const Num<A> acc = sell_row_sum<A>(d.sp[s] + lane, d.sp[s + 1], d.sc, d.sv, x, d.n);
+        const int b = d.sp[s];
+        const Num<A> acc = sell_row_sum<A, MODE>(b, (d.sp[s + 1] - b) >> 6, lane, d.sc, d.sv, x, d.n);
         const bool valid = lane < d.slice_rows[s];
         const long row = (long)d.slice_row0[s] + lane;
         if (valid) store<A>(y, d.n, row, acc);
         if constexpr (MODE == 1) {
             Num<A> c = zero<A>();
-            if (valid) c = dot_step<A>(c, load<A>(x, d.n, row), acc);
+            if (valid) c = dot_step<A>(c, load_il<A>(x, row), acc);
             c = wave_sum<A>(c);
             if (lane == 0) store_scalar<A>(slots + (long)s * K, c);
         }
@@ -154,7 +155,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_init_kernel(BatchDev d, const do
             if constexpr (A == FP64) ri = promote<A>(bi.w[0] - q[i]);
             else ri = add<A>(bi, neg<A>(load<A>(q, d.n, i)));
             store<A>(r, d.n, i, ri);
-            store<A>(p, d.n, i, ri);
+            store_il<A>(p, i, ri);
             rr = dot_step<A>(rr, ri, ri);
             bb = dot_step<A>(bb, bi, bi);
         }
@@ -307,11 +308,11 @@ __global__ void __launch_bounds__(BNT) mw_batch_step_p_kernel(BatchDev d, const 
         if (lane >= d.slice_rows[s]) continue;
         const long i = (long)d.slice_row0[s] + lane;
         const Num<A> al = load_scalar<A>(d.alpha + (long)sys * K);
-        const Num<A> pi = load<A>(p, d.n, i);
+        const Num<A> pi = load_il<A>(p, i);
         store<A>(x, d.n, i, axpy_term<A>(al, pi, load<A>(x, d.n, i)));
         if (run) {
             const Num<A> be = load_scalar<A>(d.beta + (long)sys * K);
-            store<A>(p, d.n, i, axpy_term<A>(be, pi, load<A>(r, d.n, i)));
+            store_il<A>(p, i, axpy_term<A>(be, pi, load<A>(r, d.n, i)));
         }
     }
 }

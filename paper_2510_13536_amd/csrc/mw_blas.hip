@@ -118,7 +118,8 @@ __global__ void __launch_bounds__(FIN_NT) mw_reduce_slots_kernel(int nslots, con
 // in LDS (FP64: the pair (a_ij, x_j), whose accumulation is one fma); then
 // every thread adds the products of its own row that fall in the chunk, in
 // CSR order, into a register accumulator that persists across chunks.
-// MODE 1 (CG): also the partial of p^T q into slots[logical workgroup].
+// MODE 1 (CG): x is p, kept word-interleaved by the solver; also the
+// partial of p^T q into slots[logical workgroup].
 template <int A, int MODE>
 __global__ void __launch_bounds__(NT) mw_csr_spmv_kernel(int n, const int32_t *__restrict__ row_ptr,
                                                          const int32_t *__restrict__ col,
@@ -157,7 +158,7 @@ __global__ void __launch_bounds__(NT) mw_csr_spmv_kernel(int n, const int32_t *_
             const int t = (int)threadIdx.x + j * NT;
             if (t < cn) {
                 const double a = val[c0 + t];
-                const Num<A> xj = load<A>(x, n, col[c0 + t]);
+                const Num<A> xj = load_v<A, MODE>(x, n, col[c0 + t]);
                 if constexpr (A == FP64) {
                     lds[0][t] = a;
                     lds[1][t] = xj.w[0];
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(NT) mw_csr_spmv_kernel(int n, const int32_t *_
     if (row < n) store<A>(y, n, row, acc);
     if constexpr (MODE == 1) {
         Num<A> c = zero<A>();
-        if (row < n) c = dot_step<A>(c, load<A>(x, n, row), acc);
+        if (row < n) c = dot_step<A>(c, load_il<A>(x, row), acc);
         const Num<A> sum = block_sum<A, NT>(c);
         if (threadIdx.x == 0) store_scalar<A>(slots + (long)lb * K, sum);
     }
@@ -196,9 +197,10 @@ __global__ void __launch_bounds__(NT) mw_csr_spmv_kernel(int n, const int32_t *_
 //
 // Persistent workgroups of NWAVE wavefronts walk tiles of NWAVE slices
 // (xcd_tiles); wavefront w of a tile takes slice 4t + w, lane l its row
-// 64 s + l.  Entry j of that row sits at slice_ptr[s] + 64 j + l.
-// MODE 1 (CG): x is p, y is q; each thread accumulates p_i q_i over its
-// rows in tile order, and the workgroup sum goes to slots[blockIdx.x].
+// 64 s + l (entry positions: sell_row_sum).
+// MODE 1 (CG): x is p, kept word-interleaved by the solver, y is q; each
+// thread accumulates p_i q_i over its rows in tile order, and the
+// workgroup sum goes to slots[blockIdx.x].
 template <int A, int MODE>
 __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const int32_t *__restrict__ sp,
                                                           const int32_t *__restrict__ sc,
@@ -221,10 +223,11 @@ __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const i
         const int s = t * NWAVE + wave;
         if (s >= ns) continue;  // whole wavefront
         const int row = s * 64 + lane;
-        const Num<A> acc = sell_row_sum<A>(sp[s] + lane, sp[s + 1], sc, sv, x, n);
+        const int b = sp[s];
+        const Num<A> acc = sell_row_sum<A, MODE>(b, (sp[s + 1] - b) >> 6, lane, sc, sv, x, n);
         if (row < n) {
             store<A>(y, n, row, acc);
-            if constexpr (MODE == 1) part = dot_step<A>(part, load<A>(x, n, row), acc);
+            if constexpr (MODE == 1) part = dot_step<A>(part, load_il<A>(x, row), acc);
         }
     }
     if constexpr (MODE == 1) {
@@ -316,7 +319,7 @@ __global__ void __launch_bounds__(NT) mw_sell_fill_kernel(int n, int ns, const i
     const int rs = row < n ? row_ptr[row] : 0;
     const int len = row < n ? row_ptr[row + 1] - rs : 0;
     for (int j = 0; j < w; ++j) {
-        const int pos = b + 64 * j + lane;
+        const int pos = sell_pos(b, w, j, lane);
         if (j < len) {
             sval[pos] = val[rs + j];
             scol[pos] = col[rs + j];

@@ -41,30 +41,45 @@ __device__ __forceinline__ T load_matrix(const T *p)
     else return *p;
 }
 
-// Sum of one row of a SELL-64 slice: entries z0, z0 + 64, ... < z1 (the
-// lane's column of the slice), in order, from zero; padding (col < 0) is
-// skipped.  Two entries are loaded ahead of their dependent adds.
-template <int A>
-__device__ __forceinline__ Num<A> sell_row_sum(int z0, int z1, const int32_t *__restrict__ sc,
+// Sum of one row of a SELL-64 slice of width w starting at entry b, for
+// lane l.  Inside a slice the entries are stored in pairs: entries 2m and
+// 2m + 1 of lane l at b + 128 m + 2 l (+1), so one 16-byte load brings
+// two values (8 bytes two columns); an odd last entry at b + 128 (w/2) + l.
+// Every wavefront load is contiguous.  The entries are added in order
+// j = 0, 1, ..., from zero; padding (col < 0) is skipped.  x is in word
+// planes (XL = 0) or word-interleaved (XL = 1).
+typedef int ivec2 __attribute__((ext_vector_type(2)));
+
+template <int A, int XL>
+__device__ __forceinline__ Num<A> sell_row_sum(int b, int w, int lane, const int32_t *__restrict__ sc,
                                                const double *__restrict__ sv, const double *__restrict__ x, long n)
 {
     Num<A> acc = zero<A>();
-    int z = z0;
-    for (; z + 64 < z1; z += 128) {
-        const double a0 = load_matrix<A>(sv + z), a1 = load_matrix<A>(sv + z + 64);
-        const int c0 = load_matrix<A>(sc + z), c1 = load_matrix<A>(sc + z + 64);
-        const Num<A> x0 = load<A>(x, n, c0 < 0 ? 0 : c0);
-        const Num<A> x1 = load<A>(x, n, c1 < 0 ? 0 : c1);
-        if (c0 >= 0) acc = row_step<A>(acc, a0, x0);
-        if (c1 >= 0) acc = row_step<A>(acc, a1, x1);
+    const int wp = w >> 1;
+    for (int m = 0; m < wp; ++m) {
+        const int z = b + 128 * m + 2 * lane;
+        const dvec2 a = load_matrix<A>((const dvec2 *)(sv + z));
+        const ivec2 c = load_matrix<A>((const ivec2 *)(sc + z));
+        const Num<A> x0 = load_v<A, XL>(x, n, c.x < 0 ? 0 : c.x);
+        const Num<A> x1 = load_v<A, XL>(x, n, c.y < 0 ? 0 : c.y);
+        if (c.x >= 0) acc = row_step<A>(acc, a.x, x0);
+        if (c.y >= 0) acc = row_step<A>(acc, a.y, x1);
     }
-    if (z < z1) {
+    if (w & 1) {
+        const int z = b + 128 * wp + lane;
         const double a0 = load_matrix<A>(sv + z);
         const int c0 = load_matrix<A>(sc + z);
-        const Num<A> x0 = load<A>(x, n, c0 < 0 ? 0 : c0);
+        const Num<A> x0 = load_v<A, XL>(x, n, c0 < 0 ? 0 : c0);
         if (c0 >= 0) acc = row_step<A>(acc, a0, x0);
     }
     return acc;
+}
+
+// Position of entry j of lane l in a slice of width w starting at b.
+__device__ __forceinline__ int sell_pos(int b, int w, int j, int lane)
+{
+    const int wp = w >> 1;
+    return (j < 2 * wp) ? b + 128 * (j >> 1) + 2 * lane + (j & 1) : b + 128 * wp + lane;
 }
 
 // Sum over the 64 lanes of a wavefront (shuffle tree, offsets 32 .. 1);
