@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const i
                                                           const double *__restrict__ sv,
                                                           const double *__restrict__ x, double *__restrict__ y,
                                                           double *__restrict__ slots, const int32_t *__restrict__ run_prev,
-                                                          int32_t *__restrict__ run_cur)
+                                                          int32_t *__restrict__ run_cur, int rev)
 {
     constexpr int K = words(A);
     if constexpr (MODE == 1) {
@@ -217,10 +217,10 @@ __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const i
         }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const TileRange tr = xcd_tiles((ns + NWAVE - 1) / NWAVE);
+    const TileWalk tw = xcd_walk((ns + NWAVE - 1) / NWAVE, rev);
     Num<A> part = zero<A>();
-    for (int t = tr.first; t < tr.end; t += tr.step) {
-        const int s = t * NWAVE + wave;
+    for (int m = 0; m < tw.count; ++m) {
+        const int s = tw[m] * NWAVE + wave;
         if (s >= ns) continue;  // whole wavefront
         const int row = s * 64 + lane;
         const int b = sp[s];
@@ -384,17 +384,17 @@ int spmv_slots(const mw_csr_t *M, const mw_spmv_plan_t *plan)
 
 template <int A>
 int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, double *y, double *slots,
-                const int32_t *run_prev, int32_t *run_cur, int mode, hipStream_t s, int *nslots)
+                const int32_t *run_prev, int32_t *run_cur, int mode, hipStream_t s, int *nslots, int rev)
 {
     if (plan && plan->format == MW_FMT_SELL64) {
         const int ns = plan->nslices;
         const int g = persistent_grid(blocks_for(ns, NWAVE));
         if (mode == 0)
             hipLaunchKernelGGL((mw_sell_spmv_kernel<A, 0>), dim3(g), dim3(NT), 0, s, M->n, ns, plan->slice_ptr,
-                               plan->col, plan->val, x, y, slots, run_prev, run_cur);
+                               plan->col, plan->val, x, y, slots, run_prev, run_cur, rev);
         else
             hipLaunchKernelGGL((mw_sell_spmv_kernel<A, 1>), dim3(g), dim3(NT), 0, s, M->n, ns, plan->slice_ptr,
-                               plan->col, plan->val, x, y, slots, run_prev, run_cur);
+                               plan->col, plan->val, x, y, slots, run_prev, run_cur, rev);
         if (nslots) *nslots = g;
     } else {
         const int nb = blocks_for(M->n, NT);
@@ -411,15 +411,15 @@ int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, 
 }
 
 template int spmv_launch<FP64>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                               const int32_t *, int32_t *, int, hipStream_t, int *);
+                               const int32_t *, int32_t *, int, hipStream_t, int *, int);
 template int spmv_launch<DW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                             const int32_t *, int32_t *, int, hipStream_t, int *);
+                             const int32_t *, int32_t *, int, hipStream_t, int *, int);
 template int spmv_launch<QDW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                              const int32_t *, int32_t *, int, hipStream_t, int *);
+                              const int32_t *, int32_t *, int, hipStream_t, int *, int);
 template int spmv_launch<TW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                             const int32_t *, int32_t *, int, hipStream_t, int *);
+                             const int32_t *, int32_t *, int, hipStream_t, int *, int);
 template int spmv_launch<QTW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                              const int32_t *, int32_t *, int, hipStream_t, int *);
+                              const int32_t *, int32_t *, int, hipStream_t, int *, int);
 
 size_t plan_bytes(int32_t n, int32_t nnz) { return plan_layout(n, nnz).bytes; }
 

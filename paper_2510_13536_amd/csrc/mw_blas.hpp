@@ -113,10 +113,12 @@ int spmv_max_slots(int32_t n);
 // y = A x.  plan == nullptr or plan->format == MW_FMT_CSR: CSR kernel on M;
 // else the SELL-64 kernel.  mode 1 (CG): x is p, y is q, the workgroup
 // partials of p^T q go to `slots` (their count to *nslots); the launch does
-// nothing but pass the stop on (*run_cur = 0) when *run_prev is 0.
+// nothing but pass the stop on (*run_cur = 0) when *run_prev is 0.  rev:
+// walk the tiles backwards (see xcd_walk).
 template <int A>
 int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, double *y, double *slots,
-                const int32_t *run_prev, int32_t *run_cur, int mode, hipStream_t s, int *nslots = nullptr);
+                const int32_t *run_prev, int32_t *run_cur, int mode, hipStream_t s, int *nslots = nullptr,
+                int rev = 0);
 
 // Number of slots a CG-mode SpMV launch writes (see spmv_launch).
 int spmv_slots(const mw_csr_t *M, const mw_spmv_plan_t *plan);

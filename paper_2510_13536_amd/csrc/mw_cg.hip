@@ -131,7 +131,7 @@ template <int A, int UNT>
 __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in, const double *__restrict__ slots_in,
                                                            const double *__restrict__ q, double *__restrict__ r,
                                                            double *__restrict__ slots_out, CgState *__restrict__ st,
-                                                           int par)
+                                                           int par, int rev)
 {
     constexpr int K = words(A);
     __shared__ Num<A> s_alpha;
@@ -167,10 +167,10 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
     if (s_brk) return;
     const Num<A> al = s_alpha;
     const bool norm = is_quasi(A) && st->normalize;
-    const TileRange tr = xcd_tiles((n + UNT - 1) / UNT);
+    const TileWalk tw = xcd_walk((n + UNT - 1) / UNT, rev);
     Num<A> rr = zero<A>();
-    for (int t = tr.first; t < tr.end; t += tr.step) {
-        const long i = (long)t * UNT + threadIdx.x;
+    for (int m = 0; m < tw.count; ++m) {
+        const long i = (long)tw[m] * UNT + threadIdx.x;
         if (i >= n) continue;
         Num<A> ri = axmy_term<A>(al, load<A>(q, n, i), load<A>(r, n, i));
         if (norm) ri = normalise<A>(ri);
@@ -188,7 +188,8 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
 template <int A, int UNT>
 __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in, const double *__restrict__ slots_in,
                                                            const double *__restrict__ r, double *__restrict__ p,
-                                                           double *__restrict__ x, CgState *__restrict__ st, int par)
+                                                           double *__restrict__ x, CgState *__restrict__ st, int par,
+                                                           int rev)
 {
     __shared__ Num<A> s_beta;
     __shared__ int s_stop;
@@ -225,9 +226,9 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
     const bool stop = s_stop;
     const Num<A> be = s_beta;
     const Num<A> al = load_scalar<A>(st->alpha[par]);
-    const TileRange tr = xcd_tiles((n + UNT - 1) / UNT);
-    for (int t = tr.first; t < tr.end; t += tr.step) {
-        const long i = (long)t * UNT + threadIdx.x;
+    const TileWalk tw = xcd_walk((n + UNT - 1) / UNT, rev);
+    for (int m = 0; m < tw.count; ++m) {
+        const long i = (long)tw[m] * UNT + threadIdx.x;
         if (i >= n) continue;
         const Num<A> pi = load_il<A>(p, i);
         store<A>(x, n, i, axpy_term<A>(al, pi, load<A>(x, n, i)));
@@ -329,12 +330,13 @@ template <int A, int UNT>
 void launch_steps(const ChunkArgs &c, int k, int par, hipStream_t s)
 {
     const int gu = c.nslots_up;
+    // consecutive kernels walk the rows in opposite directions
     if (k == 1)
         hipLaunchKernelGGL((mw_cg_step_r_kernel<A, UNT>), dim3(gu), dim3(UNT), 0, s, c.n, c.nslots_sp, c.slots_a, c.q,
-                           c.r, c.slots_b, c.st, par);
+                           c.r, c.slots_b, c.st, par, par ^ 1);
     else
         hipLaunchKernelGGL((mw_cg_step_p_kernel<A, UNT>), dim3(gu), dim3(UNT), 0, s, c.n, c.nslots_up, c.slots_b, c.r,
-                           c.p, c.x, c.st, par);
+                           c.p, c.x, c.st, par, par);
 }
 
 template <int A>
@@ -347,7 +349,7 @@ int enqueue_chunk(const ChunkArgs &c, EventPool *ev, hipStream_t s)
             if (timed) HIP_TRY(hipEventRecord(ev->e[(it * NKERN + k) * 2], s));
             if (k == 0) {
                 const int rc = spmv_launch<A>(c.M, c.plan, c.p, c.q, c.slots_a, &c.st->run[par ^ 1], &c.st->run[par],
-                                              1, s);
+                                              1, s, nullptr, par);
                 if (rc) return rc;
             } else if (c.unt == 1024) {
                 launch_steps<A, 1024>(c, k, par, s);

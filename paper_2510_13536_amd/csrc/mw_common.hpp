@@ -41,6 +41,25 @@ __device__ __forceinline__ TileRange xcd_tiles(int ntiles)
     return TileRange{t0 + j, t1, nbx};
 }
 
+// The m-th tile of the range, walking the XCD's part forwards (rev = 0) or
+// backwards (rev = 1).  Consecutive kernels that walk in opposite
+// directions start on the rows the previous kernel touched last, which are
+// the most likely to still be in the Infinity Cache.
+struct TileWalk {
+    int base, count, step, rev;
+    __device__ __forceinline__ int operator[](int m) const { return rev ? base - m * step : base + m * step; }
+};
+
+__device__ __forceinline__ TileWalk xcd_walk(int ntiles, int rev)
+{
+    const TileRange r = xcd_tiles(ntiles);
+    const int t0 = r.first - (int)(blockIdx.x / NXCD);  // first tile of the XCD's part
+    const int len = r.end - t0;
+    const int j = (int)(blockIdx.x / NXCD);
+    const int count = (j < len) ? (len - j + r.step - 1) / r.step : 0;
+    return TileWalk{rev ? r.end - 1 - j : r.first, count, r.step, rev};
+}
+
 // Grid size of a persistent streaming kernel over ntiles tiles.
 inline int persistent_grid(long ntiles)
 {
