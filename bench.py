@@ -2,17 +2,22 @@
 Poisson problem 128^3 (n = 2,097,152, nnz = 14,581,760), one MI355X.
 
 One step = one complete CG solve (x0 = 0, QTW arithmetic, tol 1e-12) with
-the matrix, b and workspace already resident in HBM.  The JSON line adds:
-  roofline      the dominant kernel (the CG-mode SpMV) measured live with
-                HIP events around each of its launches during the timed
-                steps; algorithmic bytes per launch
+the matrix, b and workspace already resident in HBM, run the way a caller
+runs it (iteration chunks replayed from a captured hipGraph).  The JSON line
+adds:
+  roofline      the dominant kernel (the CG-mode SpMV): HIP events around
+                each of its launches on the solver's stream, over solves
+                run right after the timed steps with the same kernels
+                launched directly (events recorded inside a replayed graph
+                cannot be read back); algorithmic bytes per launch
                 12 nnz + 4 (n + 1) + 16 k n (k = 3 words);
   cpu_baseline  the CPU oracle on this host, timed on a bounded sample (a
                 few CG iterations of the same solve), scaled to the solve's
                 iteration count;
   extra         SpMV GB/s for every arithmetic (MALL flushed between
                 repetitions), time to solution of every arithmetic, the
-                QTW / DW time ratio, per-kernel times.
+                QTW / DW time ratio, per-kernel times, the batched and
+                adjoint workloads.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
 import argparse
@@ -36,14 +41,14 @@ def spmv_bytes(n, nnz, k):
 
 
 def kernel_source_hash():
-    """Hash of the HIP sources and the ABI header: stored traffic figures
-    are reported only while the kernels are the ones that were profiled."""
+    """Hash of the sources the SpMV kernel is compiled from (its file, the
+    headers it includes, the ABI header): stored traffic figures are
+    reported only while the kernel is the one that was profiled."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2510_13536_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in ("mw_arith.hpp", "mw_common.hpp", "mw_blas.hpp", "mw_blas.hip"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     h.update(open(os.path.join(ROOT, "include", "mw.h"), "rb").read())
     return h.hexdigest()[:16]
 
@@ -148,6 +153,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the per-arithmetic extras")
     ap.add_argument("--cpu-iters", type=int, default=16)
+    ap.add_argument("--prof-steps", type=int, default=2, help="event-timed solves for the roofline")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -187,13 +193,12 @@ def main():
         log("warmup solve: %s" % info)
     torch.cuda.synchronize()
 
-    prof = mw.CgProf.of("spmv")
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         x.zero_()
-        _, info = mw.cg_solve(arith, Ad, bd, x=x, tol=tol, maxit=maxit, workspace=ws, prof=prof)
+        _, info = mw.cg_solve(arith, Ad, bd, x=x, tol=tol, maxit=maxit, workspace=ws)
         infos.append(info)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -202,6 +207,19 @@ def main():
     assert all(i["status"] == "ok" for i in infos), infos
     log("timed: %.2f ms/solve, %d iterations, device %.2f ms" % (ms_per_step, iters, 1e3 * infos[-1]["seconds"]))
 
+    # kernel durations: the same solve with HIP events around every SpMV
+    prof = mw.CgProf.of("spmv")
+    pinfos = []
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for _ in range(args.prof_steps):
+        x.zero_()
+        _, info = mw.cg_solve(arith, Ad, bd, x=x, tol=tol, maxit=maxit, workspace=ws, prof=prof)
+        pinfos.append(info)
+    torch.cuda.synchronize()
+    prof_ms = 1e3 * (time.perf_counter() - p0) / max(args.prof_steps, 1)
+    assert all(i["status"] == "ok" and i["iters"] == iters for i in pinfos), pinfos
+
     pd = prof.as_dict()
     sp_us = pd["spmv"]["avg_us"]
     sp_bytes = spmv_bytes(A.n, A.nnz, k)
@@ -209,11 +227,18 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic("mw_sell_spmv_kernel<4, 1>"),
                 "kernel": "mw_sell_spmv_kernel<QTW, CG mode>", "bytes_per_launch": sp_bytes,
-                "avg_launch_us": round(sp_us, 2), "launches": pd["spmv"]["launches"]}
+                "avg_launch_us": round(sp_us, 2), "launches": pd["spmv"]["launches"],
+                "timing": "HIP events around each SpMV launch on the solver stream, %d event-timed solves "
+                          "(direct launches, %.2f ms/solve) right after the timed steps" % (args.prof_steps, prof_ms)}
 
     extra = {"iterations": iters, "device_seconds": infos[-1]["seconds"],
              "per_iteration_us": 1e3 * ms_per_step / max(iters, 1),
-             "kernel_avg_us": {c: (round(v["avg_us"], 2) if v["avg_us"] else None) for c, v in pd.items()}}
+             "event_timed_ms_per_step": round(prof_ms, 3)}
+    # every kernel class event-timed, one more solve
+    pall = mw.CgProf()
+    x.zero_()
+    mw.cg_solve(arith, Ad, bd, x=x, tol=tol, maxit=maxit, workspace=ws, prof=pall)
+    extra["kernel_avg_us"] = {c: (round(v["avg_us"], 2) if v["avg_us"] else None) for c, v in pall.as_dict().items()}
 
     if not args.quick:
         # Standalone SpMV bandwidth for every arithmetic, planned (SELL-64)

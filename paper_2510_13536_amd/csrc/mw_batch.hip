@@ -61,7 +61,7 @@ __device__ __forceinline__ TileRange slice_tiles(int ns) { return xcd_tiles((ns 
 __global__ void __launch_bounds__(BNT) mw_batch_width_kernel(BatchDev d, const int32_t *__restrict__ row_ptr,
                                                              int32_t *__restrict__ width)
 {
-    const int s = blockIdx.x * NWAVE + (threadIdx.x >> 6);
+    const int s = blockIdx.x * NWAVE + wave_id();
     const int lane = threadIdx.x & 63;
     if (s >= d.ns) return;
     int len = 0;
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_fill_kernel(BatchDev d, const in
                                                             const int32_t *__restrict__ slice_ptr,
                                                             int32_t *__restrict__ scol, double *__restrict__ sval)
 {
-    const int s = blockIdx.x * NWAVE + (threadIdx.x >> 6);
+    const int s = blockIdx.x * NWAVE + wave_id();
     const int lane = threadIdx.x & 63;
     if (s >= d.ns) return;
     const int b = slice_ptr[s];
@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_spmv_kernel(BatchDev d, const do
                                                             double *__restrict__ y, double *__restrict__ slots)
 {
     constexpr int K = words(A);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const TileRange tr = slice_tiles(d.ns);
     for (int t = tr.first; t < tr.end; t += tr.step) {
         const int s = t * NWAVE + wave;
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_init_kernel(BatchDev d, const do
                                                             double *__restrict__ slots_bb)
 {
     constexpr int K = words(A);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const TileRange tr = slice_tiles(d.ns);
     for (int t = tr.first; t < tr.end; t += tr.step) {
         const int s = t * NWAVE + wave;
@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_step_r_kernel(BatchDev d, const 
                                                               double *__restrict__ r, double *__restrict__ slots)
 {
     constexpr int K = words(A);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const bool norm = is_quasi(A) && *d.normalize;
     const TileRange tr = slice_tiles(d.ns);
     for (int t = tr.first; t < tr.end; t += tr.step) {
@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_step_p_kernel(BatchDev d, const 
                                                               double *__restrict__ p, double *__restrict__ x)
 {
     constexpr int K = words(A);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const TileRange tr = slice_tiles(d.ns);
     for (int t = tr.first; t < tr.end; t += tr.step) {
         const int s = t * NWAVE + wave;

@@ -19,6 +19,8 @@
 // bit-identical to that definition, whatever the launch shape.
 #include "mw_blas.hpp"
 
+#include <cstdlib>
+
 #include <cstring>
 
 using namespace mwk;
@@ -216,7 +218,7 @@ __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const i
             return;
         }
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const TileWalk tw = xcd_walk((ns + NWAVE - 1) / NWAVE, rev);
     Num<A> part = zero<A>();
     for (int m = 0; m < tw.count; ++m) {
@@ -260,7 +262,7 @@ __global__ void __launch_bounds__(NT) mw_csr_grad_kernel(int n, const int32_t *_
 __global__ void __launch_bounds__(NT) mw_sell_width_kernel(int n, int ns, const int32_t *__restrict__ row_ptr,
                                                            int32_t *__restrict__ width)
 {
-    const int s = blockIdx.x * NWAVE + (threadIdx.x >> 6);
+    const int s = blockIdx.x * NWAVE + wave_id();
     const int lane = threadIdx.x & 63;
     if (s >= ns) return;
     const int row = s * 64 + lane;
@@ -310,7 +312,7 @@ __global__ void __launch_bounds__(NT) mw_sell_fill_kernel(int n, int ns, const i
                                                           const int32_t *__restrict__ slice_ptr,
                                                           int32_t *__restrict__ scol, double *__restrict__ sval)
 {
-    const int s = blockIdx.x * NWAVE + (threadIdx.x >> 6);
+    const int s = blockIdx.x * NWAVE + wave_id();
     const int lane = threadIdx.x & 63;
     if (s >= ns) return;
     const int row = s * 64 + lane;
@@ -376,34 +378,50 @@ int spmv_max_slots(int32_t n)
     return csr > MAX_GRID ? csr : MAX_GRID;
 }
 
-int spmv_slots(const mw_csr_t *M, const mw_spmv_plan_t *plan)
+// Workgroups of the SELL SpMV.  QTW runs best with six resident
+// wavefronts per SIMD (1536 workgroups of four), the other arithmetics
+// with eight (2048), swept on MI355X for 3D Poisson 128^3 over 512..2048;
+// MW_SGRID overrides (8 .. MAX_GRID).
+int sell_grid(int a, int ns)
 {
-    if (plan && plan->format == MW_FMT_SELL64) return persistent_grid(blocks_for(plan->nslices, NWAVE));
+    int cap = (a == MW_QTW) ? 1536 : MAX_GRID;
+    if (const char *e = getenv("MW_SGRID")) {
+        const int v = atoi(e);
+        if (v >= 8 && v <= MAX_GRID) cap = v;
+    }
+    const int g = persistent_grid(blocks_for(ns, NWAVE));
+    return g < cap ? g : cap;
+}
+
+int spmv_slots(int a, const mw_csr_t *M, const mw_spmv_plan_t *plan)
+{
+    if (plan && plan->format == MW_FMT_SELL64) return sell_grid(a, plan->nslices);
     return blocks_for(M->n, NT);
 }
 
 template <int A>
 int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, double *y, double *slots,
-                const int32_t *run_prev, int32_t *run_cur, int mode, hipStream_t s, int *nslots, int rev)
+                const int32_t *run_prev, int32_t *run_cur, int mode, hipStream_t s, int *nslots, int rev,
+                hipEvent_t ev0, hipEvent_t ev1)
 {
     if (plan && plan->format == MW_FMT_SELL64) {
         const int ns = plan->nslices;
-        const int g = persistent_grid(blocks_for(ns, NWAVE));
+        const int g = sell_grid(A, ns);
         if (mode == 0)
-            hipLaunchKernelGGL((mw_sell_spmv_kernel<A, 0>), dim3(g), dim3(NT), 0, s, M->n, ns, plan->slice_ptr,
-                               plan->col, plan->val, x, y, slots, run_prev, run_cur, rev);
+            MW_LAUNCH((mw_sell_spmv_kernel<A, 0>), dim3(g), dim3(NT), s, ev0, ev1, M->n, ns, plan->slice_ptr,
+                      plan->col, plan->val, x, y, slots, run_prev, run_cur, rev);
         else
-            hipLaunchKernelGGL((mw_sell_spmv_kernel<A, 1>), dim3(g), dim3(NT), 0, s, M->n, ns, plan->slice_ptr,
-                               plan->col, plan->val, x, y, slots, run_prev, run_cur, rev);
+            MW_LAUNCH((mw_sell_spmv_kernel<A, 1>), dim3(g), dim3(NT), s, ev0, ev1, M->n, ns, plan->slice_ptr,
+                      plan->col, plan->val, x, y, slots, run_prev, run_cur, rev);
         if (nslots) *nslots = g;
     } else {
         const int nb = blocks_for(M->n, NT);
         if (mode == 0)
-            hipLaunchKernelGGL((mw_csr_spmv_kernel<A, 0>), dim3(nb), dim3(NT), 0, s, M->n, M->row_ptr, M->col_idx,
-                               M->val, x, y, slots, run_prev, run_cur);
+            MW_LAUNCH((mw_csr_spmv_kernel<A, 0>), dim3(nb), dim3(NT), s, ev0, ev1, M->n, M->row_ptr, M->col_idx,
+                      M->val, x, y, slots, run_prev, run_cur);
         else
-            hipLaunchKernelGGL((mw_csr_spmv_kernel<A, 1>), dim3(nb), dim3(NT), 0, s, M->n, M->row_ptr, M->col_idx,
-                               M->val, x, y, slots, run_prev, run_cur);
+            MW_LAUNCH((mw_csr_spmv_kernel<A, 1>), dim3(nb), dim3(NT), s, ev0, ev1, M->n, M->row_ptr, M->col_idx,
+                      M->val, x, y, slots, run_prev, run_cur);
         if (nslots) *nslots = nb;
     }
     HIP_TRY(hipGetLastError());
@@ -411,15 +429,15 @@ int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, 
 }
 
 template int spmv_launch<FP64>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                               const int32_t *, int32_t *, int, hipStream_t, int *, int);
+                               const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t);
 template int spmv_launch<DW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                             const int32_t *, int32_t *, int, hipStream_t, int *, int);
+                             const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t);
 template int spmv_launch<QDW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                              const int32_t *, int32_t *, int, hipStream_t, int *, int);
+                              const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t);
 template int spmv_launch<TW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                             const int32_t *, int32_t *, int, hipStream_t, int *, int);
+                             const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t);
 template int spmv_launch<QTW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                              const int32_t *, int32_t *, int, hipStream_t, int *, int);
+                              const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t);
 
 size_t plan_bytes(int32_t n, int32_t nnz) { return plan_layout(n, nnz).bytes; }
 

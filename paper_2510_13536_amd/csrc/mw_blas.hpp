@@ -114,13 +114,17 @@ int spmv_max_slots(int32_t n);
 // else the SELL-64 kernel.  mode 1 (CG): x is p, y is q, the workgroup
 // partials of p^T q go to `slots` (their count to *nslots); the launch does
 // nothing but pass the stop on (*run_cur = 0) when *run_prev is 0.  rev:
-// walk the tiles backwards (see xcd_walk).
+// walk the tiles backwards (see xcd_walk).  ev0/ev1: optional events that
+// time the kernel (MW_LAUNCH).
 template <int A>
 int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, double *y, double *slots,
                 const int32_t *run_prev, int32_t *run_cur, int mode, hipStream_t s, int *nslots = nullptr,
-                int rev = 0);
+                int rev = 0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// Workgroups of a SELL SpMV launch in arithmetic a over ns slices.
+int sell_grid(int a, int ns);
 
 // Number of slots a CG-mode SpMV launch writes (see spmv_launch).
-int spmv_slots(const mw_csr_t *M, const mw_spmv_plan_t *plan);
+int spmv_slots(int a, const mw_csr_t *M, const mw_spmv_plan_t *plan);
 
 }  // namespace mwh

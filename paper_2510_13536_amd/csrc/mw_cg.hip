@@ -325,18 +325,18 @@ bool same_key(const ChunkArgs &a, const ChunkArgs &b)
 
 // Enqueues one chunk (even length; iteration j of the chunk has parity
 // (j + 1) & 1, since chunks start after an even number of iterations).
-// With a mask, records events around the timed classes.
+// With a mask, the kernels of the timed classes carry a pair of events.
 template <int A, int UNT>
-void launch_steps(const ChunkArgs &c, int k, int par, hipStream_t s)
+void launch_steps(const ChunkArgs &c, int k, int par, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const int gu = c.nslots_up;
     // consecutive kernels walk the rows in opposite directions
     if (k == 1)
-        hipLaunchKernelGGL((mw_cg_step_r_kernel<A, UNT>), dim3(gu), dim3(UNT), 0, s, c.n, c.nslots_sp, c.slots_a, c.q,
-                           c.r, c.slots_b, c.st, par, par ^ 1);
+        MW_LAUNCH((mw_cg_step_r_kernel<A, UNT>), dim3(gu), dim3(UNT), s, e0, e1, c.n, c.nslots_sp, c.slots_a, c.q,
+                  c.r, c.slots_b, c.st, par, par ^ 1);
     else
-        hipLaunchKernelGGL((mw_cg_step_p_kernel<A, UNT>), dim3(gu), dim3(UNT), 0, s, c.n, c.nslots_up, c.slots_b, c.r,
-                           c.p, c.x, c.st, par, par);
+        MW_LAUNCH((mw_cg_step_p_kernel<A, UNT>), dim3(gu), dim3(UNT), s, e0, e1, c.n, c.nslots_up, c.slots_b, c.r,
+                  c.p, c.x, c.st, par, par);
 }
 
 template <int A>
@@ -346,19 +346,19 @@ int enqueue_chunk(const ChunkArgs &c, EventPool *ev, hipStream_t s)
         const int par = (it + 1) & 1;
         for (int k = 0; k < NKERN; ++k) {
             const bool timed = ev && (c.timed_mask & (1 << KCLASS[k]));
-            if (timed) HIP_TRY(hipEventRecord(ev->e[(it * NKERN + k) * 2], s));
+            hipEvent_t e0 = timed ? ev->e[(it * NKERN + k) * 2] : nullptr;
+            hipEvent_t e1 = timed ? ev->e[(it * NKERN + k) * 2 + 1] : nullptr;
             if (k == 0) {
                 const int rc = spmv_launch<A>(c.M, c.plan, c.p, c.q, c.slots_a, &c.st->run[par ^ 1], &c.st->run[par],
-                                              1, s, nullptr, par);
+                                              1, s, nullptr, par, e0, e1);
                 if (rc) return rc;
             } else if (c.unt == 1024) {
-                launch_steps<A, 1024>(c, k, par, s);
+                launch_steps<A, 1024>(c, k, par, s, e0, e1);
             } else if (c.unt == 512) {
-                launch_steps<A, 512>(c, k, par, s);
+                launch_steps<A, 512>(c, k, par, s, e0, e1);
             } else {
-                launch_steps<A, 256>(c, k, par, s);
+                launch_steps<A, 256>(c, k, par, s, e0, e1);
             }
-            if (timed) HIP_TRY(hipEventRecord(ev->e[(it * NKERN + k) * 2 + 1], s));
         }
     }
     HIP_TRY(hipGetLastError());
@@ -468,7 +468,7 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     const UpdateShape us = update_shape(A);
     c.unt = us.unt;
     c.ugrid = us.ugrid;
-    c.nslots_sp = spmv_slots(M, plan);
+    c.nslots_sp = spmv_slots(A, M, plan);
     c.nslots_up = update_grid(n, us);
 
     if (!fl->stopped) {

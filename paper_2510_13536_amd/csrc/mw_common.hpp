@@ -2,6 +2,7 @@
 // the libmwcg kernels (gfx950, wave64).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -59,6 +60,11 @@ __device__ __forceinline__ TileWalk xcd_walk(int ntiles, int rev)
     const int count = (j < len) ? (len - j + r.step - 1) / r.step : 0;
     return TileWalk{rev ? r.end - 1 - j : r.first, count, r.step, rev};
 }
+
+// Index of the calling wavefront inside its workgroup, as a wave-uniform
+// (scalar) value, so per-slice bounds are scalar loads and loops over a
+// slice are scalar loops.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Grid size of a persistent streaming kernel over ntiles tiles.
 inline int persistent_grid(long ntiles)
@@ -163,6 +169,15 @@ inline bool valid_csr(const mw_csr_t *A)
     do {                                                           \
         hipError_t e_ = (call);                                    \
         if (e_ != hipSuccess) return mwh::hip_fail(e_, #call);     \
+    } while (0)
+
+// Kernel launch; given a pair of events, they are attached to the dispatch
+// itself (hipExtLaunchKernelGGL), so their elapsed time is the kernel's
+// execution alone.
+#define MW_LAUNCH(kern, grid, block, stream, ev0, ev1, ...)                                  \
+    do {                                                                                       \
+        if (ev0) hipExtLaunchKernelGGL(kern, grid, block, 0, stream, ev0, ev1, 0, __VA_ARGS__); \
+        else hipLaunchKernelGGL(kern, grid, block, 0, stream, __VA_ARGS__);                     \
     } while (0)
 
 #define MW_DISPATCH(a, fn, ...)                          \
