@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 METRIC = "QTW CG time-to-1e-12 residual & SpMV HBM GB/s; batched/adjoint vs plain"
 HBM_PEAK_GBS = 8000.0
 WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3}
+ARITH_CODE = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4}
 
 
 def spmv_bytes(n, nnz, k):
@@ -109,6 +110,47 @@ def bench_batched(mw, P, torch, dev, nsys=512):
     return out
 
 
+def bench_illcond(mw, P, torch, dev, maxit=20000):
+    """Ill-conditioned banded SPD (n = 2^20, 27 nnz/row, D A D scaled):
+    planned SpMV GB/s (Infinity Cache read-flushed) and a CG run of at most
+    `maxit` iterations toward 1e-10 in FP64, DW and QTW (relative residual
+    reached, time per iteration)."""
+    A, b, _ = P.case_banded_illcond()
+    Ad = mw.DeviceCSR.from_host(A, dev)
+    bd = torch.as_tensor(b, device=dev)
+    plan = mw.Plan(Ad)
+    flush = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    out = {"workload": "banded SPD offsets +-1..13, D A D (D_ii = 10^U(-3,3)), n=%d, nnz=%d, tol 1e-10, "
+                       "at most %d iterations" % (A.n, A.nnz, maxit)}
+    for ar in ("fp64", "dw", "qtw"):
+        kk = WORDS[ar]
+        xv = torch.rand((kk, A.n), dtype=torch.float64, device=dev)
+        yv = torch.empty_like(xv)
+        ts = []
+        for rep in range(8):
+            sink.copy_(flush.sum().reshape(1))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            mw.spmv_planned(ar, plan, xv, yv)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep >= 2:
+                ts.append(e0.elapsed_time(e1))
+        gbs = spmv_bytes(A.n, A.nnz, kk) / (statistics.median(ts) * 1e-3) / 1e9
+        x = torch.zeros((kk, A.n), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = mw.cg_solve(ar, Ad, bd, x=x, tol=1e-10, maxit=maxit)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[ar] = {"spmv_GBps_planned_flushed": round(gbs, 1), "iters": info["iters"], "status": info["status"],
+                   "rel_res": info["rel_res"], "seconds": round(sec, 3),
+                   "per_iteration_us": round(1e6 * sec / max(info["iters"], 1), 1)}
+        log("ill-conditioned %s: %s" % (ar, out[ar]))
+    return out
+
+
 def bench_adjoint(mw, P, torch, dev):
     """A(theta) = 3D Laplacian 100^3 + diag(theta), loss 0.5||x - x_t||^2,
     QTW: forward + adjoint solve (all 2n gradient entries) vs the cost of
@@ -152,6 +194,8 @@ def main():
     ap.add_argument("--nx", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the per-arithmetic extras")
+    ap.add_argument("--arith", default="qtw", choices=sorted(WORDS),
+                    help="arithmetic of the timed solve (the headline metric is QTW)")
     ap.add_argument("--cpu-iters", type=int, default=16)
     ap.add_argument("--prof-steps", type=int, default=2, help="event-timed solves for the roofline")
     ap.add_argument("--calib-copy", action="store_true",
@@ -180,7 +224,7 @@ def main():
     log("problem: 3D Poisson %d^3 n=%d nnz=%d (%.1fs)" % (args.nx, A.n, A.nnz, time.time() - t))
     Ad = mw.DeviceCSR.from_host(A, dev)
     bd = torch.as_tensor(b, device=dev)
-    arith = "qtw"
+    arith = args.arith
     k = WORDS[arith]
     tol = 1e-12
     maxit = 10 * A.n
@@ -225,8 +269,8 @@ def main():
     sp_bytes = spmv_bytes(A.n, A.nnz, k)
     achieved = sp_bytes / (sp_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic("mw_sell_spmv_kernel<4, 1>"),
-                "kernel": "mw_sell_spmv_kernel<QTW, CG mode>", "bytes_per_launch": sp_bytes,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic("mw_sell_spmv_kernel<%d, 1>" % ARITH_CODE[arith]),
+                "kernel": "mw_sell_spmv_kernel<%s, CG mode>" % arith.upper(), "bytes_per_launch": sp_bytes,
                 "avg_launch_us": round(sp_us, 2), "launches": pd["spmv"]["launches"],
                 "timing": "HIP events around each SpMV launch on the solver stream, %d event-timed solves "
                           "(direct launches, %.2f ms/solve) right after the timed steps" % (args.prof_steps, prof_ms)}
@@ -289,6 +333,7 @@ def main():
     if not args.quick:
         extra["batched"] = bench_batched(mw, P, torch, dev)
         extra["adjoint"] = bench_adjoint(mw, P, torch, dev)
+        extra["illcond"] = bench_illcond(mw, P, torch, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -303,9 +348,9 @@ def main():
         setup = max((s1 - s0) - 2 * per_iter, 0.0)
         cpu = {"value": round(setup + per_iter * iters, 2), "unit": "s", "cores": O.num_threads(),
                "kind": "oracle",
-               "sample": "%d QTW CG iterations of the same 128^3 solve (difference of maxit=%d and maxit=2 runs); "
+               "sample": "%d %s CG iterations of the same %d^3 solve (difference of maxit=%d and maxit=2 runs); "
                          "per-iteration time %.3f s x the GPU solve's %d iterations plus setup (extrapolated)"
-                         % (ci, 2 + ci, per_iter, iters)}
+                         % (ci, arith.upper(), args.nx, 2 + ci, per_iter, iters)}
         log("cpu baseline: %s" % cpu)
 
     out = {"metric": METRIC, "value": round(ms_per_step / 1e3, 5), "unit": "s", "n_gpus": 1,
@@ -313,7 +358,7 @@ def main():
            "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": "3D 7-point Poisson %d^3 (n=%d, nnz=%d), FP64 CSR int32, x_true~U[-1,1] seed 2, "
-                                  "b=A x_true; QTW CG from x0=0 to ||r||/||b||<1e-12" % (args.nx, A.n, A.nnz),
+                                  "b=A x_true; %s CG from x0=0 to ||r||/||b||<1e-12" % (args.nx, A.n, A.nnz, arith.upper()),
                       "arith": arith, "tol": tol, "n": A.n, "nnz": A.nnz},
            "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     print(json.dumps(out), flush=True)
