@@ -94,15 +94,27 @@ enum {
 };
 
 /* A SpMV plan (host struct; the arrays it points to live in the caller's
- * plan buffer in device memory, plus the caller's CSR arrays). */
+ * plan buffer in device memory, plus the caller's CSR arrays).  SELL64
+ * storage is counted in 64-entry slots: slice s owns slots
+ * slice_ptr[s] / 64 .. slice_ptr[s + 1] / 64 - 1, one per entry of its
+ * longest row. */
 typedef struct {
     int32_t n, nnz;
     int32_t format;             /* MW_FMT_SELL64, or MW_FMT_CSR as fallback    */
     int32_t nslices;            /* ceil(n / 64)                               */
     int64_t stored;             /* SELL64: entries stored, padding included    */
-    const int32_t *slice_ptr;   /* SELL64: nslices + 1 offsets                */
-    const int32_t *col;         /* SELL64: column of each entry, -1 = padding  */
-    const double *val;          /* SELL64: value of each entry                 */
+    const int32_t *slice_ptr;   /* SELL64: nslices + 1 offsets (entries)      */
+    const int32_t *col;         /* SELL64: column of each entry of an explicit-
+                                   column slice, -1 = padding (unused entries
+                                   of diagonal-slot slices are unspecified)   */
+    const double *val;          /* SELL64: value of each entry (0 = padding)   */
+    const int32_t *slot_off;    /* SELL64: per slot of a diagonal-slot slice,
+                                   the column offset (column - row) it holds  */
+    const uint64_t *slot_mask;  /* SELL64: per slot, bit l set when row
+                                   64 s + l has an entry in that slot; 0 for
+                                   every slot of an explicit-column slice     */
+    int32_t ndiag;              /* SELL64: slices stored as diagonal slots    */
+    int32_t reserved;
     mw_csr_t csr;               /* the source matrix                          */
 } mw_spmv_plan_t;
 
@@ -221,12 +233,18 @@ size_t mw_spmv_plan_bytes(int32_t n, int32_t nnz);
 
 /*
  * Re-lays A out for the GPU (a set-up step, not part of the paper's
- * method): slices of 64 consecutive rows, one per wavefront, each slice
- * padded to its longest row and stored column-major (entry j of row
- * 64 s + l at slice_ptr[s] + 64 j + l), so that each lane owns one row and
- * every wavefront load of values or column indices is contiguous.  The row
- * contents and their order are kept, so products computed from the plan
- * are bit-identical to those from the CSR arrays.  When the padding would
+ * method): slices of 64 consecutive rows, one per wavefront, each lane
+ * owning one row; each slice is padded to its longest row, width w.
+ * Entries j = 2m and 2m + 1 of row 64 s + l are stored at
+ * slice_ptr[s] + 128 m + 2 l (+1), an odd last entry (j = w - 1) at
+ * slice_ptr[s] + 128 (w / 2) + l, so every wavefront load is contiguous and
+ * each lane reads two entries per 16-byte load.  A slice whose rows can be
+ * assigned, each in its own CSR order, to w slots that each hold one
+ * column offset (column - row) for all its rows is stored as diagonal
+ * slots: values only, plus slot_off / slot_mask per slot (stencil and
+ * banded slices); other slices keep explicit columns.  Row contents and
+ * their order are kept, so products computed from the plan are
+ * bit-identical to those from the CSR arrays.  When the padding would
  * exceed the buffer (rows of very uneven length inside one slice) the plan
  * falls back to format MW_FMT_CSR.  A's arrays must stay valid while the
  * plan is used.  buffer: device memory of at least mw_spmv_plan_bytes

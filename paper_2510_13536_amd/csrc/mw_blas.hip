@@ -9,12 +9,15 @@
 //                        products), then every row's thread adds its own
 //                        products in CSR order.
 //   mw_sell_spmv_kernel  the planned form (SELL-64): slices of 64 rows, one
-//                        wavefront per slice and one lane per row, the
-//                        slice's entries stored column-major so every load
-//                        of values and column indices is one contiguous
-//                        512-byte wavefront access.  Each lane walks its
-//                        row's entries in CSR order; padding entries (col
-//                        -1) are skipped, not added as zeros.
+//                        wavefront per slice and one lane per row, entries
+//                        stored in pairs so every wavefront load of values
+//                        (and column indices) is contiguous.  A slice whose
+//                        rows fit diagonal slots (one column offset per
+//                        slot, stencil and banded rows) stores no column
+//                        indices: the gather address is row + offset, the
+//                        slot's lane mask skips rows without that entry.
+//                        Other slices keep explicit columns; padding
+//                        entries (col -1) are skipped, not added as zeros.
 // Both sum every row sequentially from zero in CSR order, so both are
 // bit-identical to that definition, whatever the launch shape.
 #include "mw_blas.hpp"
@@ -206,6 +209,8 @@ __global__ void __launch_bounds__(NT) mw_csr_spmv_kernel(int n, const int32_t *_
 template <int A, int MODE>
 __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const int32_t *__restrict__ sp,
                                                           const int32_t *__restrict__ sc,
+                                                          const int32_t *__restrict__ soff,
+                                                          const uint64_t *__restrict__ smask,
                                                           const double *__restrict__ sv,
                                                           const double *__restrict__ x, double *__restrict__ y,
                                                           double *__restrict__ slots, const int32_t *__restrict__ run_prev,
@@ -226,7 +231,7 @@ __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const i
         if (s >= ns) continue;  // whole wavefront
         const int row = s * 64 + lane;
         const int b = sp[s];
-        const Num<A> acc = sell_row_sum<A, MODE>(b, (sp[s + 1] - b) >> 6, lane, sc, sv, x, n);
+        const Num<A> acc = slice_row_sum<A, MODE>(b, (sp[s + 1] - b) >> 6, lane, row, sc, soff, smask, sv, x, n);
         if (row < n) {
             store<A>(y, n, row, acc);
             if constexpr (MODE == 1) part = dot_step<A>(part, load_il<A>(x, row), acc);
@@ -305,12 +310,20 @@ __global__ void __launch_bounds__(FIN_NT) mw_sell_scan_kernel(int ns, const int3
     }
 }
 
-// Scatter the CSR rows into the slices (column-major inside a slice).
+// Scatter the CSR rows into the slices.  First the slot assignment of
+// diagonal slices is tried: slot j takes, from every lane whose next
+// unplaced entry has the smallest column offset among all lanes' next
+// entries, that entry (each lane keeps its CSR order).  When that places
+// every entry within the slice width w, the slice keeps the values so
+// placed plus one offset and lane mask per slot; otherwise it is
+// rewritten with explicit columns and zero slot masks.
 __global__ void __launch_bounds__(NT) mw_sell_fill_kernel(int n, int ns, const int32_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
                                                           const double *__restrict__ val,
                                                           const int32_t *__restrict__ slice_ptr,
-                                                          int32_t *__restrict__ scol, double *__restrict__ sval)
+                                                          int32_t *__restrict__ scol, double *__restrict__ sval,
+                                                          int32_t *__restrict__ soff, uint64_t *__restrict__ smask,
+                                                          int32_t *__restrict__ ndiag)
 {
     const int s = blockIdx.x * NWAVE + wave_id();
     const int lane = threadIdx.x & 63;
@@ -318,8 +331,28 @@ __global__ void __launch_bounds__(NT) mw_sell_fill_kernel(int n, int ns, const i
     const int row = s * 64 + lane;
     const int b = slice_ptr[s];
     const int w = (slice_ptr[s + 1] - b) / 64;
+    const int sl = b >> 6;
     const int rs = row < n ? row_ptr[row] : 0;
     const int len = row < n ? row_ptr[row + 1] - rs : 0;
+    int k = 0;  // this lane's entries placed so far
+    for (int j = 0; j < w; ++j) {
+        const int cand = k < len ? col[rs + k] - row : 0x7fffffff;
+        int m = cand;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
+        const bool has = k < len && cand == m;
+        const uint64_t mask = __ballot(has);
+        sval[sell_pos(b, w, j, lane)] = has ? val[rs + k] : 0.0;
+        if (lane == 0) {
+            soff[sl + j] = m;
+            smask[sl + j] = mask;
+        }
+        if (has) ++k;
+    }
+    if (__ballot(k != len) == 0) {
+        if (lane == 0 && w > 0) atomicAdd(ndiag, 1);
+        return;
+    }
     for (int j = 0; j < w; ++j) {
         const int pos = sell_pos(b, w, j, lane);
         if (j < len) {
@@ -329,12 +362,15 @@ __global__ void __launch_bounds__(NT) mw_sell_fill_kernel(int n, int ns, const i
             sval[pos] = 0.0;
             scol[pos] = -1;
         }
+        if (lane == 0) smask[sl + j] = 0;
     }
 }
 
-// Plan buffer layout.
+// Plan buffer: slice_ptr, the width scratch, the 64-bit total and the
+// diagonal-slice count, then per 64-entry slot the offset and lane mask,
+// then columns and values.
 struct PlanLayout {
-    size_t slice_ptr, width, total, col, val, bytes;
+    size_t slice_ptr, width, total, ndiag, soff, smask, col, val, bytes;
     long long cap;  // entries the buffer can hold
 };
 
@@ -343,10 +379,14 @@ PlanLayout plan_layout(int32_t n, int32_t nnz)
     const long long ns = (n + 63) / 64;
     PlanLayout L;
     L.cap = (long long)nnz + (long long)nnz / 4 + 64 * ns;
+    const long long slots = L.cap / 64 + 1;
     L.slice_ptr = 0;
     L.width = align256(sizeof(int32_t) * (ns + 1));
     L.total = L.width + align256(sizeof(int32_t) * ns);
-    L.col = L.total + 256;
+    L.ndiag = L.total + 8;
+    L.soff = L.total + 256;
+    L.smask = L.soff + align256(sizeof(int32_t) * slots);
+    L.col = L.smask + align256(sizeof(uint64_t) * slots);
     L.val = L.col + align256(sizeof(int32_t) * L.cap);
     L.bytes = L.val + align256(sizeof(double) * L.cap);
     return L;
@@ -409,10 +449,10 @@ int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, 
         const int g = sell_grid(A, ns);
         if (mode == 0)
             MW_LAUNCH((mw_sell_spmv_kernel<A, 0>), dim3(g), dim3(NT), s, ev0, ev1, M->n, ns, plan->slice_ptr,
-                      plan->col, plan->val, x, y, slots, run_prev, run_cur, rev);
+                      plan->col, plan->slot_off, plan->slot_mask, plan->val, x, y, slots, run_prev, run_cur, rev);
         else
             MW_LAUNCH((mw_sell_spmv_kernel<A, 1>), dim3(g), dim3(NT), s, ev0, ev1, M->n, ns, plan->slice_ptr,
-                      plan->col, plan->val, x, y, slots, run_prev, run_cur, rev);
+                      plan->col, plan->slot_off, plan->slot_mask, plan->val, x, y, slots, run_prev, run_cur, rev);
         if (nslots) *nslots = g;
     } else {
         const int nb = blocks_for(M->n, NT);
@@ -451,6 +491,9 @@ int plan_build(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *pl
     int32_t *sp = (int32_t *)(base + L.slice_ptr);
     int32_t *width = (int32_t *)(base + L.width);
     long long *total = (long long *)(base + L.total);
+    int32_t *ndiag = (int32_t *)(base + L.ndiag);
+    int32_t *soff = (int32_t *)(base + L.soff);
+    uint64_t *smask = (uint64_t *)(base + L.smask);
     int32_t *scol = (int32_t *)(base + L.col);
     double *sval = (double *)(base + L.val);
     long long *htot = pinned_total();
@@ -469,16 +512,22 @@ int plan_build(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *pl
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(htot, total, sizeof(long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    const long long stored = *htot;
+    const long long stored = htot[0];
     if (stored > L.cap || stored > 0x7fffffffLL) return MW_OK;  // CSR fallback
+    HIP_TRY(hipMemsetAsync(ndiag, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL(mw_sell_fill_kernel, dim3(nbw), dim3(NT), 0, s, n, ns, A->row_ptr, A->col_idx, A->val, sp,
-                       scol, sval);
+                       scol, sval, soff, smask, ndiag);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(htot + 1, ndiag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     plan->format = MW_FMT_SELL64;
     plan->stored = stored;
     plan->slice_ptr = sp;
     plan->col = scol;
     plan->val = sval;
+    plan->slot_off = soff;
+    plan->slot_mask = smask;
+    plan->ndiag = (int32_t)htot[1];
     return MW_OK;
 }
 

@@ -75,6 +75,50 @@ __device__ __forceinline__ Num<A> sell_row_sum(int b, int w, int lane, const int
     return acc;
 }
 
+// Sum of one row of a diagonal-slot slice (same value positions as
+// sell_row_sum): slot j holds, for every lane whose bit is set in
+// smask[j], the entry in column row + soff[j]; other lanes hold 0 there
+// and skip the slot.  A lane's entries occupy its set slots in CSR order,
+// so the row is summed in CSR order from zero, as in sell_row_sum.
+// soff / smask point at the slice's first slot (wave-uniform: scalar
+// loads); the gathers need no column loads.
+template <int A, int XL>
+__device__ __forceinline__ Num<A> dia_row_sum(int b, int w, int lane, long row, const int32_t *__restrict__ soff,
+                                              const uint64_t *__restrict__ smask, const double *__restrict__ sv,
+                                              const double *__restrict__ x, long n)
+{
+    Num<A> acc = zero<A>();
+    const int wp = w >> 1;
+    for (int m = 0; m < wp; ++m) {
+        const int z = b + 128 * m + 2 * lane;
+        const dvec2 a = load_matrix<A>((const dvec2 *)(sv + z));
+        const bool p0 = (smask[2 * m] >> lane) & 1, p1 = (smask[2 * m + 1] >> lane) & 1;
+        Num<A> x0 = zero<A>(), x1 = zero<A>();
+        if (p0) x0 = load_v<A, XL>(x, n, row + soff[2 * m]);
+        if (p1) x1 = load_v<A, XL>(x, n, row + soff[2 * m + 1]);
+        if (p0) acc = row_step<A>(acc, a.x, x0);
+        if (p1) acc = row_step<A>(acc, a.y, x1);
+    }
+    if (w & 1) {
+        const int z = b + 128 * wp + lane;
+        const double a0 = load_matrix<A>(sv + z);
+        if ((smask[w - 1] >> lane) & 1) acc = row_step<A>(acc, a0, load_v<A, XL>(x, n, row + soff[w - 1]));
+    }
+    return acc;
+}
+
+// Row sum of slice entries starting at b, width w: diagonal slots when the
+// slice has them (its first slot mask is nonzero), explicit columns else.
+template <int A, int XL>
+__device__ __forceinline__ Num<A> slice_row_sum(int b, int w, int lane, long row, const int32_t *__restrict__ sc,
+                                                const int32_t *__restrict__ soff, const uint64_t *__restrict__ smask,
+                                                const double *__restrict__ sv, const double *__restrict__ x, long n)
+{
+    const int sl = b >> 6;
+    if (w > 0 && smask[sl] != 0) return dia_row_sum<A, XL>(b, w, lane, row, soff + sl, smask + sl, sv, x, n);
+    return sell_row_sum<A, XL>(b, w, lane, sc, sv, x, n);
+}
+
 // Position of entry j of lane l in a slice of width w starting at b.
 __device__ __forceinline__ int sell_pos(int b, int w, int j, int lane)
 {

@@ -319,6 +319,7 @@ bool same_key(const ChunkArgs &a, const ChunkArgs &b)
            a.x == b.x && a.slots_a == b.slots_a && a.slots_b == b.slots_b && a.st == b.st && a.plan && b.plan &&
            a.plan->format == b.plan->format && a.plan->nslices == b.plan->nslices &&
            a.plan->slice_ptr == b.plan->slice_ptr && a.plan->col == b.plan->col && a.plan->val == b.plan->val &&
+           a.plan->slot_off == b.plan->slot_off && a.plan->slot_mask == b.plan->slot_mask &&
            a.M->row_ptr == b.M->row_ptr && a.M->col_idx == b.M->col_idx && a.M->val == b.M->val &&
            a.M->n == b.M->n;
 }

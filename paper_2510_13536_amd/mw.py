@@ -59,7 +59,8 @@ FMT = {0: "csr", 1: "sell64"}
 
 class SpmvPlan(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("format", C.c_int32), ("nslices", C.c_int32),
-                ("stored", C.c_int64), ("slice_ptr", _vp), ("col", _vp), ("val", _vp), ("csr", Csr)]
+                ("stored", C.c_int64), ("slice_ptr", _vp), ("col", _vp), ("val", _vp), ("slot_off", _vp),
+                ("slot_mask", _vp), ("ndiag", C.c_int32), ("reserved", C.c_int32), ("csr", Csr)]
 
 
 class CgOpts(C.Structure):
@@ -257,6 +258,11 @@ class Plan:
     @property
     def stored(self):
         return int(self.c.stored)
+
+    @property
+    def ndiag(self):
+        """Slices stored as diagonal slots (SELL-64 only)."""
+        return int(self.c.ndiag)
 
 
 def spmv_planned(arith, plan, x, y=None):

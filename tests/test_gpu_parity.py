@@ -122,12 +122,64 @@ def ragged_matrix(seed=3):
     return P.CSR.from_scipy(sp.coo_matrix((v, (r, c)), shape=(n, n)))
 
 
+def unsorted_matrix():
+    # 3D Poisson rows with their CSR entries in a seeded random order: the
+    # sum order is the stored order, which the plan must keep
+    A = P.poisson3d(9, 8, 7)
+    rng = np.random.default_rng(21)
+    col, val = A.col_idx.copy(), A.val.copy()
+    for i in range(A.n):
+        a, b = A.row_ptr[i], A.row_ptr[i + 1]
+        perm = rng.permutation(b - a)
+        col[a:b] = col[a:b][perm]
+        val[a:b] = val[a:b][perm]
+    return P.CSR(A.n, A.row_ptr.copy(), col, val)
+
+
+def reversed_matrix():
+    # a circulant Laplacian with every row stored in descending column
+    # order: slices away from the wrap-around still take diagonal slots, in
+    # descending offset order
+    A = P.circulant_laplacian(2500, [1, 3, 250], [0.5, 0.25, 1.0])
+    col, val = A.col_idx.copy(), A.val.copy()
+    for i in range(A.n):
+        a, b = A.row_ptr[i], A.row_ptr[i + 1]
+        col[a:b] = col[a:b][::-1]
+        val[a:b] = val[a:b][::-1]
+    return P.CSR(A.n, A.row_ptr.copy(), col, val)
+
+
+def diagonal_slices(A):
+    """Slices a SpMV plan stores as diagonal slots: slot j takes, from each
+    of the 64 rows, its next CSR entry when that entry's column offset is the
+    smallest among the rows' next entries; a slice qualifies when its rows
+    are used up within its width (the longest row)."""
+    ns = (A.n + 63) // 64
+    count = 0
+    for s in range(ns):
+        rows = range(64 * s, min(64 * s + 64, A.n))
+        offs = [list(A.col_idx[A.row_ptr[r]:A.row_ptr[r + 1]] - r) for r in rows]
+        w = max(len(o) for o in offs)
+        k = [0] * len(offs)
+        for _ in range(w):
+            cands = [o[kk] for o, kk in zip(offs, k) if kk < len(o)]
+            if not cands:
+                break
+            m = min(cands)
+            k = [kk + 1 if kk < len(o) and o[kk] == m else kk for o, kk in zip(offs, k)]
+        if w > 0 and all(kk == len(o) for o, kk in zip(offs, k)):
+            count += 1
+    return count
+
+
 MATRICES = {
     "poisson2d_64": lambda: P.poisson2d(64),
     "poisson3d_ragged": lambda: P.poisson3d(13, 11, 7),
     "banded27": lambda: P.banded_spd(5000, half_bw=13, seed=1, dseed=2),
     "circulant": lambda: P.circulant_laplacian(3001, [1, 17, 400, 1200], [0.5, 0.3, 1.0, 0.2]),
     "ragged": ragged_matrix,
+    "unsorted": unsorted_matrix,
+    "reversed": reversed_matrix,
 }
 
 
@@ -272,6 +324,14 @@ def test_spmv_planned_bit_exact(mw, arith, mat):
     assert plan.format == ("csr" if mat == "ragged" else "sell64")
     if plan.format == "sell64":
         assert plan.stored >= A.nnz and plan.stored % 64 == 0
+        # stencil / banded slices become diagonal slots, the circulant's
+        # wrap-around slices and the shuffled rows keep explicit columns
+        assert plan.ndiag == diagonal_slices(A)
+        ns = (A.n + 63) // 64
+        if mat in ("poisson2d_64", "banded27"):
+            assert plan.ndiag == ns
+        if mat == "circulant":
+            assert 0 < plan.ndiag < ns
     got = host(mw.spmv_planned(arith, plan, dev(x)))
     assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
 
