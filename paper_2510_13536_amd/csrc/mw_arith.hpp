@@ -309,69 +309,92 @@ __device__ __forceinline__ void store_scalar(double *__restrict__ s, const Num<A
     for (int w = 0; w < words(A); ++w) s[w] = x.w[w];
 }
 
-// Word-interleaved vectors (element i's k words at v[k i .. k i + k)): the
-// solvers keep p, the only vector the SpMV gathers, in this layout so one
-// gathered element is one or two wide loads instead of k narrow ones.
+// Gather layout of the vector the SpMV reads (the solvers keep p in it):
+// 2-word values interleaved (element i's words at v[2 i], v[2 i + 1]); 3-word
+// values as interleaved leading pairs (v[2 i], v[2 i + 1]) followed by a
+// plane of third words (v[2 n + i]).  A gathered element is then one wide
+// load (plus one narrow one for 3 words) touching the fewest cache lines
+// per wavefront: 16 + 8 bytes per lane instead of 24 at a 24-byte stride.
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 template <int A>
-__device__ __forceinline__ Num<A> load_il(const double *__restrict__ v, long i)
+__device__ __forceinline__ Num<A> load_il(const double *__restrict__ v, long n, long i)
 {
     Num<A> r;
     if constexpr (words(A) == 1) {
         r.w[0] = v[i];
-    } else if constexpr (words(A) == 2) {
+    } else {
         const dvec2 t = *(const dvec2 *)(v + 2 * i);
         r.w[0] = t.x;
         r.w[1] = t.y;
-    } else {
-        struct W3 {
-            double a, b, c;
-        } t;
-        __builtin_memcpy(&t, v + 3 * i, sizeof(t));
-        r.w[0] = t.a;
-        r.w[1] = t.b;
-        r.w[2] = t.c;
+        if constexpr (words(A) == 3) r.w[2] = v[2 * n + i];
     }
     return r;
 }
 
 template <int A>
-__device__ __forceinline__ void store_il(double *__restrict__ v, long i, const Num<A> &x)
+__device__ __forceinline__ void store_il(double *__restrict__ v, long n, long i, const Num<A> &x)
 {
-    if constexpr (words(A) == 2) {
+    if constexpr (words(A) == 1) {
+        v[i] = x.w[0];
+    } else {
         dvec2 t;
         t.x = x.w[0];
         t.y = x.w[1];
         *(dvec2 *)(v + 2 * i) = t;
-    } else {
-#pragma unroll
-        for (int w = 0; w < words(A); ++w) v[words(A) * i + w] = x.w[w];
+        if constexpr (words(A) == 3) v[2 * n + i] = x.w[2];
     }
 }
 
-// Load of element i in word planes (IL = 0) or interleaved (IL = 1).
+// Load of element i in word planes (IL = 0) or the gather layout (IL = 1).
 template <int A, int IL>
 __device__ __forceinline__ Num<A> load_v(const double *__restrict__ v, long n, long i)
 {
-    if constexpr (IL) return load_il<A>(v, i);
+    if constexpr (IL) return load_il<A>(v, n, i);
     else return load<A>(v, n, i);
 }
 
 template <int A, int IL>
 __device__ __forceinline__ void store_v(double *__restrict__ v, long n, long i, const Num<A> &x)
 {
-    if constexpr (IL) store_il<A>(v, i, x);
+    if constexpr (IL) store_il<A>(v, n, i, x);
     else store<A>(v, n, i, x);
 }
 
-// Lane-to-lane move of a whole value (wavefront of 64).
+// Lane-to-lane move of a whole value (wavefront of 64): lane l receives
+// lane l + off; lanes whose source lies outside the wavefront keep their
+// own value.
 template <int A>
 __device__ __forceinline__ Num<A> shfl_down(const Num<A> &v, int off)
 {
     Num<A> r;
 #pragma unroll
     for (int w = 0; w < words(A); ++w) r.w[w] = __shfl_down(v.w[w], off, 64);
+    return r;
+}
+
+// Whole-wavefront shift by one lane (DPP wave_shl:1 / wave_shr:1, one VALU
+// move per 32 bits): DIR = +1, lane l receives lane l + 1; DIR = -1, lane l
+// receives lane l - 1.  The lane without a source (63, resp. 0) receives
+// `edge`.  Must run with every lane active.
+template <int DIR>
+__device__ __forceinline__ double wave_shift1(double v, double edge)
+{
+    const long long bits = __double_as_longlong(v);
+    constexpr int ctrl = DIR > 0 ? 0x130 : 0x138;
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, ctrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), ctrl, 0xf, 0xf, false);
+    const double r = __hiloint2double(hi, lo);
+    const int lane = threadIdx.x & 63;
+    return lane == (DIR > 0 ? 63 : 0) ? edge : r;
+}
+
+template <int DIR, int A>
+__device__ __forceinline__ Num<A> wave_shift1(const Num<A> &v, const Num<A> &edge)
+{
+    Num<A> r;
+#pragma unroll
+    for (int w = 0; w < words(A); ++w) r.w[w] = wave_shift1<DIR>(v.w[w], edge.w[w]);
     return r;
 }
 

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_spmv_kernel(BatchDev d, const do
         if (valid) store<A>(y, d.n, row, acc);
         if constexpr (MODE == 1) {
             Num<A> c = zero<A>();
-            if (valid) c = dot_step<A>(c, load_il<A>(x, row), acc);
+            if (valid) c = dot_step<A>(c, load_il<A>(x, d.n, row), acc);
             c = wave_sum<A>(c);
             if (lane == 0) store_scalar<A>(slots + (long)s * K, c);
         }
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_init_kernel(BatchDev d, const do
             if constexpr (A == FP64) ri = promote<A>(bi.w[0] - q[i]);
             else ri = add<A>(bi, neg<A>(load<A>(q, d.n, i)));
             store<A>(r, d.n, i, ri);
-            store_il<A>(p, i, ri);
+            store_il<A>(p, d.n, i, ri);
             rr = dot_step<A>(rr, ri, ri);
             bb = dot_step<A>(bb, bi, bi);
         }
@@ -308,11 +308,11 @@ __global__ void __launch_bounds__(BNT) mw_batch_step_p_kernel(BatchDev d, const 
         if (lane >= d.slice_rows[s]) continue;
         const long i = (long)d.slice_row0[s] + lane;
         const Num<A> al = load_scalar<A>(d.alpha + (long)sys * K);
-        const Num<A> pi = load_il<A>(p, i);
+        const Num<A> pi = load_il<A>(p, d.n, i);
         store<A>(x, d.n, i, axpy_term<A>(al, pi, load<A>(x, d.n, i)));
         if (run) {
             const Num<A> be = load_scalar<A>(d.beta + (long)sys * K);
-            store_il<A>(p, i, axpy_term<A>(be, pi, load<A>(r, d.n, i)));
+            store_il<A>(p, d.n, i, axpy_term<A>(be, pi, load<A>(r, d.n, i)));
         }
     }
 }

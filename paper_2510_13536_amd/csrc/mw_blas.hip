@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(FIN_NT) mw_reduce_slots_kernel(int nslots, con
 // in LDS (FP64: the pair (a_ij, x_j), whose accumulation is one fma); then
 // every thread adds the products of its own row that fall in the chunk, in
 // CSR order, into a register accumulator that persists across chunks.
-// MODE 1 (CG): x is p, kept word-interleaved by the solver; also the
+// MODE 1 (CG): x is p, kept in the gather layout (load_il) by the solver; also the
 // partial of p^T q into slots[logical workgroup].
 template <int A, int MODE>
 __global__ void __launch_bounds__(NT) mw_csr_spmv_kernel(int n, const int32_t *__restrict__ row_ptr,
@@ -192,7 +192,7 @@ __global__ void __launch_bounds__(NT) mw_csr_spmv_kernel(int n, const int32_t *_
     if (row < n) store<A>(y, n, row, acc);
     if constexpr (MODE == 1) {
         Num<A> c = zero<A>();
-        if (row < n) c = dot_step<A>(c, load_il<A>(x, row), acc);
+        if (row < n) c = dot_step<A>(c, load_il<A>(x, n, row), acc);
         const Num<A> sum = block_sum<A, NT>(c);
         if (threadIdx.x == 0) store_scalar<A>(slots + (long)lb * K, sum);
     }
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(NT) mw_csr_spmv_kernel(int n, const int32_t *_
 // Persistent workgroups of NWAVE wavefronts walk tiles of NWAVE slices
 // (xcd_tiles); wavefront w of a tile takes slice 4t + w, lane l its row
 // 64 s + l (entry positions: sell_row_sum).
-// MODE 1 (CG): x is p, kept word-interleaved by the solver, y is q; each
+// MODE 1 (CG): x is p, kept in the gather layout (load_il) by the solver, y is q; each
 // thread accumulates p_i q_i over its rows in tile order, and the
 // workgroup sum goes to slots[blockIdx.x].
 template <int A, int MODE>
@@ -231,10 +231,28 @@ __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const i
         if (s >= ns) continue;  // whole wavefront
         const int row = s * 64 + lane;
         const int b = sp[s];
-        const Num<A> acc = slice_row_sum<A, MODE>(b, (sp[s + 1] - b) >> 6, lane, row, sc, soff, smask, sv, x, n);
-        if (row < n) {
-            store<A>(y, n, row, acc);
-            if constexpr (MODE == 1) part = dot_step<A>(part, load_il<A>(x, row), acc);
+        const int w = (sp[s + 1] - b) >> 6;
+        Num<A> acc;
+        if (slice_is_diag(b, w, smask)) {
+            // x[row]: the offset-0 slot, the source of the +-1 slots and,
+            // in CG mode, p_i of p^T q
+            const Num<A> xc = row < n ? load_v<A, MODE>(x, n, row) : zero<A>();
+            Num<A> xe = zero<A>();
+            if constexpr (neighbour_moves<A>()) {
+                const long re = lane == 0 ? (long)row - 1 : (long)row + 1;
+                if ((lane == 0 || lane == 63) && re >= 0 && re < n) xe = load_v<A, MODE>(x, n, re);
+            }
+            acc = dia_row_sum<A, MODE>(b, w, lane, row, soff + (b >> 6), smask + (b >> 6), sv, x, n, xc, xe);
+            if (row < n) {
+                store<A>(y, n, row, acc);
+                if constexpr (MODE == 1) part = dot_step<A>(part, xc, acc);
+            }
+        } else {
+            acc = sell_row_sum<A, MODE>(b, w, lane, sc, sv, x, n);
+            if (row < n) {
+                store<A>(y, n, row, acc);
+                if constexpr (MODE == 1) part = dot_step<A>(part, load_il<A>(x, n, row), acc);
+            }
         }
     }
     if constexpr (MODE == 1) {

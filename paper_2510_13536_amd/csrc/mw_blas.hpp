@@ -47,7 +47,7 @@ __device__ __forceinline__ T load_matrix(const T *p)
 // two values (8 bytes two columns); an odd last entry at b + 128 (w/2) + l.
 // Every wavefront load is contiguous.  The entries are added in order
 // j = 0, 1, ..., from zero; padding (col < 0) is skipped.  x is in word
-// planes (XL = 0) or word-interleaved (XL = 1).
+// planes (XL = 0) or in the gather layout of load_il (XL = 1).
 typedef int ivec2 __attribute__((ext_vector_type(2)));
 
 template <int A, int XL>
@@ -75,17 +75,47 @@ __device__ __forceinline__ Num<A> sell_row_sum(int b, int w, int lane, const int
     return acc;
 }
 
+// Whether diagonal slices take the +-1 offsets from the neighbouring lane
+// (DPP moves, see dia_x) instead of gathering them.  It pays for QTW, whose
+// SpMV is bound by its gather traffic (measured on MI355X: 48.4 -> 44.5 us
+// on 3D Poisson 128^3); FP64/DW/QDW gain nothing and TW, bound by its
+// arithmetic, loses to the extra moves.
+template <int A>
+constexpr bool neighbour_moves() { return A == QTW; }
+
+// x[row + o] for a lane of a diagonal-slot slice whose slot has column
+// offset o (wave-uniform); need: the lane has an entry in the slot.  xc is
+// x[row] (0 for rows past n).  Offset 0 is xc itself.  With
+// neighbour_moves, offsets +-1 are xc moved from the neighbouring lane and
+// xe is the value one row beyond the slice's edge lane (lane 0:
+// x[row - 1], lane 63: x[row + 1]).  Any other offset is a gather.  Called
+// by the whole wavefront (the moves need every lane).
+template <int A, int XL>
+__device__ __forceinline__ Num<A> dia_x(int o, bool need, long row, const Num<A> &xc, const Num<A> &xe,
+                                        const double *__restrict__ x, long n)
+{
+    if (o == 0) return xc;
+    if constexpr (neighbour_moves<A>()) {
+        if (o == 1) return wave_shift1<1, A>(xc, xe);
+        if (o == -1) return wave_shift1<-1, A>(xc, xe);
+    }
+    Num<A> v = zero<A>();
+    if (need) v = load_v<A, XL>(x, n, row + o);
+    return v;
+}
+
 // Sum of one row of a diagonal-slot slice (same value positions as
 // sell_row_sum): slot j holds, for every lane whose bit is set in
 // smask[j], the entry in column row + soff[j]; other lanes hold 0 there
 // and skip the slot.  A lane's entries occupy its set slots in CSR order,
 // so the row is summed in CSR order from zero, as in sell_row_sum.
 // soff / smask point at the slice's first slot (wave-uniform: scalar
-// loads); the gathers need no column loads.
+// loads); the gathers need no column loads.  xc, xe: see dia_x.
 template <int A, int XL>
 __device__ __forceinline__ Num<A> dia_row_sum(int b, int w, int lane, long row, const int32_t *__restrict__ soff,
                                               const uint64_t *__restrict__ smask, const double *__restrict__ sv,
-                                              const double *__restrict__ x, long n)
+                                              const double *__restrict__ x, long n, const Num<A> &xc,
+                                              const Num<A> &xe)
 {
     Num<A> acc = zero<A>();
     const int wp = w >> 1;
@@ -93,30 +123,26 @@ __device__ __forceinline__ Num<A> dia_row_sum(int b, int w, int lane, long row, 
         const int z = b + 128 * m + 2 * lane;
         const dvec2 a = load_matrix<A>((const dvec2 *)(sv + z));
         const bool p0 = (smask[2 * m] >> lane) & 1, p1 = (smask[2 * m + 1] >> lane) & 1;
-        Num<A> x0 = zero<A>(), x1 = zero<A>();
-        if (p0) x0 = load_v<A, XL>(x, n, row + soff[2 * m]);
-        if (p1) x1 = load_v<A, XL>(x, n, row + soff[2 * m + 1]);
+        const Num<A> x0 = dia_x<A, XL>(soff[2 * m], p0, row, xc, xe, x, n);
+        const Num<A> x1 = dia_x<A, XL>(soff[2 * m + 1], p1, row, xc, xe, x, n);
         if (p0) acc = row_step<A>(acc, a.x, x0);
         if (p1) acc = row_step<A>(acc, a.y, x1);
     }
     if (w & 1) {
         const int z = b + 128 * wp + lane;
         const double a0 = load_matrix<A>(sv + z);
-        if ((smask[w - 1] >> lane) & 1) acc = row_step<A>(acc, a0, load_v<A, XL>(x, n, row + soff[w - 1]));
+        const bool p0 = (smask[w - 1] >> lane) & 1;
+        const Num<A> x0 = dia_x<A, XL>(soff[w - 1], p0, row, xc, xe, x, n);
+        if (p0) acc = row_step<A>(acc, a0, x0);
     }
     return acc;
 }
 
-// Row sum of slice entries starting at b, width w: diagonal slots when the
-// slice has them (its first slot mask is nonzero), explicit columns else.
-template <int A, int XL>
-__device__ __forceinline__ Num<A> slice_row_sum(int b, int w, int lane, long row, const int32_t *__restrict__ sc,
-                                                const int32_t *__restrict__ soff, const uint64_t *__restrict__ smask,
-                                                const double *__restrict__ sv, const double *__restrict__ x, long n)
+// A slice starting at b with width w uses diagonal slots when its first
+// slot mask is nonzero (wave-uniform).
+__device__ __forceinline__ bool slice_is_diag(int b, int w, const uint64_t *__restrict__ smask)
 {
-    const int sl = b >> 6;
-    if (w > 0 && smask[sl] != 0) return dia_row_sum<A, XL>(b, w, lane, row, soff + sl, smask + sl, sv, x, n);
-    return sell_row_sum<A, XL>(b, w, lane, sc, sv, x, n);
+    return w > 0 && smask[b >> 6] != 0;
 }
 
 // Position of entry j of lane l in a slice of width w starting at b.

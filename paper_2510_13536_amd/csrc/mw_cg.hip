@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(NT) mw_cg_init_kernel(int n, const double *__r
         if constexpr (A == FP64) ri = promote<A>(bi.w[0] - q[i]);
         else ri = add<A>(bi, neg<A>(load<A>(q, n, i)));
         store<A>(r, n, i, ri);
-        store_il<A>(p, i, ri);
+        store_il<A>(p, n, i, ri);
         rr = dot_step<A>(rr, ri, ri);
         bb = dot_step<A>(bb, bi, bi);
     }
@@ -230,9 +230,9 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
     for (int m = 0; m < tw.count; ++m) {
         const long i = (long)tw[m] * UNT + threadIdx.x;
         if (i >= n) continue;
-        const Num<A> pi = load_il<A>(p, i);
+        const Num<A> pi = load_il<A>(p, n, i);
         store<A>(x, n, i, axpy_term<A>(al, pi, load<A>(x, n, i)));
-        if (!stop) store_il<A>(p, i, axpy_term<A>(be, pi, load<A>(r, n, i)));
+        if (!stop) store_il<A>(p, n, i, axpy_term<A>(be, pi, load<A>(r, n, i)));
     }
 }
 
