@@ -10,7 +10,9 @@ adds:
                 run right after the timed steps with the same kernels
                 launched directly (events recorded inside a replayed graph
                 cannot be read back); algorithmic bytes per launch
-                12 nnz + 4 (n + 1) + 16 k n (k = 3 words);
+                12 nnz + 4 (n + 1) + 16 k n (k = 3 words), the CSR
+                definition; the plan's diagonal-slot slices stream fewer
+                (format_bytes_per_launch, no column indices);
   cpu_baseline  the CPU oracle on this host, timed on a bounded sample (a
                 few CG iterations of the same solve), scaled to the solve's
                 iteration count;
@@ -268,10 +270,23 @@ def main():
     sp_us = pd["spmv"]["avg_us"]
     sp_bytes = spmv_bytes(A.n, A.nnz, k)
     achieved = sp_bytes / (sp_us * 1e-6) / 1e9
+    # what the planned SpMV actually streams: when every slice is stored as
+    # diagonal slots, 8 bytes per stored value, 12 per slot (offset + lane
+    # mask), 4 per slice pointer, 16 k per row (own p read, q written)
+    plan = mw.Plan(Ad)
+    fmt_bytes = None
+    if plan.format == "sell64" and plan.ndiag == plan.c.nslices:
+        fmt_bytes = 8 * plan.stored + 12 * (plan.stored // 64) + 4 * (plan.c.nslices + 1) + 16 * k * A.n
+    plan_info = {"format": plan.format, "nslices": int(plan.c.nslices), "diagonal_slices": plan.ndiag,
+                 "stored_entries": plan.stored}
+    del plan
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic("mw_sell_spmv_kernel<%d, 1>" % ARITH_CODE[arith]),
                 "kernel": "mw_sell_spmv_kernel<%s, CG mode>" % arith.upper(), "bytes_per_launch": sp_bytes,
                 "avg_launch_us": round(sp_us, 2), "launches": pd["spmv"]["launches"],
+                "format_bytes_per_launch": fmt_bytes,
+                "format_GBps": round(fmt_bytes / (sp_us * 1e-6) / 1e9, 1) if fmt_bytes else None,
+                "plan": plan_info,
                 "timing": "HIP events around each SpMV launch on the solver stream, %d event-timed solves "
                           "(direct launches, %.2f ms/solve) right after the timed steps" % (args.prof_steps, prof_ms)}
 
