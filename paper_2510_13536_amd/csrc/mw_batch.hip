@@ -7,7 +7,8 @@
 //
 // Layout: a SELL-64 copy of the matrix whose slices never straddle two
 // systems (each system's rows start a new slice), so every wavefront works
-// for exactly one system.  Per-system reductions use one partial per slice
+// for exactly one system; slices whose rows fit diagonal slots store no
+// column indices, as in the single-system plan (fill_slice).  Per-system reductions use one partial per slice
 // (a wavefront shuffle tree, no workgroup barrier), summed in slice order by
 // one workgroup per system.
 //
@@ -43,6 +44,8 @@ struct BatchDev {
     const int32_t *sp;             // SELL slice offsets, ns + 1
     const int32_t *sc;             // SELL columns (-1 = padding)
     const double *sv;              // SELL values
+    const int32_t *soff;           // per slot of a diagonal slice: column offset
+    const uint64_t *smask;         // per slot: rows that have an entry in it
     double *rho, *alpha, *beta;    // nsys * K each
     double *nb, *rel;              // nsys each
     int32_t *active, *xdue, *iters, *status;  // nsys each
@@ -78,29 +81,21 @@ __global__ void __launch_bounds__(BNT) mw_batch_fill_kernel(BatchDev d, const in
                                                             const int32_t *__restrict__ col,
                                                             const double *__restrict__ val,
                                                             const int32_t *__restrict__ slice_ptr,
-                                                            int32_t *__restrict__ scol, double *__restrict__ sval)
+                                                            int32_t *__restrict__ scol, double *__restrict__ sval,
+                                                            int32_t *__restrict__ soff, uint64_t *__restrict__ smask)
 {
     const int s = blockIdx.x * NWAVE + wave_id();
     const int lane = threadIdx.x & 63;
     if (s >= d.ns) return;
     const int b = slice_ptr[s];
     const int w = (slice_ptr[s + 1] - b) / 64;
+    const long row = (long)d.slice_row0[s] + lane;
     int rs = 0, len = 0;
     if (lane < d.slice_rows[s]) {
-        const int row = d.slice_row0[s] + lane;
         rs = row_ptr[row];
         len = row_ptr[row + 1] - rs;
     }
-    for (int j = 0; j < w; ++j) {
-        const int pos = sell_pos(b, w, j, lane);
-        if (j < len) {
-            sval[pos] = val[rs + j];
-            scol[pos] = col[rs + j];
-        } else {
-            sval[pos] = 0.0;
-            scol[pos] = -1;
-        }
-    }
+    (void)fill_slice(b, w, lane, row, rs, len, col, val, scol, sval, soff, smask);
 }
 
 // ------------------------------------------------------------- kernels
@@ -121,13 +116,26 @@ __global__ void __launch_bounds__(BNT) mw_batch_spmv_kernel(BatchDev d, const do
             if (!d.active[d.slice_sys[s]]) continue;
         }
         const int b = d.sp[s];
-        const Num<A> acc = sell_row_sum<A, MODE>(b, (d.sp[s + 1] - b) >> 6, lane, d.sc, d.sv, x, d.n);
+        const int w = (d.sp[s + 1] - b) >> 6;
         const bool valid = lane < d.slice_rows[s];
         const long row = (long)d.slice_row0[s] + lane;
+        Num<A> acc, xc = zero<A>();
+        if (slice_is_diag(b, w, d.smask)) {
+            if (valid) xc = load_v<A, MODE>(x, d.n, row);
+            Num<A> xe = zero<A>();
+            if constexpr (neighbour_moves<A>()) {
+                const long re = lane == 0 ? row - 1 : row + 1;
+                if ((lane == 0 || lane == 63) && re >= 0 && re < d.n) xe = load_v<A, MODE>(x, d.n, re);
+            }
+            acc = dia_row_sum<A, MODE>(b, w, lane, row, d.soff + (b >> 6), d.smask + (b >> 6), d.sv, x, d.n, xc, xe);
+        } else {
+            acc = sell_row_sum<A, MODE>(b, w, lane, d.sc, d.sv, x, d.n);
+            if (MODE == 1 && valid) xc = load_il<A>(x, d.n, row);
+        }
         if (valid) store<A>(y, d.n, row, acc);
         if constexpr (MODE == 1) {
             Num<A> c = zero<A>();
-            if (valid) c = dot_step<A>(c, load_il<A>(x, d.n, row), acc);
+            if (valid) c = dot_step<A>(c, xc, acc);
             c = wave_sum<A>(c);
             if (lane == 0) store_scalar<A>(slots + (long)s * K, c);
         }
@@ -321,7 +329,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_step_p_kernel(BatchDev d, const 
 
 struct BatchLayout {
     size_t r, p, q, slots_a, slots_b, sys_slice_off, slice_sys, slice_row0, slice_rows, dscal, iscal, params, width,
-        slice_ptr, total, col, val, bytes;
+        slice_ptr, total, soff, smask, col, val, bytes;
     long long ns_max, cap;
 };
 
@@ -352,6 +360,8 @@ BatchLayout batch_layout(int a, int32_t nsys, int32_t n, int32_t nnz)
     L.width = take(sizeof(int32_t) * L.ns_max);
     L.slice_ptr = take(sizeof(int32_t) * (L.ns_max + 1));
     L.total = take(sizeof(long long));
+    L.soff = take(sizeof(int32_t) * (L.cap / 64 + 8));
+    L.smask = take(sizeof(uint64_t) * (L.cap / 64 + 8));
     L.col = take(sizeof(int32_t) * L.cap);
     L.val = take(sizeof(double) * L.cap);
     L.bytes = o;
@@ -474,6 +484,8 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     d.sp = (int32_t *)(base + L.slice_ptr);
     d.sc = (int32_t *)(base + L.col);
     d.sv = (double *)(base + L.val);
+    d.soff = (int32_t *)(base + L.soff);
+    d.smask = (uint64_t *)(base + L.smask);
     double *dscal = (double *)(base + L.dscal);
     d.rho = dscal;
     d.alpha = d.rho + (size_t)K * nsys;
@@ -524,7 +536,7 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
         return MW_EINVAL;
     }
     hipLaunchKernelGGL(mw_batch_fill_kernel, dim3(nbw), dim3(BNT), 0, s, d, M->row_ptr, M->col_idx, M->val, d.sp,
-                       (int32_t *)d.sc, (double *)d.sv);
+                       (int32_t *)d.sc, (double *)d.sv, (int32_t *)d.soff, (uint64_t *)d.smask);
     HIP_TRY(hipGetLastError());
 
     // r0 = b - A x0, p0 = r0, per-system rho0, ||b||, flags

@@ -328,13 +328,8 @@ __global__ void __launch_bounds__(FIN_NT) mw_sell_scan_kernel(int ns, const int3
     }
 }
 
-// Scatter the CSR rows into the slices.  First the slot assignment of
-// diagonal slices is tried: slot j takes, from every lane whose next
-// unplaced entry has the smallest column offset among all lanes' next
-// entries, that entry (each lane keeps its CSR order).  When that places
-// every entry within the slice width w, the slice keeps the values so
-// placed plus one offset and lane mask per slot; otherwise it is
-// rewritten with explicit columns and zero slot masks.
+// Scatter the CSR rows into the slices (fill_slice); counts the slices
+// stored as diagonal slots.
 __global__ void __launch_bounds__(NT) mw_sell_fill_kernel(int n, int ns, const int32_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
                                                           const double *__restrict__ val,
@@ -349,39 +344,9 @@ __global__ void __launch_bounds__(NT) mw_sell_fill_kernel(int n, int ns, const i
     const int row = s * 64 + lane;
     const int b = slice_ptr[s];
     const int w = (slice_ptr[s + 1] - b) / 64;
-    const int sl = b >> 6;
     const int rs = row < n ? row_ptr[row] : 0;
     const int len = row < n ? row_ptr[row + 1] - rs : 0;
-    int k = 0;  // this lane's entries placed so far
-    for (int j = 0; j < w; ++j) {
-        const int cand = k < len ? col[rs + k] - row : 0x7fffffff;
-        int m = cand;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
-        const bool has = k < len && cand == m;
-        const uint64_t mask = __ballot(has);
-        sval[sell_pos(b, w, j, lane)] = has ? val[rs + k] : 0.0;
-        if (lane == 0) {
-            soff[sl + j] = m;
-            smask[sl + j] = mask;
-        }
-        if (has) ++k;
-    }
-    if (__ballot(k != len) == 0) {
-        if (lane == 0 && w > 0) atomicAdd(ndiag, 1);
-        return;
-    }
-    for (int j = 0; j < w; ++j) {
-        const int pos = sell_pos(b, w, j, lane);
-        if (j < len) {
-            sval[pos] = val[rs + j];
-            scol[pos] = col[rs + j];
-        } else {
-            sval[pos] = 0.0;
-            scol[pos] = -1;
-        }
-        if (lane == 0) smask[sl + j] = 0;
-    }
+    if (fill_slice(b, w, lane, row, rs, len, col, val, scol, sval, soff, smask) && lane == 0) atomicAdd(ndiag, 1);
 }
 
 // Plan buffer: slice_ptr, the width scratch, the 64-bit total and the

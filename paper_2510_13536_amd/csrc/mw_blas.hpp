@@ -152,6 +152,51 @@ __device__ __forceinline__ int sell_pos(int b, int w, int j, int lane)
     return (j < 2 * wp) ? b + 128 * (j >> 1) + 2 * lane + (j & 1) : b + 128 * wp + lane;
 }
 
+// Scatters one slice (rows given per lane: first entry rs, length len; 0
+// for lanes without a row) starting at entry b with width w.  First the
+// diagonal-slot assignment is tried: slot j takes, from every lane whose
+// next unplaced entry has the smallest column offset (column - row) among
+// all lanes' next entries, that entry (each lane keeps its CSR order).
+// When that places every entry within w slots, the slice keeps the values
+// so placed plus one offset and lane mask per slot (slots from b / 64);
+// otherwise it is rewritten with explicit columns and zero slot masks.
+// Called by a whole wavefront; returns whether the slice is diagonal.
+__device__ __forceinline__ bool fill_slice(int b, int w, int lane, long row, int rs, int len,
+                                           const int32_t *__restrict__ col, const double *__restrict__ val,
+                                           int32_t *__restrict__ scol, double *__restrict__ sval,
+                                           int32_t *__restrict__ soff, uint64_t *__restrict__ smask)
+{
+    const int sl = b >> 6;
+    int k = 0;  // this lane's entries placed so far
+    for (int j = 0; j < w; ++j) {
+        const int cand = k < len ? (int)(col[rs + k] - row) : 0x7fffffff;
+        int m = cand;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
+        const bool has = k < len && cand == m;
+        const uint64_t mask = __ballot(has);
+        sval[sell_pos(b, w, j, lane)] = has ? val[rs + k] : 0.0;
+        if (lane == 0) {
+            soff[sl + j] = m;
+            smask[sl + j] = mask;
+        }
+        if (has) ++k;
+    }
+    if (__ballot(k != len) == 0) return w > 0;
+    for (int j = 0; j < w; ++j) {
+        const int pos = sell_pos(b, w, j, lane);
+        if (j < len) {
+            sval[pos] = val[rs + j];
+            scol[pos] = col[rs + j];
+        } else {
+            sval[pos] = 0.0;
+            scol[pos] = -1;
+        }
+        if (lane == 0) smask[sl + j] = 0;
+    }
+    return false;
+}
+
 // Sum over the 64 lanes of a wavefront (shuffle tree, offsets 32 .. 1);
 // valid in lane 0.
 template <int A>
