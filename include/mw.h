@@ -147,6 +147,22 @@ typedef struct {
     int32_t reserved;
 } mw_cg_prof_t;
 
+/* Launch shape of the solvers' kernels (a set-up choice, not part of the
+ * paper's method; results of a solve depend on it only through the order
+ * in which per-workgroup dot partials are combined).  A field <= 0 means
+ * "not set". */
+typedef struct {
+    int32_t spmv_grid;       /* workgroups of the SpMV (batched: of every
+                                slice kernel), 8 .. 2048                    */
+    int32_t update_grid;     /* single system: workgroups of the two
+                                vector-update kernels, 8 .. 2048            */
+    int32_t update_threads;  /* single system: threads per update
+                                workgroup, 256, 512 or 1024                 */
+    int32_t chunk;           /* iterations per captured chunk, 1 .. 4096   */
+    double us_per_iteration; /* set by the tuners: measured device time per
+                                iteration of the chosen shape              */
+} mw_shape_t;
+
 /* Solver options (host memory); pass NULL for the defaults. */
 typedef struct {
     int32_t normalize;  /* QDW/QTW: 1 (default) normalises r after its
@@ -164,6 +180,12 @@ typedef struct {
     int32_t no_graph;   /* nonzero: launch each kernel directly instead of
                            replaying a captured hipGraph of a chunk       */
     int32_t reserved;
+    const mw_shape_t *shape;  /* optional launch shape; its set fields take
+                           precedence over a tuned shape (mw_cg_tune), which
+                           takes precedence over the MW_SGRID / MW_UGRID /
+                           MW_UNT environment overrides and the built-in
+                           shape.  chunk above takes precedence over
+                           shape->chunk.  Invalid values: MW_EINVAL.       */
 } mw_cg_opts_t;
 
 /* Number of FP64 words of an arithmetic: 1, 2, 2, 3, 3; -1 if unknown. */
@@ -315,9 +337,10 @@ size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int3
  * iters, status: DEVICE int32[nsys] outputs (may be NULL); rel_res: DEVICE
  * double[nsys] output, each system's last relative residual (may be NULL).
  * info (host, may be NULL): iters = the largest count, status = the worst
- * status (MW_OK < MW_NOT_CONVERGED < MW_BREAKDOWN), seconds.  opts: normalize,
- * chunk (default 16) and no_graph are honoured.  All systems advance in
- * lockstep, five kernels per iteration replayed from a captured hipGraph;
+ * status (MW_OK < MW_NOT_CONVERGED < MW_BREAKDOWN), seconds.  opts:
+ * normalize, chunk (default 16), no_graph and shape (spmv_grid, chunk) are
+ * honoured.  All systems advance in lockstep, five kernels per iteration
+ * replayed from a captured hipGraph;
  * a converged system's rows cost a flag test per 64-row slice afterwards.
  * Each system gives the same results whatever the other systems are, but
  * its dots are summed per 64-row slice, so they need not be bit-identical
@@ -329,6 +352,45 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
                         const double *b, double *x, double tol, int32_t maxit, const mw_cg_opts_t *opts,
                         void *workspace, int32_t *iters, int32_t *status, double *rel_res,
                         mw_cg_info_t *info, void *stream);
+
+/*
+ * Launch-shape autotuner (a set-up step, not part of the paper's method).
+ * Times `iters` CG iterations (tol = 0, so every candidate runs the same
+ * iterations; x is scratch and overwritten, b as for mw_cg_solve, b != 0)
+ * for each candidate shape -- SpMV grids 1024, 1280, 1536, 1792, 2048 x
+ * update grids 512, 1024, 2048 at 256 threads, candidates that clamp to
+ * the same launch counted once -- on `stream`'s device, each timed on its
+ * second run (the first captures its graph).  The fastest goes to *best
+ * and into a per-process table keyed by (a, n, nnz): later mw_cg_solve
+ * calls on matrices of that size use it unless opts->shape sets a field.
+ * iters: 2 .. 4096.  workspace: as mw_cg_solve.  Synchronises `stream`.
+ * Returns MW_OK or a negative error (MW_EINVAL also when b = 0 or the
+ * iterations break down before iters).
+ */
+int mw_cg_tune(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, int32_t iters, void *workspace,
+               mw_shape_t *best, void *stream);
+
+/*
+ * The same for mw_cg_solve_batched: candidate slice-kernel grids 256, 512,
+ * 1024, 1536, 2048, each timed over `iters` lockstep iterations of all
+ * systems (tol = 0); the table key is (a, n, nnz, nsys).  Arguments as
+ * mw_cg_solve_batched plus iters (2 .. 4096) and *best.
+ */
+int mw_cg_batched_tune(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, const mw_csr_t *A,
+                       const double *b, double *x, int32_t iters, void *workspace, mw_shape_t *best,
+                       void *stream);
+
+/*
+ * The launch shape a solve of an n x n matrix with nnz entries would use
+ * now with opts->shape unset (nsys = 0: mw_cg_solve; nsys >= 1:
+ * mw_cg_solve_batched of nsys systems, whose slice grid depends on the
+ * systems' slice count, reported here as 0 when not tuned): a tuned shape,
+ * else the environment overrides, else the built-in one, with grids
+ * clamped to what the matrix needs.  us_per_iteration: the tuned value, 0
+ * if not tuned.  Returns 1 if a tuned shape applies, 0 if not, or
+ * MW_EINVAL.
+ */
+int mw_cg_shape(mw_arith_t a, int32_t n, int32_t nnz, int32_t nsys, mw_shape_t *shape);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmwcg.so")
-SOURCES = ["mw_blas.hip", "mw_cg.hip", "mw_batch.hip"]
+SOURCES = ["mw_blas.hip", "mw_cg.hip", "mw_batch.hip", "mw_tune.hip"]
 
 
 def hipcc():

@@ -388,11 +388,12 @@ int32_t *pinned_count()
 }
 
 struct BatchKey {
-    int arith, nsys, ns, n, chunk;
+    int arith, nsys, ns, n, chunk, grid;
     const void *ptrs[8];
     bool operator==(const BatchKey &o) const
     {
-        if (arith != o.arith || nsys != o.nsys || ns != o.ns || n != o.n || chunk != o.chunk) return false;
+        if (arith != o.arith || nsys != o.nsys || ns != o.ns || n != o.n || chunk != o.chunk || grid != o.grid)
+            return false;
         for (int i = 0; i < 8; ++i)
             if (ptrs[i] != o.ptrs[i]) return false;
         return true;
@@ -422,10 +423,9 @@ BatchGraph &batch_graph()
 }
 
 template <int A>
-int enqueue_batch_chunk(const BatchDev &d, int chunk, double *r, double *p, double *q, double *x, double *sa,
+int enqueue_batch_chunk(const BatchDev &d, int chunk, int g, double *r, double *p, double *q, double *x, double *sa,
                         double *sb, hipStream_t s)
 {
-    const int g = persistent_grid(blocks_for(d.ns, NWAVE));
     for (int it = 0; it < chunk; ++it) {
         hipLaunchKernelGGL((mw_batch_spmv_kernel<A, 1>), dim3(g), dim3(BNT), 0, s, d, p, q, sa);
         hipLaunchKernelGGL((mw_batch_alpha_kernel<A>), dim3(d.nsys), dim3(BNT), 0, s, d, sa);
@@ -446,7 +446,6 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     const int n = M->n;
     const BatchLayout L = batch_layout(A, nsys, n, M->nnz);
     char *base = (char *)ws;
-    int chunk = (opts && opts->chunk > 0) ? opts->chunk : 16;
     const bool use_graph = !(opts && opts->no_graph);
 
     // slices: each system starts a new 64-row slice
@@ -464,6 +463,8 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     }
     h_sso[nsys] = (int32_t)h_sys.size();
     const int ns = (int)h_sys.size();
+    const BatchShape bsh = batch_shape(A, n, M->nnz, nsys, ns, opts ? opts->shape : nullptr, opts ? opts->chunk : 0);
+    const int chunk = bsh.chunk;
 
     hipStream_t s = batch_stream();
     int32_t *hcount = pinned_count();
@@ -540,7 +541,7 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     HIP_TRY(hipGetLastError());
 
     // r0 = b - A x0, p0 = r0, per-system rho0, ||b||, flags
-    const int g = persistent_grid(blocks_for(ns > 0 ? ns : 1, NWAVE));
+    const int g = bsh.grid;
     HIP_TRY(hipMemsetAsync(d.n_active, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL((mw_batch_spmv_kernel<A, 0>), dim3(g), dim3(BNT), 0, s, d, x, q, sa);
     hipLaunchKernelGGL((mw_batch_init_kernel<A>), dim3(g), dim3(BNT), 0, s, d, b, q, r, p, sa, sb);
@@ -552,11 +553,11 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     int chunks = 0;
     if (*hcount > 0 && use_graph) {
         BatchGraph &G = batch_graph();
-        BatchKey key{A, nsys, ns, n, chunk, {r, p, q, x, sa, sb, d.sp, base}};
+        BatchKey key{A, nsys, ns, n, chunk, g, {r, p, q, x, sa, sb, d.sp, base}};
         if (!(G.valid && G.key == key)) {
             G.release();
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            rc = enqueue_batch_chunk<A>(d, chunk, r, p, q, x, sa, sb, s);
+            rc = enqueue_batch_chunk<A>(d, chunk, g, r, p, q, x, sa, sb, s);
             hipGraph_t gr = nullptr;
             const hipError_t ce = hipStreamEndCapture(s, &gr);
             if (rc) return rc;
@@ -571,7 +572,7 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
         if (use_graph) {
             HIP_TRY(hipGraphLaunch(batch_graph().exec, s));
         } else {
-            rc = enqueue_batch_chunk<A>(d, chunk, r, p, q, x, sa, sb, s);
+            rc = enqueue_batch_chunk<A>(d, chunk, g, r, p, q, x, sa, sb, s);
             if (rc) return rc;
         }
         ++chunks;
@@ -619,18 +620,79 @@ size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int3
     return batch_layout(a, nsys, n, nnz).bytes;
 }
 
+}  // extern "C"
+
+namespace {
+
+bool batched_args_ok(int a, int32_t nsys, const int32_t *sys_row_off, const mw_csr_t *A, const double *b,
+                     const double *x, const void *workspace)
+{
+    if (!valid_arith(a) || nsys <= 0 || !sys_row_off || !valid_csr(A) || !b || !x || !workspace) return false;
+    if (sys_row_off[0] != 0 || sys_row_off[nsys] != A->n) return false;
+    for (int s = 0; s < nsys; ++s)
+        if (sys_row_off[s + 1] < sys_row_off[s]) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, const mw_csr_t *A, const double *b,
                         double *x, double tol, int32_t maxit, const mw_cg_opts_t *opts, void *workspace,
                         int32_t *iters, int32_t *status, double *rel_res, mw_cg_info_t *info, void *stream)
 {
-    if (!valid_arith(a) || nsys <= 0 || !sys_row_off || !valid_csr(A) || !b || !x || !workspace || !(tol >= 0.0) ||
-        maxit < 0)
-        return MW_EINVAL;
-    if (sys_row_off[0] != 0 || sys_row_off[nsys] != A->n) return MW_EINVAL;
-    for (int s = 0; s < nsys; ++s)
-        if (sys_row_off[s + 1] < sys_row_off[s]) return MW_EINVAL;
+    if (!batched_args_ok(a, nsys, sys_row_off, A, b, x, workspace) || !(tol >= 0.0) || maxit < 0) return MW_EINVAL;
+    if (opts && !shape_valid(opts->shape)) return MW_EINVAL;
     MW_DISPATCH(a, batched_a, nsys, sys_row_off, A, b, x, tol, maxit, opts, workspace, iters, status, rel_res, info,
                 (hipStream_t)stream);
+}
+
+int mw_cg_batched_tune(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, const mw_csr_t *A,
+                       const double *b, double *x, int32_t iters, void *workspace, mw_shape_t *best, void *stream)
+{
+    if (!best || iters < 2 || iters > 4096 || !batched_args_ok(a, nsys, sys_row_off, A, b, x, workspace))
+        return MW_EINVAL;
+    const int grids[] = {256, 512, 1024, 1536, 2048};
+    const size_t xbytes = sizeof(double) * (size_t)mw_words(a) * (size_t)A->n;
+    hipStream_t s = (hipStream_t)stream;
+    double best_t = 0.0;
+    mw_shape_t win{};
+    int last = -1;
+    for (int g : grids) {
+        mw_shape_t cand{g, 0, 0, iters, 0.0};
+        mw_cg_opts_t o{};
+        o.normalize = 1;
+        o.shape = &cand;
+        double t = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {  // the first run captures the chunk's graph
+            HIP_TRY(hipMemsetAsync(x, 0, xbytes, s));
+            mw_cg_info_t info{};
+            const int rc = mw_cg_solve_batched(a, nsys, sys_row_off, A, b, x, 0.0, iters, &o, workspace, nullptr,
+                                               nullptr, nullptr, &info, stream);
+            if (rc < 0) return rc;
+            if (info.iters < iters) {
+                set_error("mw_cg_batched_tune: the iterations stopped early (b = 0 or breakdown)");
+                return MW_EINVAL;
+            }
+            t = info.seconds;
+        }
+        if (best_t == 0.0 || t < best_t) {
+            best_t = t;
+            win = cand;
+        }
+        // larger grids clamp to the slices' own count: stop once they do
+        int ns = 0;
+        for (int k = 0; k < nsys; ++k) ns += (sys_row_off[k + 1] - sys_row_off[k] + 63) / 64;
+        const int need = persistent_grid(blocks_for(ns > 0 ? ns : 1, NWAVE));
+        if (g >= need || g == last) break;
+        last = g;
+    }
+    win.us_per_iteration = 1e6 * best_t / iters;
+    win.chunk = 0;
+    tuned_put(a, A->n, A->nnz, nsys, win);
+    *best = win;
+    return MW_OK;
 }
 
 }  // extern "C"

@@ -401,35 +401,14 @@ int spmv_max_slots(int32_t n)
     return csr > MAX_GRID ? csr : MAX_GRID;
 }
 
-// Workgroups of the SELL SpMV.  QTW runs best with six resident
-// wavefronts per SIMD (1536 workgroups of four), the other arithmetics
-// with eight (2048), swept on MI355X for 3D Poisson 128^3 over 512..2048;
-// MW_SGRID overrides (8 .. MAX_GRID).
-int sell_grid(int a, int ns)
-{
-    int cap = (a == MW_QTW) ? 1536 : MAX_GRID;
-    if (const char *e = getenv("MW_SGRID")) {
-        const int v = atoi(e);
-        if (v >= 8 && v <= MAX_GRID) cap = v;
-    }
-    const int g = persistent_grid(blocks_for(ns, NWAVE));
-    return g < cap ? g : cap;
-}
-
-int spmv_slots(int a, const mw_csr_t *M, const mw_spmv_plan_t *plan)
-{
-    if (plan && plan->format == MW_FMT_SELL64) return sell_grid(a, plan->nslices);
-    return blocks_for(M->n, NT);
-}
-
 template <int A>
 int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, double *y, double *slots,
                 const int32_t *run_prev, int32_t *run_cur, int mode, hipStream_t s, int *nslots, int rev,
-                hipEvent_t ev0, hipEvent_t ev1)
+                hipEvent_t ev0, hipEvent_t ev1, int grid)
 {
     if (plan && plan->format == MW_FMT_SELL64) {
         const int ns = plan->nslices;
-        const int g = sell_grid(A, ns);
+        const int g = grid > 0 ? grid : cg_shape(A, M->n, M->nnz, ns, nullptr, 0).sgrid;
         if (mode == 0)
             MW_LAUNCH((mw_sell_spmv_kernel<A, 0>), dim3(g), dim3(NT), s, ev0, ev1, M->n, ns, plan->slice_ptr,
                       plan->col, plan->slot_off, plan->slot_mask, plan->val, x, y, slots, run_prev, run_cur, rev);
@@ -452,15 +431,15 @@ int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, 
 }
 
 template int spmv_launch<FP64>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                               const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t);
+                               const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
 template int spmv_launch<DW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                             const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t);
+                             const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
 template int spmv_launch<QDW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                              const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t);
+                              const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
 template int spmv_launch<TW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                             const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t);
+                             const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
 template int spmv_launch<QTW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
-                              const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t);
+                              const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
 
 size_t plan_bytes(int32_t n, int32_t nnz) { return plan_layout(n, nnz).bytes; }
 

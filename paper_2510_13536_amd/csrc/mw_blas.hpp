@@ -225,21 +225,36 @@ int plan_build(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *pl
 // Most reduction slots any CG-mode SpMV launch writes for n rows.
 int spmv_max_slots(int32_t n);
 
-// y = A x.  plan == nullptr or plan->format == MW_FMT_CSR: CSR kernel on M;
-// else the SELL-64 kernel.  mode 1 (CG): x is p, y is q, the workgroup
-// partials of p^T q go to `slots` (their count to *nslots); the launch does
-// nothing but pass the stop on (*run_cur = 0) when *run_prev is 0.  rev:
-// walk the tiles backwards (see xcd_walk).  ev0/ev1: optional events that
-// time the kernel (MW_LAUNCH).
+// y = A x.  plan == nullptr or plan->format == MW_FMT_CSR: CSR kernel on M
+// (one workgroup per NT rows); else the SELL-64 kernel on `grid`
+// workgroups (0: the built-in shape, cg_shape).  mode 1 (CG): x is p, y is
+// q, the workgroup partials of p^T q go to `slots` (their count to
+// *nslots); the launch does nothing but pass the stop on (*run_cur = 0)
+// when *run_prev is 0.  rev: walk the tiles backwards (see xcd_walk).
+// ev0/ev1: optional events that time the kernel (MW_LAUNCH).
 template <int A>
 int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, double *y, double *slots,
                 const int32_t *run_prev, int32_t *run_cur, int mode, hipStream_t s, int *nslots = nullptr,
-                int rev = 0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                int rev = 0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int grid = 0);
 
-// Workgroups of a SELL SpMV launch in arithmetic a over ns slices.
-int sell_grid(int a, int ns);
-
-// Number of slots a CG-mode SpMV launch writes (see spmv_launch).
-int spmv_slots(int a, const mw_csr_t *M, const mw_spmv_plan_t *plan);
+// Launch shapes (mw_tune.hip).  Precedence: the fields an explicit shape
+// sets, then a tuned shape of the same (arith, n, nnz[, nsys]), then the
+// MW_SGRID / MW_UGRID / MW_UNT environment overrides, then the built-in
+// shape.
+struct CgShape {
+    int sgrid;  // workgroups of the SELL SpMV
+    int unt;    // threads per update workgroup (256, 512, 1024)
+    int ugrid;  // workgroups of the update kernels
+    int chunk;  // iterations per chunk (even)
+};
+struct BatchShape {
+    int grid;   // workgroups of the slice kernels
+    int chunk;  // iterations per chunk
+};
+CgShape cg_shape(int a, int n, int nnz, int ns, const mw_shape_t *explicit_shape, int opts_chunk);
+BatchShape batch_shape(int a, int n, int nnz, int nsys, int ns, const mw_shape_t *explicit_shape, int opts_chunk);
+void tuned_put(int a, int n, int nnz, int nsys, const mw_shape_t &s);
+bool tuned_get(int a, int n, int nnz, int nsys, mw_shape_t *s);
+bool shape_valid(const mw_shape_t *s);
 
 }  // namespace mwh

@@ -32,34 +32,8 @@ using namespace mwh;
 
 namespace {
 
-// Launch shape of the two vector-update kernels: UNT threads per
-// workgroup (a template argument: 256, 512 or 1024) and at most `ugrid`
-// workgroups.  Each workgroup reduces all partials of the kernel before it.
-constexpr int UGRID_MAX = 2048;
-
-struct UpdateShape {
-    int unt, ugrid;
-};
-
-// Default shape: 256 threads, at most 1024 workgroups (best of the swept
-// 256/512/1024-thread, 256..2048-workgroup shapes for all five arithmetics
-// on MI355X, 3D Poisson 128^3), overridable with MW_UNT / MW_UGRID.
-UpdateShape update_shape(int a)
-{
-    UpdateShape u{256, 1024};
-    (void)a;
-    if (const char *e = getenv("MW_UNT")) u.unt = atoi(e);
-    if (const char *e = getenv("MW_UGRID")) u.ugrid = atoi(e);
-    if (u.unt != 256 && u.unt != 512 && u.unt != 1024) u.unt = 256;
-    if (u.ugrid < 8 || u.ugrid > UGRID_MAX) u.ugrid = 1024;
-    return u;
-}
-
-inline int update_grid(int n, const UpdateShape &u)
-{
-    const int t = blocks_for(n, u.unt);
-    return t < u.ugrid ? t : u.ugrid;
-}
+// Workspace slot arrays hold the partials of up to this many workgroups.
+constexpr int UGRID_MAX = MAX_GRID;
 
 // r = b - q (q = A x0), p = r, partials of r^T r and b^T b.
 template <int A>
@@ -351,7 +325,7 @@ int enqueue_chunk(const ChunkArgs &c, EventPool *ev, hipStream_t s)
             hipEvent_t e1 = timed ? ev->e[(it * NKERN + k) * 2 + 1] : nullptr;
             if (k == 0) {
                 const int rc = spmv_launch<A>(c.M, c.plan, c.p, c.q, c.slots_a, &c.st->run[par ^ 1], &c.st->run[par],
-                                              1, s, nullptr, par, e0, e1);
+                                              1, s, nullptr, par, e0, e1, c.nslots_sp);
                 if (rc) return rc;
             } else if (c.unt == 1024) {
                 launch_steps<A, 1024>(c, k, par, s, e0, e1);
@@ -405,8 +379,6 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     double *sa = (double *)(base + L.slots_a);
     double *sb = (double *)(base + L.slots_b);
     CgState *st = (CgState *)(base + L.state);
-    int chunk = (opts && opts->chunk > 0) ? opts->chunk : 32;
-    chunk += chunk & 1;  // even: the parity pattern repeats per chunk
     mw_cg_prof_t *prof = opts ? opts->prof : nullptr;
     const int mask = prof ? (prof->mask ? prof->mask : 0xF) : 0;
     // events recorded by graph nodes cannot be read back: timing uses direct launches
@@ -442,8 +414,13 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     h.history = opts ? opts->history : nullptr;
     HIP_TRY(hipMemcpyAsync(st, &h, sizeof(CgState), hipMemcpyHostToDevice, s));
 
+    const CgShape sh = cg_shape(A, n, M->nnz, plan->nslices, opts ? opts->shape : nullptr, opts ? opts->chunk : 0);
+    const int chunk = sh.chunk;
+    const bool sell = plan->format == MW_FMT_SELL64;
+
     // r0 = b - A x0, p0 = r0, rho0, ||b||
-    int rc = spmv_launch<A>(M, plan, x, q, nullptr, nullptr, nullptr, 0, s);
+    int rc = spmv_launch<A>(M, plan, x, q, nullptr, nullptr, nullptr, 0, s, nullptr, 0, nullptr, nullptr,
+                            sell ? sh.sgrid : 0);
     if (rc) return rc;
     const int gi = persistent_grid(blocks_for(n, NT));
     hipLaunchKernelGGL((mw_cg_init_kernel<A>), dim3(gi), dim3(NT), 0, s, n, b, q, r, p, sa, sb);
@@ -466,11 +443,10 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     c.slots_a = sa;
     c.slots_b = sb;
     c.st = st;
-    const UpdateShape us = update_shape(A);
-    c.unt = us.unt;
-    c.ugrid = us.ugrid;
-    c.nslots_sp = spmv_slots(A, M, plan);
-    c.nslots_up = update_grid(n, us);
+    c.unt = sh.unt;
+    c.ugrid = sh.ugrid;
+    c.nslots_sp = sell ? sh.sgrid : blocks_for(n, NT);
+    c.nslots_up = sh.ugrid;
 
     if (!fl->stopped) {
         if (use_graph) {
@@ -558,7 +534,70 @@ int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, dou
     if (!valid_arith(a) || !valid_csr(A) || !b || !x || !workspace || !(tol >= 0.0) || maxit < 0)
         return MW_EINVAL;
     if (opts && opts->plan && (opts->plan->n != A->n || opts->plan->csr.row_ptr != A->row_ptr)) return MW_EINVAL;
+    if (opts && !shape_valid(opts->shape)) return MW_EINVAL;
     MW_DISPATCH(a, cg_a, A, b, x, tol, maxit, opts, workspace, info, (hipStream_t)stream);
+}
+
+int mw_cg_tune(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, int32_t iters, void *workspace,
+               mw_shape_t *best, void *stream)
+{
+    if (!valid_arith(a) || !valid_csr(A) || !b || !x || !workspace || !best || iters < 2 || iters > 4096)
+        return MW_EINVAL;
+    const int n = A->n;
+    const CgLayout L = cg_layout(a, n, A->nnz);
+    hipStream_t s = (hipStream_t)stream;
+    // one plan for every candidate
+    mw_spmv_plan_t plan;
+    int rc = plan_build(A, (char *)workspace + L.plan, L.total - L.plan, &plan, s);
+    if (rc) return rc;
+    const int ns = plan.nslices;
+    const int sgs[] = {1024, 1280, 1536, 1792, 2048};
+    const int ugs[] = {512, 1024, 2048};
+    int seen[16][2];
+    int nseen = 0;
+    double best_t = 0.0;
+    mw_shape_t win{};
+    const size_t xbytes = sizeof(double) * (size_t)mw_words(a) * (size_t)n;
+    for (int sg : sgs) {
+        for (int ug : ugs) {
+            mw_shape_t cand{sg, ug, 256, iters + (iters & 1), 0.0};
+            const CgShape eff = cg_shape(a, n, A->nnz, ns, &cand, 0);
+            const int key[2] = {plan.format == MW_FMT_SELL64 ? eff.sgrid : 0, eff.ugrid};
+            bool dup = false;
+            for (int i = 0; i < nseen; ++i) dup = dup || (seen[i][0] == key[0] && seen[i][1] == key[1]);
+            if (dup) continue;
+            seen[nseen][0] = key[0];
+            seen[nseen][1] = key[1];
+            ++nseen;
+            mw_cg_opts_t o{};
+            o.normalize = 1;
+            o.plan = &plan;
+            o.shape = &cand;
+            double t = 0.0;
+            for (int rep = 0; rep < 2; ++rep) {  // the first run captures the chunk's graph
+                HIP_TRY(hipMemsetAsync(x, 0, xbytes, s));
+                mw_cg_info_t info{};
+                rc = mw_cg_solve(a, A, b, x, 0.0, iters, &o, workspace, &info, stream);
+                if (rc < 0) return rc;
+                if (info.iters < iters) {
+                    set_error("mw_cg_tune: the iterations stopped early (b = 0 or breakdown)");
+                    return MW_EINVAL;
+                }
+                t = info.seconds;
+            }
+            if (best_t == 0.0 || t < best_t) {
+                best_t = t;
+                win = cand;
+                win.spmv_grid = key[0] > 0 ? key[0] : sg;
+                win.update_grid = key[1];
+            }
+        }
+    }
+    win.us_per_iteration = 1e6 * best_t / iters;
+    win.chunk = 0;  // tuned shapes leave the chunk length to the solver
+    tuned_put(a, n, A->nnz, 0, win);
+    *best = win;
+    return MW_OK;
 }
 
 }  // extern "C"

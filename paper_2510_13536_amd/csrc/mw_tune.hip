@@ -1,0 +1,160 @@
+// mw_tune.hip -- launch shapes of the solvers: the built-in shapes, the
+// environment overrides, the per-process table the tuners fill, and their
+// precedence (explicit > tuned > environment > built-in).  The tuners
+// themselves run the solvers and live beside them (mw_cg.hip,
+// mw_batch.hip).
+#include "mw_blas.hpp"
+
+#include <cstdlib>
+#include <mutex>
+
+using namespace mwk;
+using namespace mwh;
+
+namespace {
+
+struct TunedEntry {
+    int a, n, nnz, nsys;
+    mw_shape_t s;
+};
+
+constexpr int TABLE_SIZE = 64;  // distinct matrix sizes remembered; oldest replaced
+
+std::mutex g_mu;
+TunedEntry g_tab[TABLE_SIZE];
+int g_used = 0, g_next = 0;
+
+int env_int(const char *name)
+{
+    const char *e = getenv(name);
+    return e ? atoi(e) : 0;
+}
+
+bool in_range(int v, int lo, int hi) { return v <= 0 || (v >= lo && v <= hi); }
+
+}  // namespace
+
+namespace mwh {
+
+void tuned_put(int a, int n, int nnz, int nsys, const mw_shape_t &s)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (int i = 0; i < g_used; ++i) {
+        TunedEntry &e = g_tab[i];
+        if (e.a == a && e.n == n && e.nnz == nnz && e.nsys == nsys) {
+            e.s = s;
+            return;
+        }
+    }
+    g_tab[g_next] = TunedEntry{a, n, nnz, nsys, s};
+    g_next = (g_next + 1) % TABLE_SIZE;
+    if (g_used < TABLE_SIZE) ++g_used;
+}
+
+bool tuned_get(int a, int n, int nnz, int nsys, mw_shape_t *s)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (int i = 0; i < g_used; ++i) {
+        const TunedEntry &e = g_tab[i];
+        if (e.a == a && e.n == n && e.nnz == nnz && e.nsys == nsys) {
+            *s = e.s;
+            return true;
+        }
+    }
+    return false;
+}
+
+bool shape_valid(const mw_shape_t *s)
+{
+    if (!s) return true;
+    const int t = s->update_threads;
+    return in_range(s->spmv_grid, 8, MAX_GRID) && in_range(s->update_grid, 8, MAX_GRID) &&
+           (t <= 0 || t == 256 || t == 512 || t == 1024) && in_range(s->chunk, 1, 4096);
+}
+
+// The fields set in `over` replace those of `base`.
+static mw_shape_t overlay(mw_shape_t base, const mw_shape_t *over)
+{
+    if (!over) return base;
+    if (over->spmv_grid > 0) base.spmv_grid = over->spmv_grid;
+    if (over->update_grid > 0) base.update_grid = over->update_grid;
+    if (over->update_threads > 0) base.update_threads = over->update_threads;
+    if (over->chunk > 0) base.chunk = over->chunk;
+    return base;
+}
+
+CgShape cg_shape(int a, int n, int nnz, int ns, const mw_shape_t *explicit_shape, int opts_chunk)
+{
+    mw_shape_t s{};
+    (void)tuned_get(a, n, nnz, 0, &s);
+    s = overlay(s, explicit_shape);
+    CgShape r;
+    // SpMV: QTW runs best with six resident wavefronts per SIMD (1536
+    // workgroups of four), the other arithmetics with eight (2048), swept
+    // on MI355X for 3D Poisson 128^3 over 512 .. 2048.
+    int cap = s.spmv_grid;
+    if (cap <= 0) {
+        cap = (a == MW_QTW) ? 1536 : MAX_GRID;
+        const int e = env_int("MW_SGRID");
+        if (e >= 8 && e <= MAX_GRID) cap = e;
+    }
+    const int g = persistent_grid(blocks_for(ns, NWAVE));
+    r.sgrid = g < cap ? g : cap;
+    // vector updates: 256 threads, at most 1024 workgroups (best of the
+    // swept 256/512/1024-thread, 256 .. 2048-workgroup shapes on MI355X)
+    r.unt = s.update_threads;
+    if (r.unt <= 0) {
+        r.unt = 256;
+        const int e = env_int("MW_UNT");
+        if (e == 256 || e == 512 || e == 1024) r.unt = e;
+    }
+    int ucap = s.update_grid;
+    if (ucap <= 0) {
+        ucap = 1024;
+        const int e = env_int("MW_UGRID");
+        if (e >= 8 && e <= MAX_GRID) ucap = e;
+    }
+    const int ub = blocks_for(n, r.unt);
+    r.ugrid = ub < ucap ? ub : ucap;
+    r.chunk = opts_chunk > 0 ? opts_chunk : (s.chunk > 0 ? s.chunk : 32);
+    r.chunk += r.chunk & 1;  // even: the parity pattern repeats per chunk
+    return r;
+}
+
+BatchShape batch_shape(int a, int n, int nnz, int nsys, int ns, const mw_shape_t *explicit_shape, int opts_chunk)
+{
+    mw_shape_t s{};
+    (void)tuned_get(a, n, nnz, nsys, &s);
+    s = overlay(s, explicit_shape);
+    BatchShape r;
+    const int g = persistent_grid(blocks_for(ns > 0 ? ns : 1, NWAVE));
+    r.grid = (s.spmv_grid > 0 && s.spmv_grid < g) ? s.spmv_grid : g;
+    r.chunk = opts_chunk > 0 ? opts_chunk : (s.chunk > 0 ? s.chunk : 16);
+    return r;
+}
+
+}  // namespace mwh
+
+extern "C" {
+
+int mw_cg_shape(mw_arith_t a, int32_t n, int32_t nnz, int32_t nsys, mw_shape_t *shape)
+{
+    if (!valid_arith(a) || n <= 0 || nnz < 0 || nsys < 0 || !shape) return MW_EINVAL;
+    mw_shape_t t{};
+    const bool tuned = tuned_get(a, n, nnz, nsys, &t);
+    *shape = mw_shape_t{};
+    if (nsys == 0) {
+        const CgShape c = cg_shape(a, n, nnz, (n + 63) / 64, nullptr, 0);
+        shape->spmv_grid = c.sgrid;
+        shape->update_grid = c.ugrid;
+        shape->update_threads = c.unt;
+        shape->chunk = c.chunk;
+    } else {
+        shape->spmv_grid = tuned ? t.spmv_grid : 0;
+        shape->chunk = tuned && t.chunk > 0 ? t.chunk : 16;
+    }
+    shape->us_per_iteration = tuned ? t.us_per_iteration : 0.0;
+    return tuned ? 1 : 0;
+}
+
+}  // extern "C"

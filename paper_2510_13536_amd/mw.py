@@ -63,10 +63,26 @@ class SpmvPlan(C.Structure):
                 ("slot_mask", _vp), ("ndiag", C.c_int32), ("reserved", C.c_int32), ("csr", Csr)]
 
 
+class Shape(C.Structure):
+    """Launch shape (mw_shape_t); a field <= 0 is "not set"."""
+    _fields_ = [("spmv_grid", C.c_int32), ("update_grid", C.c_int32), ("update_threads", C.c_int32),
+                ("chunk", C.c_int32), ("us_per_iteration", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+    @classmethod
+    def of(cls, shape):
+        """A Shape from a Shape, a dict of its fields, or None."""
+        if shape is None or isinstance(shape, cls):
+            return shape
+        return cls(**{f: shape.get(f, 0) for f, _ in cls._fields_})
+
+
 class CgOpts(C.Structure):
     _fields_ = [("normalize", C.c_int32), ("chunk", C.c_int32), ("history", _vp),
                 ("prof", C.POINTER(CgProf)), ("plan", C.POINTER(SpmvPlan)), ("no_graph", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("shape", C.POINTER(Shape))]
 
 
 class MWError(RuntimeError):
@@ -122,6 +138,10 @@ def lib():
     L.mw_cg_solve_batched.argtypes = [C.c_int, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Csr), _vp, _vp,
                                       C.c_double, C.c_int32, C.POINTER(CgOpts), _vp, _vp, _vp, _vp,
                                       C.POINTER(CgInfo), _vp]
+    L.mw_cg_tune.argtypes = [C.c_int, C.POINTER(Csr), _vp, _vp, C.c_int32, _vp, C.POINTER(Shape), _vp]
+    L.mw_cg_batched_tune.argtypes = [C.c_int, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Csr), _vp, _vp,
+                                     C.c_int32, _vp, C.POINTER(Shape), _vp]
+    L.mw_cg_shape.argtypes = [C.c_int, C.c_int32, C.c_int32, C.c_int32, C.POINTER(Shape)]
     _lib = L
     return L
 
@@ -294,12 +314,13 @@ def cg_workspace(arith, A, device=None):
 
 
 def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0, history=False,
-             workspace=None, prof=None, plan=None, graph=True):
+             workspace=None, prof=None, plan=None, graph=True, shape=None):
     """Solve A x = b by CG in `arith`.  Returns (x (k, n) tensor, info dict).
 
     prof: a CgProf to accumulate per-kernel device times into (optional);
     plan: a Plan of A to reuse (optional; else one is built per call);
-    graph: replay captured chunks (True) or launch kernels directly."""
+    graph: replay captured chunks (True) or launch kernels directly;
+    shape: launch shape (Shape or dict of its fields; optional)."""
     k = WORDS[arith]
     b = b.reshape(-1)
     if not (b.is_cuda and b.dtype == torch.float64 and b.is_contiguous() and b.numel() == A.n):
@@ -312,9 +333,11 @@ def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0
     if workspace is None:
         workspace = cg_workspace(arith, A, b.device)
     hist = torch.zeros(max(int(maxit), 1), dtype=torch.float64, device=b.device) if history else None
+    sh = Shape.of(shape)
     opts = CgOpts(1 if normalize else 0, int(chunk), hist.data_ptr() if hist is not None else None,
                   C.pointer(prof) if prof is not None else None,
-                  C.pointer(plan.c) if plan is not None else None, 0 if graph else 1, 0)
+                  C.pointer(plan.c) if plan is not None else None, 0 if graph else 1, 0,
+                  C.pointer(sh) if sh is not None else None)
     info = CgInfo()
     csr = A.c()
     rc = lib().mw_cg_solve(ARITH[arith], C.byref(csr), _ptr(b), _ptr(x), float(tol), int(maxit),
@@ -328,7 +351,7 @@ def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0
 
 
 def cg_solve_batched(arith, A, sys_row_off, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0,
-                     graph=True, workspace=None):
+                     graph=True, workspace=None, shape=None):
     """Solve the independent systems on the diagonal blocks of A (a DeviceCSR)
     together; sys_row_off: host sequence of nsys + 1 row offsets.
 
@@ -351,7 +374,9 @@ def cg_solve_batched(arith, A, sys_row_off, b, x=None, tol=1e-12, maxit=None, no
     iters = torch.zeros(nsys, dtype=torch.int32, device=b.device)
     status = torch.zeros(nsys, dtype=torch.int32, device=b.device)
     rel = torch.zeros(nsys, dtype=torch.float64, device=b.device)
-    opts = CgOpts(1 if normalize else 0, int(chunk), None, None, None, 0 if graph else 1, 0)
+    sh = Shape.of(shape)
+    opts = CgOpts(1 if normalize else 0, int(chunk), None, None, None, 0 if graph else 1, 0,
+                  C.pointer(sh) if sh is not None else None)
     info = CgInfo()
     csr = A.c()
     rc = lib().mw_cg_solve_batched(ARITH[arith], nsys, off.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(csr),
@@ -360,3 +385,47 @@ def cg_solve_batched(arith, A, sys_row_off, b, x=None, tol=1e-12, maxit=None, no
     _check(rc, "mw_cg_solve_batched")
     return (x, iters.cpu().numpy(), status.cpu().numpy(), rel.cpu().numpy(),
             {"iters": info.iters, "status": STATUS.get(info.status, str(info.status)), "seconds": info.seconds})
+
+
+def cg_tune(arith, A, b, iters=32, workspace=None):
+    """Time candidate launch shapes on A (mw_cg_tune); later cg_solve calls
+    on matrices of A's size use the winner.  Returns its fields (dict)."""
+    b = b.reshape(-1)
+    if not (b.is_cuda and b.dtype == torch.float64 and b.is_contiguous() and b.numel() == A.n):
+        raise MWError("b must be a contiguous float64 CUDA tensor of length n")
+    x = torch.zeros((WORDS[arith], A.n), dtype=torch.float64, device=b.device)
+    if workspace is None:
+        workspace = cg_workspace(arith, A, b.device)
+    best = Shape()
+    csr = A.c()
+    _check(lib().mw_cg_tune(ARITH[arith], C.byref(csr), _ptr(b), _ptr(x), int(iters), _ptr(workspace),
+                            C.byref(best), _stream()), "mw_cg_tune")
+    return best.as_dict()
+
+
+def cg_batched_tune(arith, A, sys_row_off, b, iters=16, workspace=None):
+    """Time candidate slice-kernel grids on a batch (mw_cg_batched_tune);
+    later cg_solve_batched calls on batches of that size use the winner."""
+    import numpy as np
+    off = np.ascontiguousarray(np.asarray(sys_row_off, dtype=np.int32))
+    nsys = off.size - 1
+    b = b.reshape(-1)
+    if not (b.is_cuda and b.dtype == torch.float64 and b.is_contiguous() and b.numel() == A.n):
+        raise MWError("b must be a contiguous float64 CUDA tensor of length n")
+    x = torch.zeros((WORDS[arith], A.n), dtype=torch.float64, device=b.device)
+    if workspace is None:
+        nbytes = lib().mw_cg_batched_workspace_bytes(ARITH[arith], nsys, A.n, A.nnz)
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=b.device)
+    best = Shape()
+    csr = A.c()
+    _check(lib().mw_cg_batched_tune(ARITH[arith], nsys, off.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(csr),
+                                    _ptr(b), _ptr(x), int(iters), _ptr(workspace), C.byref(best), _stream()),
+           "mw_cg_batched_tune")
+    return best.as_dict()
+
+
+def cg_shape(arith, n, nnz, nsys=0):
+    """(tuned, shape dict): the launch shape a solve would use now."""
+    sh = Shape()
+    rc = _check(lib().mw_cg_shape(ARITH[arith], int(n), int(nnz), int(nsys), C.byref(sh)), "mw_cg_shape")
+    return bool(rc), sh.as_dict()

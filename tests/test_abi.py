@@ -72,3 +72,54 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     assert lib.mw_dot(1, 10, bogus, bogus, bogus, None, None) == -1        # workspace
     assert lib.mw_spmv(1, None, bogus, bogus, None) == -1
     assert lib.mw_cg_solve(1, None, bogus, bogus, 1e-12, 10, None, bogus, None, None) == -1
+
+
+class Shape(C.Structure):
+    _fields_ = [("spmv_grid", C.c_int32), ("update_grid", C.c_int32), ("update_threads", C.c_int32),
+                ("chunk", C.c_int32), ("us_per_iteration", C.c_double)]
+
+
+def test_builtin_launch_shapes(lib):
+    # host-side shape resolution: no tuned entry, no GPU work
+    for v in ("MW_SGRID", "MW_UGRID", "MW_UNT"):
+        assert v not in os.environ
+    lib.mw_cg_shape.argtypes = [C.c_int, C.c_int32, C.c_int32, C.c_int32, C.POINTER(Shape)]
+    sh = Shape()
+    n, nnz = 128 ** 3, 14581760
+    for a in range(5):
+        assert lib.mw_cg_shape(a, n, nnz, 0, C.byref(sh)) == 0
+        assert sh.spmv_grid == (1536 if a == 4 else 2048)
+        assert (sh.update_grid, sh.update_threads, sh.chunk, sh.us_per_iteration) == (1024, 256, 32, 0.0)
+    # a small matrix clamps the grids to its tiles: 4096 rows = 16 tiles of 4 slices, 16 update blocks
+    assert lib.mw_cg_shape(4, 4096, 20224, 0, C.byref(sh)) == 0
+    assert (sh.spmv_grid, sh.update_grid) == (16, 16)
+    assert lib.mw_cg_shape(4, 4096, 20224, 3, C.byref(sh)) == 0          # batched: untuned
+    assert (sh.spmv_grid, sh.chunk) == (0, 16)
+    assert lib.mw_cg_shape(7, 4096, 20224, 0, C.byref(sh)) == -1
+    assert lib.mw_cg_shape(4, 0, 20224, 0, C.byref(sh)) == -1
+
+
+def test_invalid_shapes_and_tuner_arguments_rejected_without_gpu(lib):
+    vp = C.c_void_p
+
+    class Csr(C.Structure):
+        _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", vp), ("col_idx", vp), ("val", vp)]
+
+    class Opts(C.Structure):
+        _fields_ = [("normalize", C.c_int32), ("chunk", C.c_int32), ("history", vp), ("prof", vp),
+                    ("plan", vp), ("no_graph", C.c_int32), ("reserved", C.c_int32), ("shape", C.POINTER(Shape))]
+
+    bogus = vp(0x1000)
+    A = Csr(64, 64, bogus, bogus, bogus)
+    lib.mw_cg_solve.argtypes = [C.c_int, C.POINTER(Csr), vp, vp, C.c_double, C.c_int32, C.POINTER(Opts), vp, vp, vp]
+    for bad in (Shape(4, 0, 0, 0, 0.0), Shape(0, 4096, 0, 0, 0.0), Shape(0, 0, 300, 0, 0.0), Shape(0, 0, 0, 5000, 0.0)):
+        o = Opts(1, 0, None, None, None, 0, 0, C.pointer(bad))
+        assert lib.mw_cg_solve(4, C.byref(A), bogus, bogus, 1e-12, 10, C.byref(o), bogus, None, None) == -1
+    lib.mw_cg_tune.argtypes = [C.c_int, C.POINTER(Csr), vp, vp, C.c_int32, vp, C.POINTER(Shape), vp]
+    best = Shape()
+    assert lib.mw_cg_tune(4, C.byref(A), bogus, bogus, 1, bogus, C.byref(best), None) == -1      # iters
+    assert lib.mw_cg_tune(4, C.byref(A), bogus, bogus, 5000, bogus, C.byref(best), None) == -1
+    assert lib.mw_cg_tune(4, C.byref(A), bogus, bogus, 16, bogus, None, None) == -1             # best
+    lib.mw_cg_batched_tune.argtypes = [C.c_int, C.c_int32, vp, C.POINTER(Csr), vp, vp, C.c_int32, vp,
+                                       C.POINTER(Shape), vp]
+    assert lib.mw_cg_batched_tune(4, 1, None, C.byref(A), bogus, bogus, 1, bogus, C.byref(best), None) == -1
