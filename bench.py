@@ -75,7 +75,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bench_batched(mw, P, torch, dev, nsys=512):
+def bench_batched(mw, P, torch, dev, nsys=512, tune=True):
     """512 uneven SPD systems (Poisson 2D/3D and circulant Laplacians, n in
     [1024, 65536]): one batched solve vs a loop of single solves, QTW and
     DW, tol 1e-12."""
@@ -89,6 +89,7 @@ def bench_batched(mw, P, torch, dev, nsys=512):
     for ar in ("qtw", "dw"):
         k = WORDS[ar]
         x = torch.zeros((k, B.A.n), dtype=torch.float64, device=dev)
+        shape = mw.cg_batched_tune(ar, Ad, B.sys_row_off, bd, iters=16) if tune else None
         mw.cg_solve_batched(ar, Ad, B.sys_row_off, bd, x=x, tol=1e-12, maxit=100)
         x.zero_()
         torch.cuda.synchronize()
@@ -105,6 +106,7 @@ def bench_batched(mw, P, torch, dev, nsys=512):
         tl = time.perf_counter() - t0
         its = np.array(its)
         out[ar] = {"batched_s": round(tb, 4), "loop_s": round(tl, 4), "speedup": round(tl / tb, 2),
+                   "tuned_grid": shape["spmv_grid"] if shape else None,
                    "max_iters": int(iters.max()), "mean_iters": round(float(iters.mean()), 1),
                    "all_converged": bool((status == 0).all()),
                    "iters_within_2pct_of_loop": float(np.mean(np.abs(its - iters) <= np.maximum(1, 0.02 * its)))}
@@ -200,6 +202,7 @@ def main():
                     help="arithmetic of the timed solve (the headline metric is QTW)")
     ap.add_argument("--cpu-iters", type=int, default=16)
     ap.add_argument("--prof-steps", type=int, default=2, help="event-timed solves for the roofline")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape tuner (built-in shapes)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -233,6 +236,13 @@ def main():
     ws = mw.cg_workspace(arith, Ad)
     x = torch.zeros((k, A.n), dtype=torch.float64, device=dev)
 
+    # set-up, before the timed region: the launch-shape tuner picks the
+    # grids for this matrix (later solves of its size use them)
+    tuned = None
+    if not args.no_tune:
+        t = time.time()
+        tuned = mw.cg_tune(arith, Ad, bd, iters=32, workspace=ws)
+        log("tuned shape: %s (%.2f s)" % (tuned, time.time() - t))
     for _ in range(args.warmup):
         x.zero_()
         _, info = mw.cg_solve(arith, Ad, bd, x=x, tol=tol, maxit=maxit, workspace=ws)
@@ -291,6 +301,7 @@ def main():
                           "(direct launches, %.2f ms/solve) right after the timed steps" % (args.prof_steps, prof_ms)}
 
     extra = {"iterations": iters, "device_seconds": infos[-1]["seconds"],
+             "launch_shape": mw.cg_shape(arith, A.n, A.nnz)[1], "tuned": tuned is not None,
              "per_iteration_us": 1e3 * ms_per_step / max(iters, 1),
              "event_timed_ms_per_step": round(prof_ms, 3)}
     # every kernel class event-timed, one more solve
@@ -334,19 +345,22 @@ def main():
             kk = WORDS[ar]
             wsa = mw.cg_workspace(ar, Ad)
             xa = torch.zeros((kk, A.n), dtype=torch.float64, device=dev)
+            if not args.no_tune:
+                mw.cg_tune(ar, Ad, bd, iters=32, workspace=wsa)
             mw.cg_solve(ar, Ad, bd, x=xa, tol=tol, maxit=50, workspace=wsa)
             xa.zero_()
             torch.cuda.synchronize()
             s0 = time.perf_counter()
             _, ia = mw.cg_solve(ar, Ad, bd, x=xa, tol=tol, maxit=maxit, workspace=wsa)
             torch.cuda.synchronize()
-            tts[ar] = {"seconds": round(time.perf_counter() - s0, 5), "iters": ia["iters"], "status": ia["status"]}
+            tts[ar] = {"seconds": round(time.perf_counter() - s0, 5), "iters": ia["iters"], "status": ia["status"],
+                       "shape": mw.cg_shape(ar, A.n, A.nnz)[1]}
             log("%s: %s" % (ar, tts[ar]))
         extra["time_to_solution"] = tts
         extra["qtw_over_dw"] = round(tts["qtw"]["seconds"] / tts["dw"]["seconds"], 3)
 
     if not args.quick:
-        extra["batched"] = bench_batched(mw, P, torch, dev)
+        extra["batched"] = bench_batched(mw, P, torch, dev, tune=not args.no_tune)
         extra["adjoint"] = bench_adjoint(mw, P, torch, dev)
         extra["illcond"] = bench_illcond(mw, P, torch, dev)
 
