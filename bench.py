@@ -155,6 +155,27 @@ def bench_illcond(mw, P, torch, dev, maxit=20000):
     return out
 
 
+def bench_normalisation(mw, torch, Ad, bd, n, maxit=2000):
+    """3D Poisson 128^3, QDW and QTW, tol 1e-12: r normalised every K-th
+    iteration (K = 1 is the paper's placement, 0 never): status, iterations,
+    time."""
+    out = {"workload": "3D Poisson 128^3, tol 1e-12, at most %d iterations" % maxit}
+    for ar in ("qdw", "qtw"):
+        x = torch.zeros((WORDS[ar], n), dtype=torch.float64, device=bd.device)
+        row = {}
+        for K in (1, 2, 4, 8, 0):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = mw.cg_solve(ar, Ad, bd, x=x, tol=1e-12, maxit=maxit, normalize=K)
+            torch.cuda.synchronize()
+            row["K=%d" % K] = {"status": info["status"], "iters": info["iters"], "rel_res": info["rel_res"],
+                               "seconds": round(time.perf_counter() - t0, 4)}
+        out[ar] = row
+        log("normalisation %s: %s" % (ar, row))
+    return out
+
+
 def bench_adjoint(mw, P, torch, dev):
     """A(theta) = 3D Laplacian 100^3 + diag(theta), loss 0.5||x - x_t||^2,
     QTW: forward + adjoint solve (all 2n gradient entries) vs the cost of
@@ -363,6 +384,7 @@ def main():
         extra["batched"] = bench_batched(mw, P, torch, dev, tune=not args.no_tune)
         extra["adjoint"] = bench_adjoint(mw, P, torch, dev)
         extra["illcond"] = bench_illcond(mw, P, torch, dev)
+        extra["normalisation_every_K"] = bench_normalisation(mw, torch, Ad, bd, A.n)
 
     cpu = None
     if not args.no_cpu:

@@ -165,10 +165,12 @@ typedef struct {
 
 /* Solver options (host memory); pass NULL for the defaults. */
 typedef struct {
-    int32_t normalize;  /* QDW/QTW: 1 (default) normalises r after its
-                           update once per iteration (Sec. IV-D); 0 skips
-                           it (the "-NN" variants of Sec. V-B).  Ignored by
-                           the other arithmetics.                            */
+    int32_t normalize;  /* QDW/QTW: K >= 1 normalises r right after its
+                           update in iterations K, 2K, ... -- 1 (default)
+                           is every iteration (Sec. IV-D), other K explore
+                           the frequency Sec. VI leaves open; 0 never (the
+                           "-NN" variants of Sec. V-B).  Ignored by the
+                           other arithmetics; < 0: MW_EINVAL.              */
     int32_t chunk;      /* iterations launched between two host checks of
                            convergence; 0 = library default               */
     double *history;    /* optional DEVICE array of maxit doubles: entry i

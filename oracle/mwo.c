@@ -560,7 +560,10 @@ typedef struct {
  *     q = A p;  sigma = p^T q;  (sigma <= 0 or not finite: breakdown)
  *     alpha = rho / sigma
  *     x = x + alpha p;  r = r + (-(alpha q))
- *     QDW/QTW with normalise != 0: r = normalise(r)       (Sec. IV-D)
+ *     QDW/QTW: r = normalise(r) when normalise_r = K > 0 and the iteration
+ *       number (1, 2, ...) is a multiple of K; K = 1, every iteration, is
+ *       Sec. IV-D; K = 0 never (the "-NN" variants of Sec. V-B); other K
+ *       explore the frequency the paper leaves open (Sec. VI)
  *     rho' = r^T r;  iters++
  *     sqrt(fp64(rho')) / nb < tol: converged               (Sec. IV-C)
  *     iters == maxit: not converged
@@ -619,7 +622,7 @@ int mwo_cg_solve(int arith, long n, const int32_t *row_ptr, const int32_t *col,
                 mwv pi = mw_load(k, p, n, i), qi = mw_load(k, q, n, i);
                 mw_store(k, x, n, i, mw_add(arith, mw_load(k, x, n, i), mw_mul(arith, alpha, pi)));
                 mwv ri = mw_add(arith, mw_load(k, r, n, i), mw_neg(mw_mul(arith, alpha, qi)));
-                if (quasi && normalise_r) ri = mw_normalise(arith, ri);
+                if (quasi && normalise_r > 0 && (info->iters + 1) % normalise_r == 0) ri = mw_normalise(arith, ri);
                 mw_store(k, r, n, i, ri);
             }
         }

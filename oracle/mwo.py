@@ -179,7 +179,10 @@ def axpy(arith, alpha, x, y):
 
 
 def cg_solve(arith, A, b, x0=None, tol=1e-12, maxit=None, normalise=True, history=False):
-    """CG per the oracle.  Returns (x (k, n), info dict)."""
+    """CG per the oracle.  Returns (x (k, n), info dict).
+
+    normalise (QDW/QTW): True / 1 normalises r every iteration (Sec. IV-D),
+    False / 0 never; an integer K > 1 in iterations K, 2K, ..."""
     k = WORDS[arith]
     n, rp, ci, va = _csr(A)
     b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
@@ -191,7 +194,7 @@ def cg_solve(arith, A, b, x0=None, tol=1e-12, maxit=None, normalise=True, histor
     info = CGInfo()
     hist = np.zeros(max(int(maxit), 1)) if history else None
     rc = lib().mwo_cg_solve(ARITH[arith], n, _i(rp), _i(ci), _d(va), _d(b), _d(x), float(tol),
-                            int(maxit), 1 if normalise else 0, C.byref(info),
+                            int(maxit), int(normalise), C.byref(info),
                             _d(hist) if history else None)
     _check(rc)
     out = {"iters": info.iters, "status": STATUS[info.status], "status_code": info.status,

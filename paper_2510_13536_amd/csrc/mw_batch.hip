@@ -251,13 +251,15 @@ __global__ void __launch_bounds__(BNT) mw_batch_step_r_kernel(BatchDev d, const 
 {
     constexpr int K = words(A);
     const int lane = threadIdx.x & 63, wave = wave_id();
-    const bool norm = is_quasi(A) && *d.normalize;
+    // quasi types: normalise in iterations NK, 2 NK, ... of each system
+    const int NK = *d.normalize;
     const TileRange tr = slice_tiles(d.ns);
     for (int t = tr.first; t < tr.end; t += tr.step) {
         const int s = t * NWAVE + wave;
         if (s >= d.ns) continue;
         const int sys = d.slice_sys[s];
         if (!d.active[sys]) continue;
+        const bool norm = is_quasi(A) && NK > 0 && (d.iters[sys] + 1) % NK == 0;
         const Num<A> al = load_scalar<A>(d.alpha + (long)sys * K);
         Num<A> rr = zero<A>();
         if (lane < d.slice_rows[s]) {
@@ -643,7 +645,7 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
                         int32_t *iters, int32_t *status, double *rel_res, mw_cg_info_t *info, void *stream)
 {
     if (!batched_args_ok(a, nsys, sys_row_off, A, b, x, workspace) || !(tol >= 0.0) || maxit < 0) return MW_EINVAL;
-    if (opts && !shape_valid(opts->shape)) return MW_EINVAL;
+    if (opts && (!shape_valid(opts->shape) || opts->normalize < 0)) return MW_EINVAL;
     MW_DISPATCH(a, batched_a, nsys, sys_row_off, A, b, x, tol, maxit, opts, workspace, iters, status, rel_res, info,
                 (hipStream_t)stream);
 }

@@ -140,7 +140,10 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
     __syncthreads();
     if (s_brk) return;
     const Num<A> al = s_alpha;
-    const bool norm = is_quasi(A) && st->normalize;
+    // quasi types: normalise in iterations NK, 2 NK, ... (NK = 1, every
+    // iteration, is Sec. IV-D; 0 never)
+    const int NK = st->normalize;
+    const bool norm = is_quasi(A) && NK > 0 && (st->iters[par ^ 1] + 1) % NK == 0;
     const TileWalk tw = xcd_walk((n + UNT - 1) / UNT, rev);
     Num<A> rr = zero<A>();
     for (int m = 0; m < tw.count; ++m) {
@@ -534,7 +537,7 @@ int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, dou
     if (!valid_arith(a) || !valid_csr(A) || !b || !x || !workspace || !(tol >= 0.0) || maxit < 0)
         return MW_EINVAL;
     if (opts && opts->plan && (opts->plan->n != A->n || opts->plan->csr.row_ptr != A->row_ptr)) return MW_EINVAL;
-    if (opts && !shape_valid(opts->shape)) return MW_EINVAL;
+    if (opts && (!shape_valid(opts->shape) || opts->normalize < 0)) return MW_EINVAL;
     MW_DISPATCH(a, cg_a, A, b, x, tol, maxit, opts, workspace, info, (hipStream_t)stream);
 }
 

@@ -334,7 +334,7 @@ def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0
         workspace = cg_workspace(arith, A, b.device)
     hist = torch.zeros(max(int(maxit), 1), dtype=torch.float64, device=b.device) if history else None
     sh = Shape.of(shape)
-    opts = CgOpts(1 if normalize else 0, int(chunk), hist.data_ptr() if hist is not None else None,
+    opts = CgOpts(int(normalize), int(chunk), hist.data_ptr() if hist is not None else None,
                   C.pointer(prof) if prof is not None else None,
                   C.pointer(plan.c) if plan is not None else None, 0 if graph else 1, 0,
                   C.pointer(sh) if sh is not None else None)
@@ -375,7 +375,7 @@ def cg_solve_batched(arith, A, sys_row_off, b, x=None, tol=1e-12, maxit=None, no
     status = torch.zeros(nsys, dtype=torch.int32, device=b.device)
     rel = torch.zeros(nsys, dtype=torch.float64, device=b.device)
     sh = Shape.of(shape)
-    opts = CgOpts(1 if normalize else 0, int(chunk), None, None, None, 0 if graph else 1, 0,
+    opts = CgOpts(int(normalize), int(chunk), None, None, None, 0 if graph else 1, 0,
                   C.pointer(sh) if sh is not None else None)
     info = CgInfo()
     csr = A.c()

@@ -309,6 +309,35 @@ def test_cg_history_and_nn(mw):
     assert nn["status"] != "ok" and on["status"] != "ok"
 
 
+@pytest.mark.parametrize("arith", ["qdw", "qtw"])
+def test_cg_normalisation_frequency(mw, arith):
+    """normalize = K (r normalised in iterations K, 2K, ...): the GPU takes
+    the same iterations as the oracle.  C1 at K = 2 breaks down near
+    iteration 75 in both, so 60 iterations are compared (tol = 0): same
+    status and count, true residual within 10x of the oracle's; plus the
+    bitwise consequences of the schedule on the GPU itself."""
+    A, b, _ = P.case_poisson2d_64()
+    Ad = mw.DeviceCSR.from_host(A)
+    bd = dev(b)
+    xo, io = O.cg_solve(arith, A, b, tol=0.0, maxit=60, normalise=2)
+    xg, ig = mw.cg_solve(arith, Ad, bd, tol=0.0, maxit=60, normalize=2)
+    assert ig["status"] == io["status"] == "not_converged" and ig["iters"] == io["iters"] == 60
+    tro = O.true_residual(arith, A, b, xo)
+    trg = O.true_residual(arith, A, b, host(xg))
+    assert trg <= 10 * tro, (trg, tro)
+    one2, _ = mw.cg_solve(arith, Ad, bd, tol=0.0, maxit=1, normalize=2)
+    one0, _ = mw.cg_solve(arith, Ad, bd, tol=0.0, maxit=1, normalize=0)
+    assert np.array_equal(host(one2).view(np.uint64), host(one0).view(np.uint64))
+    three2, _ = mw.cg_solve(arith, Ad, bd, tol=0.0, maxit=3, normalize=2)
+    three0, _ = mw.cg_solve(arith, Ad, bd, tol=0.0, maxit=3, normalize=0)
+    assert not np.array_equal(host(three2).view(np.uint64), host(three0).view(np.uint64))
+    big, ib = mw.cg_solve(arith, Ad, bd, tol=1e-12, maxit=300, normalize=10 ** 6)
+    nn, inn = mw.cg_solve(arith, Ad, bd, tol=1e-12, maxit=300, normalize=0)
+    assert ib["iters"] == inn["iters"] and np.array_equal(host(big).view(np.uint64), host(nn).view(np.uint64))
+    with pytest.raises(mw.MWError):
+        mw.cg_solve(arith, Ad, bd, normalize=-1)
+
+
 # ----------------------------------------------------------- planned SpMV
 
 @pytest.mark.parametrize("arith", ARITHS)

@@ -158,3 +158,38 @@ def test_quasi_without_normalisation_degrades():
     assert ok["status"] == "ok"
     _, nn = O.cg_solve("qdw", A, b, tol=1e-28, maxit=4000, normalise=False)
     assert nn["status"] != "ok" or nn["iters"] >= ok["iters"]
+
+
+@pytest.mark.parametrize("arith", ["qdw", "qtw"])
+def test_normalisation_frequency_modes(arith):
+    """normalise = K: r normalised in iterations K, 2K, ... .  K = 1 is the
+    paper's placement (every iteration, Sec. IV-D) and K = 0 its -NN
+    variants; a K beyond the last iteration never fires, so it must equal
+    K = 0 bit for bit, and one iteration with K = 2 must equal one
+    un-normalised iteration while two must not."""
+    A = P.poisson2d(20, 18)
+    b = A.matvec(P.integer_vector(A.n, seed=4))
+    x1, i1 = O.cg_solve(arith, A, b, tol=1e-20, maxit=200, normalise=1)
+    xt, it = O.cg_solve(arith, A, b, tol=1e-20, maxit=200, normalise=True)
+    assert np.array_equal(x1.view(np.uint64), xt.view(np.uint64)) and i1 == it
+    x0, i0 = O.cg_solve(arith, A, b, tol=1e-20, maxit=200, normalise=0)
+    xb, ib = O.cg_solve(arith, A, b, tol=1e-20, maxit=200, normalise=10 ** 6)
+    assert np.array_equal(x0.view(np.uint64), xb.view(np.uint64)) and i0 == ib
+    ya, _ = O.cg_solve(arith, A, b, tol=0.0, maxit=1, normalise=2)
+    yb, _ = O.cg_solve(arith, A, b, tol=0.0, maxit=1, normalise=0)
+    assert np.array_equal(ya.view(np.uint64), yb.view(np.uint64))
+    # the second iteration normalises r before rho' and beta: x after the
+    # third iteration differs from the never-normalised run
+    za, _ = O.cg_solve(arith, A, b, tol=0.0, maxit=3, normalise=2)
+    zb, _ = O.cg_solve(arith, A, b, tol=0.0, maxit=3, normalise=0)
+    assert not np.array_equal(za.view(np.uint64), zb.view(np.uint64))
+    # normalisation is error-free, so while rounding stays far below FP64
+    # resolution the FP64-rounded residuals of every K coincide; only the
+    # every-iteration placement reaches 1e-20 (K = 2, 4 break down, as the
+    # -NN variants fail in Sec. V-B)
+    _, h1 = O.cg_solve(arith, A, b, tol=1e-20, maxit=400, normalise=1, history=True)
+    assert h1["status"] == "ok"
+    for K in (2, 4):
+        _, hK = O.cg_solve(arith, A, b, tol=1e-20, maxit=400, normalise=K, history=True)
+        assert np.array_equal(hK["history"][:40], h1["history"][:40])
+        assert hK["status"] != "ok"
