@@ -176,6 +176,54 @@ def bench_normalisation(mw, torch, Ad, bd, n, maxit=2000):
     return out
 
 
+def true_rel_residual(mw, torch, Ad, bd, x):
+    """||b - A x|| / ||b|| for a solution in any arithmetic, with the product
+    and the difference formed in QTW and the dots in TW (about 48
+    significant digits), so residuals far below FP64 resolution are
+    resolved."""
+    n = x.shape[1]
+    x3 = torch.zeros((3, n), dtype=torch.float64, device=bd.device)
+    x3[:x.shape[0]] = x
+    b3 = torch.zeros_like(x3)
+    b3[0] = bd
+    y = mw.spmv("qtw", Ad, x3)
+    r = mw.elementwise("qtw", "add", b3, mw.elementwise("qtw", "neg", y))
+    # b - A x cancels its leading words: renormalise (TW) so the leading word
+    # carries the value before squaring (a product of quasi triples drops
+    # the third words' product)
+    r = mw.elementwise("tw", "norm", r)
+    rr = float(mw.dot("tw", r, r).sum().item())
+    bb = float(mw.dot("tw", b3, b3).sum().item())
+    return (max(rr, 0.0) / bb) ** 0.5
+
+
+def bench_tolerances(mw, torch, Ad, bd, n, maxit=3000):
+    """3D Poisson 128^3 at tolerances beyond FP64 (1e-16, 1e-24, 1e-32), every
+    arithmetic, at most `maxit` iterations: status, iterations, time, the
+    recursive and the true relative residual (true_rel_residual), and the
+    recursive relative-residual history of the 1e-32 runs every 50
+    iterations."""
+    out = {"workload": "3D Poisson 128^3, at most %d iterations" % maxit}
+    for ar in WORDS:
+        x = torch.zeros((WORDS[ar], n), dtype=torch.float64, device=bd.device)
+        row = {}
+        for tol in (1e-16, 1e-24, 1e-32):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = mw.cg_solve(ar, Ad, bd, x=x, tol=tol, maxit=maxit, history=(tol == 1e-32))
+            torch.cuda.synchronize()
+            row["tol_%g" % tol] = {"status": info["status"], "iters": info["iters"], "rel_res": info["rel_res"],
+                                   "seconds": round(time.perf_counter() - t0, 4),
+                                   "true_rel_res": true_rel_residual(mw, torch, Ad, bd, x)}
+            if tol == 1e-32:
+                h = info["history"]
+                row["history_every_50"] = [float("%.3e" % v) for v in h[49::50]]
+        out[ar] = row
+        log("tolerances %s: %s" % (ar, {k: v for k, v in row.items() if k != "history_every_50"}))
+    return out
+
+
 def bench_adjoint(mw, P, torch, dev):
     """A(theta) = 3D Laplacian 100^3 + diag(theta), loss 0.5||x - x_t||^2,
     QTW: forward + adjoint solve (all 2n gradient entries) vs the cost of
@@ -385,6 +433,7 @@ def main():
         extra["adjoint"] = bench_adjoint(mw, P, torch, dev)
         extra["illcond"] = bench_illcond(mw, P, torch, dev)
         extra["normalisation_every_K"] = bench_normalisation(mw, torch, Ad, bd, A.n)
+        extra["tolerances"] = bench_tolerances(mw, torch, Ad, bd, A.n)
 
     cpu = None
     if not args.no_cpu:
