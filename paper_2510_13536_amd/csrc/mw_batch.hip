@@ -50,6 +50,9 @@ struct BatchDev {
     double *nb, *rel;              // nsys each
     int32_t *active, *xdue, *iters, *status;  // nsys each
     int32_t *n_active;             // running systems
+    int32_t *alist;                // slices of the systems running at the start of
+                                   // the current chunk (nullptr: every slice)
+    int32_t *n_alist;              // their count
     const double *tol;             // solve parameters in device memory
     const int32_t *maxit, *normalize;
     int nsys, ns, n;
@@ -58,6 +61,10 @@ struct BatchDev {
 constexpr int BNT = NT;  // workgroup of the slice kernels: NWAVE slices
 
 __device__ __forceinline__ TileRange slice_tiles(int ns) { return xcd_tiles((ns + NWAVE - 1) / NWAVE); }
+
+// The slices a slice kernel walks: the running systems' list, or all.
+__device__ __forceinline__ int slice_count(const BatchDev &d) { return d.alist ? *d.n_alist : d.ns; }
+__device__ __forceinline__ int slice_at(const BatchDev &d, int idx) { return d.alist ? d.alist[idx] : idx; }
 
 // ------------------------------------------------------------ plan build
 
@@ -108,10 +115,12 @@ __global__ void __launch_bounds__(BNT) mw_batch_spmv_kernel(BatchDev d, const do
 {
     constexpr int K = words(A);
     const int lane = threadIdx.x & 63, wave = wave_id();
-    const TileRange tr = slice_tiles(d.ns);
+    const int nl = slice_count(d);
+    const TileRange tr = slice_tiles(nl);
     for (int t = tr.first; t < tr.end; t += tr.step) {
-        const int s = t * NWAVE + wave;
-        if (s >= d.ns) continue;
+        const int idx = t * NWAVE + wave;
+        if (idx >= nl) continue;
+        const int s = slice_at(d, idx);
         if constexpr (MODE == 1) {
             if (!d.active[d.slice_sys[s]]) continue;
         }
@@ -151,10 +160,12 @@ __global__ void __launch_bounds__(BNT) mw_batch_init_kernel(BatchDev d, const do
 {
     constexpr int K = words(A);
     const int lane = threadIdx.x & 63, wave = wave_id();
-    const TileRange tr = slice_tiles(d.ns);
+    const int nl = slice_count(d);
+    const TileRange tr = slice_tiles(nl);
     for (int t = tr.first; t < tr.end; t += tr.step) {
-        const int s = t * NWAVE + wave;
-        if (s >= d.ns) continue;
+        const int idx = t * NWAVE + wave;
+        if (idx >= nl) continue;
+        const int s = slice_at(d, idx);
         Num<A> rr = zero<A>(), bb = zero<A>();
         if (lane < d.slice_rows[s]) {
             const long i = (long)d.slice_row0[s] + lane;
@@ -253,10 +264,12 @@ __global__ void __launch_bounds__(BNT) mw_batch_step_r_kernel(BatchDev d, const 
     const int lane = threadIdx.x & 63, wave = wave_id();
     // quasi types: normalise in iterations NK, 2 NK, ... of each system
     const int NK = *d.normalize;
-    const TileRange tr = slice_tiles(d.ns);
+    const int nl = slice_count(d);
+    const TileRange tr = slice_tiles(nl);
     for (int t = tr.first; t < tr.end; t += tr.step) {
-        const int s = t * NWAVE + wave;
-        if (s >= d.ns) continue;
+        const int idx = t * NWAVE + wave;
+        if (idx >= nl) continue;
+        const int s = slice_at(d, idx);
         const int sys = d.slice_sys[s];
         if (!d.active[sys]) continue;
         const bool norm = is_quasi(A) && NK > 0 && (d.iters[sys] + 1) % NK == 0;
@@ -308,10 +321,12 @@ __global__ void __launch_bounds__(BNT) mw_batch_step_p_kernel(BatchDev d, const 
 {
     constexpr int K = words(A);
     const int lane = threadIdx.x & 63, wave = wave_id();
-    const TileRange tr = slice_tiles(d.ns);
+    const int nl = slice_count(d);
+    const TileRange tr = slice_tiles(nl);
     for (int t = tr.first; t < tr.end; t += tr.step) {
-        const int s = t * NWAVE + wave;
-        if (s >= d.ns) continue;
+        const int idx = t * NWAVE + wave;
+        if (idx >= nl) continue;
+        const int s = slice_at(d, idx);
         const int sys = d.slice_sys[s];
         const bool run = d.active[sys];
         if (!run && !d.xdue[sys]) continue;
@@ -327,11 +342,33 @@ __global__ void __launch_bounds__(BNT) mw_batch_step_p_kernel(BatchDev d, const 
     }
 }
 
+// The running systems' slices, rebuilt at the start of every chunk so the
+// slice kernels of a batch's tail walk only those.  The list order is
+// free: every per-slice result is stored by slice index.
+__global__ void __launch_bounds__(BNT) mw_batch_list_reset_kernel(BatchDev d)
+{
+    if (threadIdx.x == 0) *d.n_alist = 0;
+}
+
+__global__ void __launch_bounds__(BNT) mw_batch_list_kernel(BatchDev d)
+{
+    const int lane = threadIdx.x & 63;
+    for (int s0 = blockIdx.x * BNT; s0 < d.ns; s0 += gridDim.x * BNT) {
+        const int s = s0 + (int)threadIdx.x;
+        const bool run = s < d.ns && d.active[d.slice_sys[s]];
+        const uint64_t m = __ballot(run);
+        int base = 0;
+        if (lane == 0 && m) base = atomicAdd(d.n_alist, __popcll(m));
+        base = __shfl(base, 0, 64);
+        if (run) d.alist[base + __popcll(m & ((1ull << lane) - 1))] = s;
+    }
+}
+
 // ------------------------------------------------------------ host side
 
 struct BatchLayout {
     size_t r, p, q, slots_a, slots_b, sys_slice_off, slice_sys, slice_row0, slice_rows, dscal, iscal, params, width,
-        slice_ptr, total, soff, smask, col, val, bytes;
+        slice_ptr, total, alist, n_alist, soff, smask, col, val, bytes;
     long long ns_max, cap;
 };
 
@@ -362,6 +399,8 @@ BatchLayout batch_layout(int a, int32_t nsys, int32_t n, int32_t nnz)
     L.width = take(sizeof(int32_t) * L.ns_max);
     L.slice_ptr = take(sizeof(int32_t) * (L.ns_max + 1));
     L.total = take(sizeof(long long));
+    L.alist = take(sizeof(int32_t) * L.ns_max);
+    L.n_alist = take(sizeof(int32_t));
     L.soff = take(sizeof(int32_t) * (L.cap / 64 + 8));
     L.smask = take(sizeof(uint64_t) * (L.cap / 64 + 8));
     L.col = take(sizeof(int32_t) * L.cap);
@@ -428,6 +467,9 @@ template <int A>
 int enqueue_batch_chunk(const BatchDev &d, int chunk, int g, double *r, double *p, double *q, double *x, double *sa,
                         double *sb, hipStream_t s)
 {
+    const int gl = blocks_for(d.ns > 0 ? d.ns : 1, BNT) < 1024 ? blocks_for(d.ns > 0 ? d.ns : 1, BNT) : 1024;
+    hipLaunchKernelGGL(mw_batch_list_reset_kernel, dim3(1), dim3(BNT), 0, s, d);
+    hipLaunchKernelGGL(mw_batch_list_kernel, dim3(gl), dim3(BNT), 0, s, d);
     for (int it = 0; it < chunk; ++it) {
         hipLaunchKernelGGL((mw_batch_spmv_kernel<A, 1>), dim3(g), dim3(BNT), 0, s, d, p, q, sa);
         hipLaunchKernelGGL((mw_batch_alpha_kernel<A>), dim3(d.nsys), dim3(BNT), 0, s, d, sa);
@@ -487,6 +529,8 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     d.sp = (int32_t *)(base + L.slice_ptr);
     d.sc = (int32_t *)(base + L.col);
     d.sv = (double *)(base + L.val);
+    d.alist = nullptr;  // set for the iteration chunks, after the set-up kernels
+    d.n_alist = (int32_t *)(base + L.n_alist);
     d.soff = (int32_t *)(base + L.soff);
     d.smask = (uint64_t *)(base + L.smask);
     double *dscal = (double *)(base + L.dscal);
@@ -552,6 +596,7 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     HIP_TRY(hipMemcpyAsync(hcount, d.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
 
+    d.alist = (int32_t *)(base + L.alist);
     int chunks = 0;
     if (*hcount > 0 && use_graph) {
         BatchGraph &G = batch_graph();
