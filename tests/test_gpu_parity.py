@@ -258,6 +258,30 @@ def test_cg_poisson3d_small(mw, arith):
     cg_parity(mw, arith, A, b, 1e-12)
 
 
+@pytest.mark.parametrize("arith", ARITHS)
+def test_cg_initial_guess(mw, arith):
+    """A nonzero x0 (random multi-word planes): r0 = b - A x0 on both sides."""
+    A, b, _ = P.case_poisson3d(nx=16)
+    k = O.WORDS[arith]
+    x0 = rand_mw(np.random.default_rng(17), k, A.n, emin=-2, emax=2)
+    xo, io = O.cg_solve(arith, A, b, x0=x0, tol=1e-12)
+    xg, ig = mw.cg_solve(arith, mw.DeviceCSR.from_host(A), dev(b), x=dev(x0), tol=1e-12)
+    assert ig["status"] == io["status"] == "ok"
+    assert abs(ig["iters"] - io["iters"]) <= max(1, int(0.02 * io["iters"]))
+    tro = O.true_residual(arith, A, b, xo)
+    trg = O.true_residual(arith, A, b, host(xg))
+    assert trg <= 10 * tro, (trg, tro)
+
+
+@pytest.mark.parametrize("n", [1, 5, 65, 64 * 16 + 1])
+def test_cg_tiny_and_ragged_sizes(mw, n):
+    """Systems smaller than one slice or tile, and one row past a boundary."""
+    A = P.poisson1d(n)
+    b = A.matvec(np.random.default_rng(n).uniform(-1, 1, n))
+    for arith in ("fp64", "qtw"):
+        cg_parity(mw, arith, A, b, 1e-12)
+
+
 @pytest.mark.parametrize("arith", ["fp64", "dw", "qtw"])
 def test_cg_tight_tolerance(mw, arith):
     A = P.poisson2d(40, 30)

@@ -193,3 +193,23 @@ def test_normalisation_frequency_modes(arith):
         _, hK = O.cg_solve(arith, A, b, tol=1e-20, maxit=400, normalise=K, history=True)
         assert np.array_equal(hK["history"][:40], h1["history"][:40])
         assert hK["status"] != "ok"
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_initial_guess(arith):
+    """Alg. 1 starts from the given x0 (r0 = b - A x0).  With x0 the exact
+    (integer, so representable) solution r0 = 0: no iteration, x0 returned
+    unchanged; from x0 = x* + a perturbation the solve converges to x*."""
+    A = P.poisson2d(15, 13)
+    xstar = P.integer_vector(A.n, seed=6)
+    b = A.matvec(xstar)
+    k = O.WORDS[arith]
+    x0 = np.zeros((k, A.n))
+    x0[0] = xstar
+    x, info = O.cg_solve(arith, A, b, x0=x0, tol=1e-12)
+    assert info["iters"] == 0 and info["status"] == "ok"
+    assert np.array_equal(x, x0)
+    x0[0] += np.random.default_rng(7).standard_normal(A.n)
+    x, info = O.cg_solve(arith, A, b, x0=x0, tol=1e-12)
+    assert info["status"] == "ok" and 0 < info["iters"] < 500
+    assert np.max(np.abs(x.sum(axis=0) - xstar)) < 1e-8
