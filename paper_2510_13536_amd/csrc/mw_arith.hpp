@@ -102,8 +102,13 @@ __device__ __forceinline__ void tw_renorm(double &c1, double &c2, double &c3)
     double s, e1, e2;
     two_sum(c2, c3, s, e2);
     two_sum(c1, s, s, e1);
-    double t0, f1;
-    two_sum(s, e1, t0, f1);
+    // (t0, f1) = TwoSum(s, e1) of the branch step.  (s, e1) is already a
+    // TwoSum result: |e1| <= ulp(s)/2 with ties rounding to even, so for
+    // finite values t0 = s and f1 = e1 exactly; t0 = fl(s + e1) is still
+    // formed, which also keeps the non-finite cases (where e1 is NaN) as
+    // the full TwoSum gives them.
+    const double t0 = s + e1;
+    const double f1 = e1;
     const bool carry = (f1 != 0.0);
     double t1, f2;
     two_sum(carry ? f1 : t0, e2, t1, f2);
