@@ -114,6 +114,15 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
         if (blockIdx.x == 0 && threadIdx.x == 0) st->run[par] = 0;
         return;
     }
+    // the first tile's operands are loaded before the reduction, so that
+    // their latency overlaps it
+    const TileWalk tw = xcd_walk((n + UNT - 1) / UNT, rev);
+    const long i0 = tw.count > 0 ? (long)tw[0] * UNT + threadIdx.x : (long)n;
+    Num<A> q0 = zero<A>(), r0 = zero<A>();
+    if (i0 < n) {
+        q0 = load<A>(q, n, i0);
+        r0 = load<A>(r, n, i0);
+    }
     const Num<A> sigma = reduce_slots<A, UNT>(nslots_in, slots_in);
     if (threadIdx.x == 0) {
         const double s64 = to_fp64<A>(sigma);
@@ -144,12 +153,13 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
     // iteration, is Sec. IV-D; 0 never)
     const int NK = st->normalize;
     const bool norm = is_quasi(A) && NK > 0 && (st->iters[par ^ 1] + 1) % NK == 0;
-    const TileWalk tw = xcd_walk((n + UNT - 1) / UNT, rev);
     Num<A> rr = zero<A>();
     for (int m = 0; m < tw.count; ++m) {
         const long i = (long)tw[m] * UNT + threadIdx.x;
         if (i >= n) continue;
-        Num<A> ri = axmy_term<A>(al, load<A>(q, n, i), load<A>(r, n, i));
+        const Num<A> qi = m == 0 ? q0 : load<A>(q, n, i);
+        const Num<A> rv = m == 0 ? r0 : load<A>(r, n, i);
+        Num<A> ri = axmy_term<A>(al, qi, rv);
         if (norm) ri = normalise<A>(ri);
         store<A>(r, n, i, ri);
         rr = dot_step<A>(rr, ri, ri);
@@ -173,6 +183,16 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
     if (!st->run[par ^ 1] || st->brk[par]) {
         if (blockIdx.x == 0 && threadIdx.x == 0) st->run[par] = 0;
         return;
+    }
+    // the first tile's operands are loaded before the reduction (as in
+    // step r)
+    const TileWalk tw = xcd_walk((n + UNT - 1) / UNT, rev);
+    const long i0 = tw.count > 0 ? (long)tw[0] * UNT + threadIdx.x : (long)n;
+    Num<A> p0 = zero<A>(), x0 = zero<A>(), r0 = zero<A>();
+    if (i0 < n) {
+        p0 = load_il<A>(p, n, i0);
+        x0 = load<A>(x, n, i0);
+        r0 = load<A>(r, n, i0);
     }
     const Num<A> rho_new = reduce_slots<A, UNT>(nslots_in, slots_in);
     if (threadIdx.x == 0) {
@@ -203,13 +223,16 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
     const bool stop = s_stop;
     const Num<A> be = s_beta;
     const Num<A> al = load_scalar<A>(st->alpha[par]);
-    const TileWalk tw = xcd_walk((n + UNT - 1) / UNT, rev);
     for (int m = 0; m < tw.count; ++m) {
         const long i = (long)tw[m] * UNT + threadIdx.x;
         if (i >= n) continue;
-        const Num<A> pi = load_il<A>(p, n, i);
-        store<A>(x, n, i, axpy_term<A>(al, pi, load<A>(x, n, i)));
-        if (!stop) store_il<A>(p, n, i, axpy_term<A>(be, pi, load<A>(r, n, i)));
+        const Num<A> pi = m == 0 ? p0 : load_il<A>(p, n, i);
+        const Num<A> xi = m == 0 ? x0 : load<A>(x, n, i);
+        store<A>(x, n, i, axpy_term<A>(al, pi, xi));
+        if (!stop) {
+            const Num<A> rv = m == 0 ? r0 : load<A>(r, n, i);
+            store_il<A>(p, n, i, axpy_term<A>(be, pi, rv));
+        }
     }
 }
 
