@@ -361,8 +361,9 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
  * iterations; x is scratch and overwritten, b as for mw_cg_solve, b != 0)
  * for each candidate shape -- SpMV grids 1024, 1280, 1536, 1792, 2048 x
  * update grids 512, 1024, 2048 at 256 threads, candidates that clamp to
- * the same launch counted once -- on `stream`'s device, each timed on its
- * second run (the first captures its graph).  The fastest goes to *best
+ * the same launch counted once -- on `stream`'s device, each timed as the
+ * best of three runs after one that captures its graph.  The fastest
+ * (the untuned shape unless another is more than 1 % faster) goes to *best
  * and into a per-process table keyed by (a, n, nnz): later mw_cg_solve
  * calls on matrices of that size use it unless opts->shape sets a field.
  * iters: 2 .. 4096.  workspace: as mw_cg_solve.  Synchronises `stream`.
