@@ -225,6 +225,51 @@ def bench_tolerances(mw, torch, Ad, bd, n, maxit=3000):
     return out
 
 
+def bench_shard(mw, P, torch, dev, parts=8, iters=200):
+    """One GPU's share of the 128^3 problem split into `parts` z-slabs: the
+    rows of 128^3 / parts planes plus one halo plane on each side (the
+    rows a shard's SpMV gathers from its neighbours), as a 128 x 128 x
+    (128 / parts + 2) Poisson matrix.  Planned SpMV GB/s (Infinity Cache
+    read-flushed) and the time of a CG iteration (tol 0, `iters`
+    iterations) per arithmetic, to compare with the full problem."""
+    import numpy as np
+    nz = 128 // parts + 2
+    A = P.poisson3d(128, 128, nz)
+    Ad = mw.DeviceCSR.from_host(A, dev)
+    b = torch.as_tensor(A.matvec(np.random.default_rng(2).uniform(-1, 1, A.n)), device=dev)
+    plan = mw.Plan(Ad)
+    flush = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    out = {"workload": "3D Poisson 128 x 128 x %d (%d-way z-slab share + 2 halo planes), n=%d, nnz=%d"
+                       % (nz, parts, A.n, A.nnz)}
+    for ar in ("fp64", "dw", "qtw"):
+        kk = WORDS[ar]
+        xv = torch.rand((kk, A.n), dtype=torch.float64, device=dev)
+        yv = torch.empty_like(xv)
+        ts = []
+        for rep in range(10):
+            sink.copy_(flush.sum().reshape(1))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            mw.spmv_planned(ar, plan, xv, yv)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep >= 2:
+                ts.append(e0.elapsed_time(e1))
+        gbs = spmv_bytes(A.n, A.nnz, kk) / (statistics.median(ts) * 1e-3) / 1e9
+        x = torch.zeros((kk, A.n), dtype=torch.float64, device=dev)
+        mw.cg_solve(ar, Ad, b, x=x, tol=0.0, maxit=iters, plan=plan)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = mw.cg_solve(ar, Ad, b, x=x, tol=0.0, maxit=iters, plan=plan)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[ar] = {"spmv_GBps_planned_flushed": round(gbs, 1), "per_iteration_us": round(1e6 * sec / iters, 1)}
+        log("shard %s: %s" % (ar, out[ar]))
+    return out
+
+
 def bench_adjoint(mw, P, torch, dev):
     """A(theta) = 3D Laplacian 100^3 + diag(theta), loss 0.5||x - x_t||^2,
     QTW: forward + adjoint solve (all 2n gradient entries) vs the cost of
@@ -441,6 +486,7 @@ def main():
         extra["illcond"] = bench_illcond(mw, P, torch, dev)
         extra["normalisation_every_K"] = bench_normalisation(mw, torch, Ad, bd, A.n)
         extra["tolerances"] = bench_tolerances(mw, torch, Ad, bd, A.n)
+        extra["shard_8way"] = bench_shard(mw, P, torch, dev)
 
     cpu = None
     if not args.no_cpu:

@@ -136,6 +136,16 @@ def unsorted_matrix():
     return P.CSR(A.n, A.row_ptr.copy(), col, val)
 
 
+def empty_slices_matrix():
+    # 2D Poisson whose rows 64 .. 64 * 4 + 9 hold no entries at all: whole
+    # empty slices (width 0) and a partly empty one between full ones
+    A = P.poisson2d(30).to_scipy().tolil()
+    for i in range(64, 64 * 4 + 10):
+        A.rows[i] = []
+        A.data[i] = []
+    return P.CSR.from_scipy(A)
+
+
 def reversed_matrix():
     # a circulant Laplacian with every row stored in descending column
     # order: slices away from the wrap-around still take diagonal slots, in
@@ -180,6 +190,7 @@ MATRICES = {
     "ragged": ragged_matrix,
     "unsorted": unsorted_matrix,
     "reversed": reversed_matrix,
+    "empty_slices": empty_slices_matrix,
 }
 
 
