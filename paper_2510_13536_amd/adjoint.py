@@ -17,10 +17,14 @@ class MWCGSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, val, b, row_ptr, col_idx, arith, tol, maxit, info_out):
         A = mw.DeviceCSR(b.numel(), row_ptr, col_idx, val.detach().contiguous())
-        x, info = mw.cg_solve(arith, A, b.detach().contiguous(), tol=tol, maxit=maxit)
+        # one SpMV plan and workspace serve the forward and the adjoint solve
+        plan = mw.Plan(A)
+        ws = mw.cg_workspace(arith, A)
+        x, info = mw.cg_solve(arith, A, b.detach().contiguous(), tol=tol, maxit=maxit, plan=plan, workspace=ws)
         if info["status"] != "ok":
             raise mw.MWError("forward solve did not converge: %s" % info)
         ctx.A, ctx.arith, ctx.tol, ctx.maxit, ctx.info_out = A, arith, tol, maxit, info_out
+        ctx.plan, ctx.ws = plan, ws
         ctx.x = x
         if info_out is not None:
             info_out["forward"] = info
@@ -29,7 +33,8 @@ class MWCGSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_x):
         A, arith = ctx.A, ctx.arith
-        lam, info = mw.cg_solve(arith, A, grad_x.detach().contiguous().reshape(-1), tol=ctx.tol, maxit=ctx.maxit)
+        lam, info = mw.cg_solve(arith, A, grad_x.detach().contiguous().reshape(-1), tol=ctx.tol, maxit=ctx.maxit,
+                                plan=ctx.plan, workspace=ctx.ws)
         if info["status"] != "ok":
             raise mw.MWError("adjoint solve did not converge: %s" % info)
         if ctx.info_out is not None:
