@@ -91,7 +91,7 @@ constexpr bool neighbour_moves() { return A == QTW; }
 // x[row - 1], lane 63: x[row + 1]).  Any other offset is a gather.  Called
 // by the whole wavefront (the moves need every lane).
 template <int A, int XL>
-__device__ __forceinline__ Num<A> dia_x(int o, bool need, long row, const Num<A> &xc, const Num<A> &xe,
+__device__ __forceinline__ Num<A> dia_x(int o, bool need, long row, Num<A> xc, Num<A> xe,
                                         const double *__restrict__ x, long n)
 {
     if (o == 0) return xc;
@@ -114,8 +114,8 @@ __device__ __forceinline__ Num<A> dia_x(int o, bool need, long row, const Num<A>
 template <int A, int XL>
 __device__ __forceinline__ Num<A> dia_row_sum(int b, int w, int lane, long row, const int32_t *__restrict__ soff,
                                               const uint64_t *__restrict__ smask, const double *__restrict__ sv,
-                                              const double *__restrict__ x, long n, const Num<A> &xc,
-                                              const Num<A> &xe)
+                                              const double *__restrict__ x, long n, Num<A> xc,
+                                              Num<A> xe)
 {
     Num<A> acc = zero<A>();
     const int wp = w >> 1;
