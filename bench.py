@@ -20,7 +20,10 @@ adds:
   extra         SpMV GB/s for every arithmetic (MALL flushed between
                 repetitions), time to solution of every arithmetic, the
                 QTW / DW time ratio, per-kernel times, the batched and
-                adjoint workloads.
+                adjoint workloads, the ill-conditioned banded matrix,
+                normalisation frequencies, tolerances beyond FP64 with
+                true residuals, error norms against an exact integer
+                solution, and one GPU's share of an 8-way split.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
 import argparse
@@ -222,6 +225,44 @@ def bench_tolerances(mw, torch, Ad, bd, n, maxit=3000):
                 row["history_every_50"] = [float("%.3e" % v) for v in h[49::50]]
         out[ar] = row
         log("tolerances %s: %s" % (ar, {k: v for k, v in row.items() if k != "history_every_50"}))
+    return out
+
+
+def bench_error_history(mw, P, torch, dev, nx=128, seed=6,
+                        checkpoints=(100, 200, 400, 600, 800, 1000, 1200, 1600, 2000)):
+    """Error norms against an exact solution: 3D Poisson nx^3 with an
+    integer solution x* in [-8, 8] (seed `seed`), so b = A x* is exact in
+    FP64.  For every arithmetic and every checkpoint m: ||x_m - x*|| / ||x*||
+    and the true relative residual of the m-th CG iterate from x_0 = 0.  The
+    m-th iterate is the result of a solve stopped after m iterations (tol 0;
+    the solver is deterministic for a fixed launch shape, so it is the m-th
+    iterate of the full solve).  x_m - x* is formed in QTW and renormalised
+    (TW) before it is rounded to FP64."""
+    A = P.poisson3d(nx)
+    xs = P.integer_vector(A.n, seed)
+    Ad = mw.DeviceCSR.from_host(A, dev)
+    bd = torch.as_tensor(A.matvec(xs), device=dev)
+    xs3 = torch.zeros((3, A.n), dtype=torch.float64, device=dev)
+    xs3[0] = torch.as_tensor(xs, device=dev)
+    nxs = float(torch.linalg.vector_norm(xs3[0]).item())
+    plan = mw.Plan(Ad)
+    out = {"workload": "3D Poisson %d^3, x* integer in [-8, 8] (seed %d), b = A x* exact" % (nx, seed),
+           "checkpoints": list(checkpoints)}
+    for ar in WORDS:
+        k = WORDS[ar]
+        ws = mw.cg_workspace(ar, Ad)
+        x = torch.zeros((k, A.n), dtype=torch.float64, device=dev)
+        err, res = [], []
+        for m in checkpoints:
+            x.zero_()
+            mw.cg_solve(ar, Ad, bd, x=x, tol=0.0, maxit=m, workspace=ws, plan=plan)
+            x3 = torch.zeros_like(xs3)
+            x3[:k] = x
+            d = mw.elementwise("tw", "norm", mw.elementwise("qtw", "add", x3, mw.elementwise("qtw", "neg", xs3)))
+            err.append(float("%.3e" % (float(torch.linalg.vector_norm(d[0]).item()) / nxs)))
+            res.append(float("%.3e" % true_rel_residual(mw, torch, Ad, bd, x)))
+        out[ar] = {"rel_error": err, "true_rel_res": res}
+        log("error history %s: %s" % (ar, out[ar]))
     return out
 
 
@@ -486,6 +527,7 @@ def main():
         extra["illcond"] = bench_illcond(mw, P, torch, dev)
         extra["normalisation_every_K"] = bench_normalisation(mw, torch, Ad, bd, A.n)
         extra["tolerances"] = bench_tolerances(mw, torch, Ad, bd, A.n)
+        extra["error_history"] = bench_error_history(mw, P, torch, dev)
         extra["shard_8way"] = bench_shard(mw, P, torch, dev)
 
     cpu = None
