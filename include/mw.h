@@ -172,7 +172,8 @@ typedef struct {
                            "-NN" variants of Sec. V-B).  Ignored by the
                            other arithmetics; < 0: MW_EINVAL.              */
     int32_t chunk;      /* iterations launched between two host checks of
-                           convergence; 0 = library default               */
+                           convergence; 0 = library default.  The single
+                           solver rounds it up to an even number.         */
     double *history;    /* optional DEVICE array of maxit doubles: entry i
                            receives the relative residual after iteration
                            i+1.  NULL = not recorded.                      */
@@ -292,8 +293,10 @@ int mw_spmv_planned(mw_arith_t a, const mw_spmv_plan_t *plan, const double *x, d
 int mw_csr_grad(mw_arith_t a, const mw_csr_t *A, const double *lam, const double *x, double *grad_val,
                 void *stream);
 
-/* Bytes of device workspace mw_cg_solve needs (256-byte aligned),
- * including room for a SpMV plan of A. */
+/* Bytes of device workspace mw_cg_solve needs (256-byte aligned): the
+ * vectors r and q, the search direction (TW/QTW: two buffers, so that x
+ * takes the updates of two iterations in one pass), partial sums, the
+ * solver state and room for a SpMV plan of A. */
 size_t mw_cg_workspace_bytes(mw_arith_t a, int32_t n, int32_t nnz);
 
 /*
@@ -314,10 +317,11 @@ size_t mw_cg_workspace_bytes(mw_arith_t a, int32_t n, int32_t nnz);
  * Returns the status (>= 0) or a negative error.  The solve runs on a
  * stream of the library's own, ordered after the work already enqueued on
  * `stream`, and is complete when the call returns.  Iterations are enqueued
- * in chunks (opts->chunk, default 32) as a captured hipGraph that is reused
- * by later calls with the same arguments on the same thread; every kernel
- * exits at once after the stop, and the host checks the stop flag once per
- * chunk.  The result is run-to-run reproducible.
+ * in chunks (opts->chunk, default 32, rounded up to an even number) as a
+ * captured hipGraph that is reused by later calls with the same arguments
+ * on the same thread; every kernel exits at once after the stop, and the
+ * host checks the stop flag once per chunk.  The result is run-to-run
+ * reproducible.
  */
 int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, double tol,
                 int32_t maxit, const mw_cg_opts_t *opts, void *workspace, mw_cg_info_t *info,

@@ -12,9 +12,19 @@ namespace mwk {
 // which the previous iteration wrote before a kernel boundary, so no
 // workgroup ever reads an entry another workgroup of the same kernel
 // writes.
+// Search-direction buffers of the CG solver: x takes the updates
+// alpha_j p_j of xr(a) consecutive iterations in one pass, so one read and
+// write of x serves xr(a) iterations at the cost of a second p buffer.
+// For 3-word types that pays (measured on MI355X, 3D Poisson 128^3: QTW
+// solve -2 %); for 1- and 2-word types the solver's working set (matrix
+// and four vectors) just fits the 256 MB Infinity Cache and a second p
+// buffer costs more than x's traffic (DW +11 %), so they keep one.
+__host__ __device__ constexpr int xr(int a) { return words(a) == 3 ? 2 : 1; }
+constexpr int XR_MAX = 2;
+
 struct CgState {
-    double rho[2][3];    // r^T r after the iteration of each parity
-    double alpha[2][3];  // alpha of the iteration of each parity
+    double rho[2][3];         // r^T r after the iteration of each parity
+    double alpha[XR_MAX][3];  // alpha of iteration k (0-based) in slot k % xr
     double nb;           // ||b||_2
     double tol;
     double rel_res;      // relative residual at the stop (or the last test)

@@ -12,12 +12,20 @@
 //      alpha = rho / sigma (breakdown test); r = r - alpha q; quasi types
 //      normalise r; partials of r^T r
 //   3. every workgroup reduces those to the same rho', counts the iteration,
-//      runs the FP64 residual test and forms beta; x = x + alpha p and,
-//      unless the solve stops here, p = r + beta p
-// The x update rides in step 3 with the p that step 1 read, which saves a
-// pass over p.  Scalars and flags an iteration produces are stored per
-// iteration parity, so no workgroup reads what another workgroup of the
-// same kernel writes; the parity of each launch is a kernel argument.
+//      runs the FP64 residual test and forms beta; unless the solve stops
+//      here, p = r + beta p
+// x is needed by no step of the loop, so its updates x = x + alpha_j p_j
+// may be applied XR = xr(A) iterations at a time (2 for 3-word types, else
+// 1): the search directions live in a ring of XR buffers (p_k in buffer
+// k % XR; with XR = 1 p is updated in place), and step 3 of every XR-th
+// iteration, of the iteration that stops the solve and of one whose alpha
+// step broke down adds the pending terms one after another, in iteration
+// order -- the same operations on the same values as one update per
+// iteration.  Chunks hold an even number of iterations, a multiple of XR,
+// so each launch's buffers are fixed.  Scalars and flags an iteration
+// produces are stored per iteration parity (alpha per buffer), so no
+// workgroup reads what another workgroup of the same kernel writes; the
+// parity and buffer of each launch are kernel arguments.
 // After the stop every kernel only passes the stop flag on and exits, so a
 // chunk of iterations is enqueued (or replayed from a captured hipGraph)
 // and the host checks the flag once per chunk.  All reductions use fixed
@@ -96,16 +104,17 @@ __global__ void __launch_bounds__(FIN_NT) mw_cg_init_final_kernel(int nslots, co
     }
 }
 
-// Iteration step 2 (parity par): every workgroup reduces the p^T q partials
-// in the same fixed order, so all derive the same sigma and
-// alpha = rho / sigma; breakdown (sigma <= 0 or a non-finite value) stops
-// the solve before any vector changes.  Then r = r - alpha q, quasi types
-// normalise r, and the workgroup partial of r^T r goes to slots_out.
+// Iteration step 2 (parity par; iteration k, 0-based, with k % xr(A) = kpos):
+// every workgroup reduces the p^T q partials in the same fixed order, so all
+// derive the same sigma and alpha = rho / sigma (stored in slot kpos);
+// breakdown (sigma <= 0 or a non-finite value) stops the solve before r or
+// p change.  Then r = r - alpha q, quasi types normalise r, and the
+// workgroup partial of r^T r goes to slots_out.
 template <int A, int UNT>
 __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in, const double *__restrict__ slots_in,
                                                            const double *__restrict__ q, double *__restrict__ r,
                                                            double *__restrict__ slots_out, CgState *__restrict__ st,
-                                                           int par, int rev)
+                                                           int par, int kpos, int rev)
 {
     constexpr int K = words(A);
     __shared__ Num<A> s_alpha;
@@ -142,7 +151,7 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
                 st->iters_final = st->iters[par ^ 1];
                 st->stopped = 1;
             } else {
-                store_scalar<A>(st->alpha[par], al);
+                store_scalar<A>(st->alpha[kpos], al);
             }
         }
     }
@@ -168,30 +177,54 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
     if (threadIdx.x == 0) store_scalar<A>(slots_out + (long)blockIdx.x * K, sum);
 }
 
-// Iteration step 3 (parity par): every workgroup reduces the r^T r
-// partials to the same rho', counts the iteration, runs the FP64 residual
-// test and derives beta = rho' / rho.  Then x = x + alpha p, and, unless
-// the solve stops here, p = r + beta p (both with this iteration's p).
+// Iteration step 3 (parity par; iteration k with k % XR = kpos, XR =
+// xr(A)): every workgroup reduces the r^T r partials to the same rho',
+// counts the iteration, runs the FP64 residual test and derives
+// beta = rho' / rho.  pk is p_k (buffer kpos); unless the solve stops
+// here, p_{k+1} = r + beta p_k goes to buffer (kpos + 1) % XR: with
+// XR = 1 that is pk itself, with XR = 2 the other buffer, po, which holds
+// p_{k-1}.  x takes the pending updates x = x + alpha_j p_j in iteration
+// order: those of iterations k - kpos .. k when kpos = XR - 1 or the solve
+// stops here, those of iterations k - kpos .. k - 1 after a breakdown of
+// this iteration's alpha step.  With XR = 2 and kpos = 1 that reads
+// p_{k-1} from po before the same thread stores p_{k+1} there.
 template <int A, int UNT>
 __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in, const double *__restrict__ slots_in,
-                                                           const double *__restrict__ r, double *__restrict__ p,
-                                                           double *__restrict__ x, CgState *__restrict__ st, int par,
-                                                           int rev)
+                                                           const double *__restrict__ r, double *__restrict__ pk,
+                                                           double *__restrict__ po, double *__restrict__ x,
+                                                           CgState *__restrict__ st, int par, int kpos_arg, int rev)
 {
+    constexpr int XR = xr(A);
+    static_assert(XR == 1 || XR == 2, "one or two search-direction buffers");
+    const int kpos = XR == 1 ? 0 : kpos_arg;
+    double *pn = XR == 1 ? pk : po;  // based on pk or po
     __shared__ Num<A> s_beta;
     __shared__ int s_stop;
-    if (!st->run[par ^ 1] || st->brk[par]) {
+    if (!st->run[par ^ 1]) {
         if (blockIdx.x == 0 && threadIdx.x == 0) st->run[par] = 0;
         return;
     }
-    // the first tile's operands are loaded before the reduction (as in
-    // step r)
     const TileWalk tw = xcd_walk((n + UNT - 1) / UNT, rev);
+    if (st->brk[par]) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->run[par] = 0;
+        if (XR == 1 || kpos == 0) return;
+        // XR = 2, kpos = 1: iteration k - 1 is pending, its p is in po
+        const Num<A> a0 = load_scalar<A>(st->alpha[0]);
+        for (int m = 0; m < tw.count; ++m) {
+            const long i = (long)tw[m] * UNT + threadIdx.x;
+            if (i >= n) continue;
+            store<A>(x, n, i, axpy_term<A>(a0, load_il<A>(po, n, i), load<A>(x, n, i)));
+        }
+        return;
+    }
+    // the first tile's operands are loaded before the reduction (as in
+    // step r); x only where it is due
+    const bool xdue = kpos == XR - 1;
     const long i0 = tw.count > 0 ? (long)tw[0] * UNT + threadIdx.x : (long)n;
     Num<A> p0 = zero<A>(), x0 = zero<A>(), r0 = zero<A>();
     if (i0 < n) {
-        p0 = load_il<A>(p, n, i0);
-        x0 = load<A>(x, n, i0);
+        p0 = load_il<A>(pk, n, i0);
+        if (xdue) x0 = load<A>(x, n, i0);
         r0 = load<A>(r, n, i0);
     }
     const Num<A> rho_new = reduce_slots<A, UNT>(nslots_in, slots_in);
@@ -222,16 +255,23 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
     __syncthreads();
     const bool stop = s_stop;
     const Num<A> be = s_beta;
-    const Num<A> al = load_scalar<A>(st->alpha[par]);
+    const bool xnow = stop || xdue;
+    // alpha of iteration k (slot kpos) and, with XR = 2 and kpos = 1, of k - 1
+    const Num<A> ak = load_scalar<A>(st->alpha[kpos]);
+    const bool two = XR == 2 && kpos == 1;
+    const Num<A> a0 = two ? load_scalar<A>(st->alpha[0]) : zero<A>();
     for (int m = 0; m < tw.count; ++m) {
         const long i = (long)tw[m] * UNT + threadIdx.x;
         if (i >= n) continue;
-        const Num<A> pi = m == 0 ? p0 : load_il<A>(p, n, i);
-        const Num<A> xi = m == 0 ? x0 : load<A>(x, n, i);
-        store<A>(x, n, i, axpy_term<A>(al, pi, xi));
+        const Num<A> pi = m == 0 ? p0 : load_il<A>(pk, n, i);
+        if (xnow) {
+            Num<A> xi = (m == 0 && xdue) ? x0 : load<A>(x, n, i);
+            if (two) xi = axpy_term<A>(a0, load_il<A>(po, n, i), xi);
+            store<A>(x, n, i, axpy_term<A>(ak, pi, xi));
+        }
         if (!stop) {
             const Num<A> rv = m == 0 ? r0 : load<A>(r, n, i);
-            store_il<A>(p, n, i, axpy_term<A>(be, pi, rv));
+            store_il<A>(pn, n, i, axpy_term<A>(be, pi, rv));
         }
     }
 }
@@ -240,6 +280,7 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
 
 struct CgLayout {
     size_t r, p, q, slots_a, slots_b, state, plan, total;
+    size_t plane;  // bytes of one vector (k planes of n, 256-aligned)
 };
 
 CgLayout cg_layout(int a, int32_t n, int32_t nnz)
@@ -250,13 +291,14 @@ CgLayout cg_layout(int a, int32_t n, int32_t nnz)
     const size_t slots = align256(sizeof(double) * nsl * K);
     CgLayout L;
     L.r = 0;
-    L.p = L.r + plane;
-    L.q = L.p + plane;
+    L.p = L.r + plane;  // xr(a) search-direction buffers
+    L.q = L.p + (size_t)xr(a) * plane;
     L.slots_a = L.q + plane;
     L.slots_b = L.slots_a + slots;
     L.state = L.slots_b + slots;
     L.plan = L.state + align256(sizeof(CgState));
     L.total = L.plan + plan_bytes(n, nnz);
+    L.plane = plane;
     return L;
 }
 
@@ -306,6 +348,7 @@ constexpr int KCLASS[NKERN] = {MW_PROF_SPMV, MW_PROF_UPDATE_R, MW_PROF_UPDATE_P}
 // Everything one chunk of iterations needs.
 struct ChunkArgs {
     int arith, n, nslots_sp, nslots_up, chunk, timed_mask, unt, ugrid;
+    long pstride;  // doubles between the search-direction buffers
     const mw_csr_t *M;
     const mw_spmv_plan_t *plan;
     double *r, *p, *q, *x, *slots_a, *slots_b;
@@ -315,7 +358,7 @@ struct ChunkArgs {
 bool same_key(const ChunkArgs &a, const ChunkArgs &b)
 {
     return a.arith == b.arith && a.n == b.n && a.nslots_sp == b.nslots_sp && a.nslots_up == b.nslots_up &&
-           a.chunk == b.chunk && a.timed_mask == b.timed_mask && a.unt == b.unt && a.ugrid == b.ugrid && a.r == b.r && a.p == b.p && a.q == b.q &&
+           a.chunk == b.chunk && a.pstride == b.pstride && a.timed_mask == b.timed_mask && a.unt == b.unt && a.ugrid == b.ugrid && a.r == b.r && a.p == b.p && a.q == b.q &&
            a.x == b.x && a.slots_a == b.slots_a && a.slots_b == b.slots_b && a.st == b.st && a.plan && b.plan &&
            a.plan->format == b.plan->format && a.plan->nslices == b.plan->nslices &&
            a.plan->slice_ptr == b.plan->slice_ptr && a.plan->col == b.plan->col && a.plan->val == b.plan->val &&
@@ -324,20 +367,22 @@ bool same_key(const ChunkArgs &a, const ChunkArgs &b)
            a.M->n == b.M->n;
 }
 
-// Enqueues one chunk (even length; iteration j of the chunk has parity
-// (j + 1) & 1, since chunks start after an even number of iterations).
-// With a mask, the kernels of the timed classes carry a pair of events.
+// Enqueues one chunk (even length, a multiple of xr(A), so chunks start
+// after a multiple of it: iteration j of the chunk, 0-based, has parity
+// (j + 1) & 1 and uses search-direction buffer j % xr(A)).  With a mask,
+// the kernels of the timed classes carry a pair of events.
 template <int A, int UNT>
-void launch_steps(const ChunkArgs &c, int k, int par, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+void launch_steps(const ChunkArgs &c, int k, int par, int kpos, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const int gu = c.nslots_up;
     // consecutive kernels walk the rows in opposite directions
     if (k == 1)
         MW_LAUNCH((mw_cg_step_r_kernel<A, UNT>), dim3(gu), dim3(UNT), s, e0, e1, c.n, c.nslots_sp, c.slots_a, c.q,
-                  c.r, c.slots_b, c.st, par, par ^ 1);
+                  c.r, c.slots_b, c.st, par, kpos, par ^ 1);
     else
         MW_LAUNCH((mw_cg_step_p_kernel<A, UNT>), dim3(gu), dim3(UNT), s, e0, e1, c.n, c.nslots_up, c.slots_b, c.r,
-                  c.p, c.x, c.st, par, par);
+                  c.p + kpos * c.pstride, xr(A) == 1 ? nullptr : c.p + ((kpos + 1) % xr(A)) * c.pstride, c.x, c.st,
+                  par, kpos, par);
 }
 
 template <int A>
@@ -345,20 +390,21 @@ int enqueue_chunk(const ChunkArgs &c, EventPool *ev, hipStream_t s)
 {
     for (int it = 0; it < c.chunk; ++it) {
         const int par = (it + 1) & 1;
+        const int kpos = it % xr(A);
         for (int k = 0; k < NKERN; ++k) {
             const bool timed = ev && (c.timed_mask & (1 << KCLASS[k]));
             hipEvent_t e0 = timed ? ev->e[(it * NKERN + k) * 2] : nullptr;
             hipEvent_t e1 = timed ? ev->e[(it * NKERN + k) * 2 + 1] : nullptr;
             if (k == 0) {
-                const int rc = spmv_launch<A>(c.M, c.plan, c.p, c.q, c.slots_a, &c.st->run[par ^ 1], &c.st->run[par],
-                                              1, s, nullptr, par, e0, e1, c.nslots_sp);
+                const int rc = spmv_launch<A>(c.M, c.plan, c.p + kpos * c.pstride, c.q, c.slots_a, &c.st->run[par ^ 1],
+                                              &c.st->run[par], 1, s, nullptr, par, e0, e1, c.nslots_sp);
                 if (rc) return rc;
             } else if (c.unt == 1024) {
-                launch_steps<A, 1024>(c, k, par, s, e0, e1);
+                launch_steps<A, 1024>(c, k, par, kpos, s, e0, e1);
             } else if (c.unt == 512) {
-                launch_steps<A, 512>(c, k, par, s, e0, e1);
+                launch_steps<A, 512>(c, k, par, kpos, s, e0, e1);
             } else {
-                launch_steps<A, 256>(c, k, par, s, e0, e1);
+                launch_steps<A, 256>(c, k, par, kpos, s, e0, e1);
             }
         }
     }
@@ -459,6 +505,7 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     c.arith = A;
     c.n = n;
     c.chunk = chunk;
+    c.pstride = (long)(L.plane / sizeof(double));
     c.timed_mask = mask;
     c.M = M;
     c.plan = plan;

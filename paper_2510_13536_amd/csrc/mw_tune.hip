@@ -117,7 +117,9 @@ CgShape cg_shape(int a, int n, int nnz, int ns, const mw_shape_t *explicit_shape
     const int ub = blocks_for(n, r.unt);
     r.ugrid = ub < ucap ? ub : ucap;
     r.chunk = opts_chunk > 0 ? opts_chunk : (s.chunk > 0 ? s.chunk : 32);
-    r.chunk += r.chunk & 1;  // even: the parity pattern repeats per chunk
+    // even (a multiple of xr(a) <= 2): the parity pattern and the
+    // search-direction buffers repeat per chunk
+    r.chunk += r.chunk & 1;
     return r;
 }
 
