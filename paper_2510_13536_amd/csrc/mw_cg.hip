@@ -123,14 +123,20 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
         if (blockIdx.x == 0 && threadIdx.x == 0) st->run[par] = 0;
         return;
     }
-    // the first tile's operands are loaded before the reduction, so that
-    // their latency overlaps it
+    // the first two tiles' operands are loaded before the reduction, so
+    // that their latency overlaps it (measured on MI355X: one tile hides
+    // part of the reduction's latency, two hide more; QTW solve -1 %)
     const TileWalk tw = xcd_walk((n + UNT - 1) / UNT, rev);
     const long i0 = tw.count > 0 ? (long)tw[0] * UNT + threadIdx.x : (long)n;
-    Num<A> q0 = zero<A>(), r0 = zero<A>();
+    const long i1 = tw.count > 1 ? (long)tw[1] * UNT + threadIdx.x : (long)n;
+    Num<A> q0 = zero<A>(), r0 = zero<A>(), q1 = zero<A>(), r1 = zero<A>();
     if (i0 < n) {
         q0 = load<A>(q, n, i0);
         r0 = load<A>(r, n, i0);
+    }
+    if (i1 < n) {
+        q1 = load<A>(q, n, i1);
+        r1 = load<A>(r, n, i1);
     }
     const Num<A> sigma = reduce_slots<A, UNT>(nslots_in, slots_in);
     if (threadIdx.x == 0) {
@@ -166,8 +172,8 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
     for (int m = 0; m < tw.count; ++m) {
         const long i = (long)tw[m] * UNT + threadIdx.x;
         if (i >= n) continue;
-        const Num<A> qi = m == 0 ? q0 : load<A>(q, n, i);
-        const Num<A> rv = m == 0 ? r0 : load<A>(r, n, i);
+        const Num<A> qi = m == 0 ? q0 : (m == 1 ? q1 : load<A>(q, n, i));
+        const Num<A> rv = m == 0 ? r0 : (m == 1 ? r1 : load<A>(r, n, i));
         Num<A> ri = axmy_term<A>(al, qi, rv);
         if (norm) ri = normalise<A>(ri);
         store<A>(r, n, i, ri);
@@ -217,15 +223,20 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
         }
         return;
     }
-    // the first tile's operands are loaded before the reduction (as in
-    // step r); x only where it is due
+    // the first two tiles' operands are loaded before the reduction (as in
+    // step r); x of the first tile where it is due
     const bool xdue = kpos == XR - 1;
     const long i0 = tw.count > 0 ? (long)tw[0] * UNT + threadIdx.x : (long)n;
-    Num<A> p0 = zero<A>(), x0 = zero<A>(), r0 = zero<A>();
+    const long i1 = tw.count > 1 ? (long)tw[1] * UNT + threadIdx.x : (long)n;
+    Num<A> p0 = zero<A>(), x0 = zero<A>(), r0 = zero<A>(), p1 = zero<A>(), r1 = zero<A>();
     if (i0 < n) {
         p0 = load_il<A>(pk, n, i0);
         if (xdue) x0 = load<A>(x, n, i0);
         r0 = load<A>(r, n, i0);
+    }
+    if (i1 < n) {
+        p1 = load_il<A>(pk, n, i1);
+        r1 = load<A>(r, n, i1);
     }
     const Num<A> rho_new = reduce_slots<A, UNT>(nslots_in, slots_in);
     if (threadIdx.x == 0) {
@@ -263,14 +274,14 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
     for (int m = 0; m < tw.count; ++m) {
         const long i = (long)tw[m] * UNT + threadIdx.x;
         if (i >= n) continue;
-        const Num<A> pi = m == 0 ? p0 : load_il<A>(pk, n, i);
+        const Num<A> pi = m == 0 ? p0 : (m == 1 ? p1 : load_il<A>(pk, n, i));
         if (xnow) {
             Num<A> xi = (m == 0 && xdue) ? x0 : load<A>(x, n, i);
             if (two) xi = axpy_term<A>(a0, load_il<A>(po, n, i), xi);
             store<A>(x, n, i, axpy_term<A>(ak, pi, xi));
         }
         if (!stop) {
-            const Num<A> rv = m == 0 ? r0 : load<A>(r, n, i);
+            const Num<A> rv = m == 0 ? r0 : (m == 1 ? r1 : load<A>(r, n, i));
             store_il<A>(pn, n, i, axpy_term<A>(be, pi, rv));
         }
     }

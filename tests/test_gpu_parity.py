@@ -312,6 +312,52 @@ def test_cg_tight_tolerance(mw, arith):
     assert err < {"fp64": 1e-12, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-38}[arith]
 
 
+def _diag_indefinite(seed, n=24):
+    """A diagonal with one to three negative entries and a random b; the
+    seeds used below break down (p^T q <= 0) after 1, 2, 3, 4 and 5
+    completed iterations."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(0.5, 4.0, n)
+    neg = rng.integers(1, 4)
+    d[rng.choice(n, neg, replace=False)] *= -rng.uniform(0.05, 1.0, neg)
+    return P.CSR.from_scipy(sp.diags(d, 0).tocsr()), rng.uniform(-1, 1, n)
+
+
+def _x_close(arith, xg, xo):
+    """Largest |x_gpu - x_oracle| / max|x_oracle|, the words' differences
+    added up (the leading words agree closely, so the sum is accurate)."""
+    e = np.zeros(xo.shape[1])
+    for w in range(xo.shape[0]):
+        e = e + (xg[w] - xo[w])
+    return np.abs(e).max() / np.abs(xo[0]).max()
+
+
+X_BOUND = {"fp64": 1e-13, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-38}
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_cg_x_after_each_stop_position(mw, arith):
+    """x at every stop position: after m = 1..6 iterations (maxit = m) and
+    after a breakdown following 1..5 iterations.  The solver applies the
+    x updates of two iterations in one pass for 3-word types, so these are
+    the stops at both positions of a pair, with and without a pending
+    update.  x equals the oracle's up to the rounding of the dots."""
+    A, b, _ = P.case_poisson3d(nx=12)
+    Ad = mw.DeviceCSR.from_host(A)
+    for m in range(1, 7):
+        xo, io = O.cg_solve(arith, A, b, tol=0.0, maxit=m)
+        xg, ig = mw.cg_solve(arith, Ad, dev(b), tol=0.0, maxit=m)
+        assert ig["status"] == io["status"] == "not_converged" and ig["iters"] == io["iters"] == m
+        assert _x_close(arith, host(xg), np.asarray(xo).reshape(-1, A.n)) < X_BOUND[arith], m
+    for seed, iters in ((3, 1), (1, 2), (0, 3), (64, 4), (191, 5)):
+        M, bm = _diag_indefinite(seed)
+        xo, io = O.cg_solve(arith, M, bm, tol=1e-14)
+        xg, ig = mw.cg_solve(arith, mw.DeviceCSR.from_host(M), dev(bm), tol=1e-14)
+        assert io["status"] == ig["status"] == "breakdown", (seed, io, ig)
+        assert io["iters"] == ig["iters"] == iters, (seed, io, ig)
+        assert _x_close(arith, host(xg), np.asarray(xo).reshape(-1, M.n)) < X_BOUND[arith], seed
+
+
 @pytest.mark.parametrize("arith", ARITHS)
 def test_cg_failure_paths(mw, arith):
     A, b, _ = P.case_poisson2d_64()
