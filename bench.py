@@ -79,6 +79,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def copy_ceiling(torch, dev, nbytes=1 << 30, reps=10):
+    """Device-to-device copy bandwidth: bytes read + written over the median
+    time of `reps` copies of a 1 GiB buffer (four times the Infinity Cache)."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    ts = []
+    for rep in range(reps + 2):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        if rep >= 2:
+            ts.append(e0.elapsed_time(e1))
+    del a, b
+    return 2 * nbytes / (statistics.median(ts) * 1e-3) / 1e9
+
+
 def bench_batched(mw, P, torch, dev, nsys=512, tune=True):
     """512 uneven SPD systems (Poisson 2D/3D and circulant Laplacians, n in
     [1024, 65536]): one batched solve vs a loop of single solves, QTW and
@@ -456,6 +474,11 @@ def main():
                 "plan": plan_info,
                 "timing": "HIP events around each SpMV launch on the solver stream, %d event-timed solves "
                           "(direct launches, %.2f ms/solve) right after the timed steps" % (args.prof_steps, prof_ms)}
+    # the same kernel against what a plain device copy reaches on this GPU
+    cc = copy_ceiling(torch, dev)
+    roofline["copy_GBps"] = round(cc, 1)
+    roofline["frac_of_copy"] = round(achieved / cc, 4)
+    log("copy ceiling %.1f GB/s; SpMV %.1f GB/s = %.3f of it" % (cc, achieved, achieved / cc))
 
     extra = {"iterations": iters, "device_seconds": infos[-1]["seconds"],
              "launch_shape": mw.cg_shape(arith, A.n, A.nnz)[1], "tuned": tuned is not None,
@@ -547,6 +570,21 @@ def main():
                          "per-iteration time %.3f s x the GPU solve's %d iterations plus setup (extrapolated)"
                          % (ci, arith.upper(), args.nx, 2 + ci, per_iter, iters)}
         log("cpu baseline: %s" % cpu)
+        # the same oracle on one thread (a few iterations)
+        nthr = O.num_threads()
+        O.set_num_threads(1)
+        c1 = max(2, ci // 4)
+        s0 = time.perf_counter()
+        O.cg_solve(arith, A, b, tol=tol, maxit=1)
+        s1 = time.perf_counter()
+        O.cg_solve(arith, A, b, tol=tol, maxit=1 + c1)
+        s2 = time.perf_counter()
+        O.set_num_threads(nthr)
+        per1 = ((s2 - s1) - (s1 - s0)) / c1
+        extra["cpu_oracle_1_thread"] = {"s_per_iteration": round(per1, 3), "extrapolated_s": round(per1 * iters, 1),
+                                        "sample": "%d %s CG iterations on one thread (difference of maxit=%d and "
+                                                  "maxit=1 runs)" % (c1, arith.upper(), 1 + c1)}
+        log("cpu oracle, 1 thread: %s" % extra["cpu_oracle_1_thread"])
 
     out = {"metric": METRIC, "value": round(ms_per_step / 1e3, 5), "unit": "s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),

@@ -427,6 +427,17 @@ int mwo_num_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops from now on (timing only: the results do
+ * not depend on it). */
+void mwo_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------
  * Exported: error-free transformations on arrays (for invariant tests).
  * which: 0 TwoSum, 1 QuickTwoSum, 2 TwoProdFMA.

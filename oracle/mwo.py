@@ -40,6 +40,8 @@ def _load(name):
         build()
     lib = C.CDLL(path)
     lib.mwo_words.argtypes = [C.c_int]
+    lib.mwo_set_num_threads.argtypes = [C.c_int]
+    lib.mwo_set_num_threads.restype = None
     lib.mwo_ops_get.restype = C.c_longlong
     lib.mwo_eft.argtypes = [C.c_int, C.c_long, _dp, _dp, _dp, _dp]
     lib.mwo_elementwise.argtypes = [C.c_int, C.c_int, C.c_long, _dp, _dp, _dp]
@@ -77,6 +79,12 @@ def lib_count():
 
 def num_threads():
     return lib().mwo_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the oracle's parallel loops (timing only; results do not
+    depend on it)."""
+    lib().mwo_set_num_threads(int(n))
 
 
 def _d(a):
