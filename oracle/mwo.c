@@ -1,7 +1,8 @@
 /*
  * mwo.c -- CPU oracle for Conjugate Gradient in FP64, double-word (DW),
  * quasi double-word (QDW, pair arithmetic), triple-word (TW) and quasi
- * triple-word (QTW) arithmetic.
+ * triple-word (QTW) arithmetic, plus QTWE: QTW with VecSum3 after every
+ * operation.
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
  * statement of what the GPU path computes.  Only the test-suite, the smoke
@@ -24,6 +25,13 @@
  *   Sec. IV-C           : A, b in FP64, everything else in the arithmetic,
  *                         residual test in FP64;
  *   Sec. IV-D           : QDW/QTW normalise r right after its AXPY update.
+ *   Sec. IV-D, VI       : normalising more often may gain accuracy at a cost;
+ *                         the best frequency and placement are left open.
+ *                         QTWE is the other end of that range: every QTW
+ *                         operation (Alg. 7, 8, 10) is followed by VecSum3
+ *                         (Alg. 9), and r gets no extra normalisation.  (For
+ *                         QDW the same placement is DW itself, since QDW is
+ *                         DW without the closing QuickTwoSum.)
  *   Alg. 1              : the CG iteration.
  *
  * Readings where the paper is silent (each is listed with its reason in the
@@ -56,7 +64,7 @@
 #include <omp.h>
 #endif
 
-enum { MWO_FP64 = 0, MWO_DW = 1, MWO_QDW = 2, MWO_TW = 3, MWO_QTW = 4 };
+enum { MWO_FP64 = 0, MWO_DW = 1, MWO_QDW = 2, MWO_TW = 3, MWO_QTW = 4, MWO_QTWE = 5 };
 
 enum {
     MWO_OK = 0,
@@ -141,7 +149,7 @@ static int words_of(int a)
     switch (a) {
     case MWO_FP64: return 1;
     case MWO_DW: case MWO_QDW: return 2;
-    case MWO_TW: case MWO_QTW: return 3;
+    case MWO_TW: case MWO_QTW: case MWO_QTWE: return 3;
     default: return -1;
     }
 }
@@ -314,6 +322,12 @@ static mwv tw_add(mwv a, mwv b) { return tw_renorm(qtw_add(a, b)); }
 static mwv tw_mul(mwv a, mwv b) { return tw_renorm(qtw_mul(a, b)); }
 static mwv tw_dxmul(double a, mwv b) { return tw_renorm(qtw_dxmul(a, b)); }
 
+/* ---- QTWE: every QTW operation followed by VecSum3 (Alg. 9) ------------ */
+
+static mwv qtwe_add(mwv a, mwv b) { return vec_sum3(qtw_add(a, b)); }
+static mwv qtwe_mul(mwv a, mwv b) { return vec_sum3(qtw_mul(a, b)); }
+static mwv qtwe_dxmul(double a, mwv b) { return vec_sum3(qtw_dxmul(a, b)); }
+
 /* ---- Dispatch by arithmetic ------------------------------------------- */
 
 static mwv mw_add(int ar, mwv a, mwv b)
@@ -323,6 +337,7 @@ static mwv mw_add(int ar, mwv a, mwv b)
     case MWO_DW: return dw_add(a, b);
     case MWO_QDW: return qdw_add(a, b);
     case MWO_TW: return tw_add(a, b);
+    case MWO_QTWE: return qtwe_add(a, b);
     default: return qtw_add(a, b);
     }
 }
@@ -334,6 +349,7 @@ static mwv mw_mul(int ar, mwv a, mwv b)
     case MWO_DW: return dw_mul(a, b);
     case MWO_QDW: return qdw_mul(a, b);
     case MWO_TW: return tw_mul(a, b);
+    case MWO_QTWE: return qtwe_mul(a, b);
     default: return qtw_mul(a, b);
     }
 }
@@ -345,6 +361,7 @@ static mwv mw_dxmul(int ar, double a, mwv b)
     case MWO_DW: return dw_dxmul(a, b);
     case MWO_QDW: return qdw_dxmul(a, b);
     case MWO_TW: return tw_dxmul(a, b);
+    case MWO_QTWE: return qtwe_dxmul(a, b);
     default: return qtw_dxmul(a, b);
     }
 }
@@ -353,7 +370,8 @@ static mwv mw_dxmul(int ar, double a, mwv b)
 static mwv mw_neg(mwv a) { return mw_make(-a.w[0], -a.w[1], -a.w[2]); }
 
 /* The normalisation each format uses: QuickTwoSum for the two-word types,
- * VecSum3 for QTW (Sec. III / IV-D), the full renormalisation for TW. */
+ * VecSum3 for QTW and QTWE (Sec. III / IV-D), the full renormalisation for
+ * TW. */
 static mwv mw_normalise(int ar, mwv a)
 {
     double x, y;

@@ -8,7 +8,8 @@ rational arithmetic fix (no GPU).
   dropped term or flipped sign would break by orders of magnitude.
 * Normalisation invariants: DW/TW results satisfy fl(c1+c2) = c1 (and
   fl(c2+c3) = c2); QuickTwoSum, VecSum3 and the TW renormalisation are
-  error-free, so QDW carries the same exact value as DW and TW as QTW.
+  error-free, so QDW carries the same exact value as DW, and TW and QTWE
+  (QTW with VecSum3 after every operation) the same as QTW.
 """
 from fractions import Fraction
 
@@ -86,6 +87,8 @@ def test_eft_adversarial(rng):
     ("qdw", "add", 8), ("qdw", "mul", 4),         # Sec. III, QDW text
     ("qtw", "add", 21), ("qtw", "mul", 24),       # Sec. III, QTW text
     ("qtw", "dxmul", 12),                         # Alg. 10: 2 TwoProd + TwoSum + fma + add
+    # QTWE: the QTW counts plus VecSum3 (Alg. 9: two TwoSums of 6 ops)
+    ("qtwe", "add", 33), ("qtwe", "mul", 36), ("qtwe", "dxmul", 24),
     ("dw", "dxmul", 6), ("qdw", "dxmul", 3),      # DWmul / QDWmul minus the a2*b1 fma
     ("fp64", "add", 1), ("fp64", "mul", 1), ("fp64", "dxmul", 1),
 ])
@@ -116,7 +119,7 @@ def _rel(err, scale):
     return float(abs(err) / scale) if scale else float(abs(err))
 
 
-@pytest.mark.parametrize("arith", ["dw", "qdw", "tw", "qtw"])
+@pytest.mark.parametrize("arith", ["dw", "qdw", "tw", "qtw", "qtwe"])
 def test_add_mul_accuracy_against_exact(arith, rng):
     k = O.WORDS[arith]
     a = rand_mw(rng, k, N_ACC)
@@ -138,7 +141,7 @@ def test_add_mul_accuracy_against_exact(arith, rng):
     assert worst_d <= mbound, worst_d / U ** k
 
 
-@pytest.mark.parametrize("arith", ["dw", "qdw", "tw", "qtw"])
+@pytest.mark.parametrize("arith", ["dw", "qdw", "tw", "qtw", "qtwe"])
 def test_div_accuracy_against_exact(arith, rng):
     k = O.WORDS[arith]
     a = rand_mw(rng, k, 600)
@@ -160,7 +163,7 @@ def test_fp64_ops_are_single_roundings(rng):
 
 def test_exact_special_cases():
     # integers and powers of two are exact in every arithmetic
-    for arith in ["dw", "qdw", "tw", "qtw"]:
+    for arith in ["dw", "qdw", "tw", "qtw", "qtwe"]:
         k = O.WORDS[arith]
         a = np.zeros((k, 3))
         b = np.zeros((k, 3))
@@ -176,7 +179,7 @@ def test_exact_special_cases():
 
 def test_div_one_third_is_accurate():
     # 1/3 to 2 and 3 words: error below the format's precision
-    for arith in ["dw", "qdw", "tw", "qtw"]:
+    for arith in ["dw", "qdw", "tw", "qtw", "qtwe"]:
         k = O.WORDS[arith]
         a = np.zeros((k, 1))
         b = np.zeros((k, 1))
@@ -201,11 +204,12 @@ def test_non_quasi_results_are_normalised(arith, rng):
             assert np.all(c[1] + c[2] == c[1])
 
 
-@pytest.mark.parametrize("base,quasi", [("dw", "qdw"), ("tw", "qtw")])
+@pytest.mark.parametrize("base,quasi", [("dw", "qdw"), ("tw", "qtw"), ("qtwe", "qtw")])
 def test_normalisation_preserves_value(base, quasi, rng):
     # QuickTwoSum (on ordered pairs), VecSum3 and the TW renormalisation are
-    # error-free: a quasi op and its normalised counterpart carry the same
-    # exact value on the same inputs.
+    # error-free: a quasi op and its normalised counterpart (DW, TW, or
+    # QTWE: VecSum3 after every QTW op) carry the same exact value on the
+    # same inputs.
     k = O.WORDS[base]
     a = rand_mw(rng, k, 800)
     b = rand_mw(rng, k, 800)

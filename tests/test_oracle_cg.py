@@ -18,8 +18,8 @@ import scipy.sparse as sp
 import oracle as O
 from paper_2510_13536_amd import problems as P
 
-ARITHS = ["fp64", "dw", "qdw", "tw", "qtw"]
-MW = ["dw", "qdw", "tw", "qtw"]
+ARITHS = ["fp64", "dw", "qdw", "tw", "qtw", "qtwe"]
+MW = ["dw", "qdw", "tw", "qtw", "qtwe"]
 
 
 def rel_error(x, xstar):
@@ -51,11 +51,11 @@ def test_manufactured_integer_solution(arith):
     A = P.poisson2d(24, 20)
     xstar = P.integer_vector(A.n, seed=3)
     b = (A.to_scipy().astype(np.int64) @ xstar.astype(np.int64)).astype(np.float64)
-    tol = {"fp64": 1e-14, "dw": 1e-28, "qdw": 1e-28, "tw": 1e-40, "qtw": 1e-40}[arith]
+    tol = {"fp64": 1e-14, "dw": 1e-28, "qdw": 1e-28, "tw": 1e-40, "qtw": 1e-40, "qtwe": 1e-40}[arith]
     x, info = O.cg_solve(arith, A, b, tol=tol)
     assert info["status"] == "ok", info
     err = rel_error(x, xstar)
-    limit = {"fp64": 1e-12, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-37}[arith]
+    limit = {"fp64": 1e-12, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-37, "qtwe": 1e-38}[arith]
     assert err < limit, err
     # the true residual, formed exactly, agrees with the recursive one's scale
     tr = O.true_residual(arith, A, b, x) / np.linalg.norm(b)
@@ -134,7 +134,7 @@ def test_invalid_arguments():
 
 
 def test_c1_iteration_counts_reasonable():
-    """2D Poisson 64x64, tol 1e-12: all five arithmetics converge within the
+    """2D Poisson 64x64, tol 1e-12: every arithmetic converges within the
     CG bound for kappa ~ 1.7e3 and agree closely with each other."""
     A, b, _ = P.case_poisson2d_64()
     its = {}

@@ -109,6 +109,9 @@ IMPL = {
     "qtw": dict(add=qtw_add, mul=qtw_mul, dxmul=qtw_dxmul, norm=vec_sum3),
     "tw": dict(add=lambda a, b: tw_renorm(qtw_add(a, b)), mul=lambda a, b: tw_renorm(qtw_mul(a, b)),
                dxmul=lambda a, b: tw_renorm(qtw_dxmul(a, b)), norm=tw_renorm),
+    # QTW with VecSum3 after every operation
+    "qtwe": dict(add=lambda a, b: vec_sum3(qtw_add(a, b)), mul=lambda a, b: vec_sum3(qtw_mul(a, b)),
+                 dxmul=lambda a, b: vec_sum3(qtw_dxmul(a, b)), norm=vec_sum3),
 }
 
 
@@ -126,7 +129,7 @@ def div(arith, a, b):
     return f["norm"]((q1, q2, q3))
 
 
-@pytest.mark.parametrize("arith", ["dw", "qdw", "tw", "qtw"])
+@pytest.mark.parametrize("arith", ["dw", "qdw", "tw", "qtw", "qtwe"])
 @pytest.mark.parametrize("op", ["add", "mul", "dxmul", "div", "norm"])
 def test_listing_bit_exact(arith, op):
     rng = np.random.default_rng(77)
