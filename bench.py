@@ -39,8 +39,8 @@ if ROOT not in sys.path:
 
 METRIC = "QTW CG time-to-1e-12 residual & SpMV HBM GB/s; batched/adjoint vs plain"
 HBM_PEAK_GBS = 8000.0
-WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3}
-ARITH_CODE = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4}
+WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3, "qtwe": 3}
+ARITH_CODE = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4, "qtwe": 5}
 
 
 def spmv_bytes(n, nnz, k):
@@ -180,7 +180,8 @@ def bench_illcond(mw, P, torch, dev, maxit=20000):
 def bench_normalisation(mw, torch, Ad, bd, n, maxit=2000):
     """3D Poisson 128^3, QDW and QTW, tol 1e-12: r normalised every K-th
     iteration (K = 1 is the paper's placement, 0 never): status, iterations,
-    time."""
+    time; and QTWE, VecSum3 after every operation (the other end of the
+    placement range; for QDW that placement is DW itself)."""
     out = {"workload": "3D Poisson 128^3, tol 1e-12, at most %d iterations" % maxit}
     for ar in ("qdw", "qtw"):
         x = torch.zeros((WORDS[ar], n), dtype=torch.float64, device=bd.device)
@@ -195,6 +196,14 @@ def bench_normalisation(mw, torch, Ad, bd, n, maxit=2000):
                                "seconds": round(time.perf_counter() - t0, 4)}
         out[ar] = row
         log("normalisation %s: %s" % (ar, row))
+    x = torch.zeros((3, n), dtype=torch.float64, device=bd.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = mw.cg_solve("qtwe", Ad, bd, x=x, tol=1e-12, maxit=maxit)
+    torch.cuda.synchronize()
+    out["qtwe_every_operation"] = {"status": info["status"], "iters": info["iters"], "rel_res": info["rel_res"],
+                                   "seconds": round(time.perf_counter() - t0, 4)}
+    log("normalisation qtwe (every operation): %s" % out["qtwe_every_operation"])
     return out
 
 

@@ -49,13 +49,18 @@
 extern "C" {
 #endif
 
-/* The five arithmetics (Sec. I list; Sec. V-B naming CG-FP64 ... CG-QTW). */
+/* The five arithmetics (Sec. I list; Sec. V-B naming CG-FP64 ... CG-QTW),
+ * and QTWE: QTW with VecSum3 (Alg. 9) after every operation, the
+ * every-operation end of the normalisation placement Sec. IV-D and VI leave
+ * open (3 words; r gets no extra normalisation; the QDW counterpart of this
+ * placement is DW itself). */
 typedef enum {
     MW_FP64 = 0,
     MW_DW = 1,
     MW_QDW = 2,
     MW_TW = 3,
-    MW_QTW = 4
+    MW_QTW = 4,
+    MW_QTWE = 5
 } mw_arith_t;
 
 /* Return codes. */

@@ -15,6 +15,10 @@
 // TW is the QTW operation followed by a renormalisation (VecSum bottom-up,
 // then VecSumErrBranch with three outputs, after Fabiano, Muller and Picot,
 // 2019), because the paper uses their TW algorithms without printing them.
+// QTWE is the QTW operation followed by VecSum3: normalisation after every
+// operation, the other end of the placement question Sec. IV-D and VI leave
+// open (the QDW counterpart is DW itself).  QTWE is not a "quasi" type for
+// the solver: r gets no extra normalisation.
 // On the GPU the branch of VecSumErrBranch is resolved with selects, so a
 // wavefront never diverges on it.
 #pragma once
@@ -25,7 +29,7 @@
 
 namespace mwk {
 
-enum Arith : int { FP64 = 0, DW = 1, QDW = 2, TW = 3, QTW = 4 };
+enum Arith : int { FP64 = 0, DW = 1, QDW = 2, TW = 3, QTW = 4, QTWE = 5 };
 
 __host__ __device__ constexpr int words(int a)
 {
@@ -122,7 +126,7 @@ __device__ __forceinline__ Num<A> normalise(Num<A> a)
 {
     if constexpr (A == DW || A == QDW) {
         quick_two_sum(a.w[0], a.w[1], a.w[0], a.w[1]);
-    } else if constexpr (A == QTW) {
+    } else if constexpr (A == QTW || A == QTWE) {
         vec_sum3(a.w[0], a.w[1], a.w[2]);
     } else if constexpr (A == TW) {
         tw_renorm(a.w[0], a.w[1], a.w[2]);
@@ -155,6 +159,7 @@ __device__ __forceinline__ Num<A> add(const Num<A> &a, const Num<A> &b)
         two_sum(t, e1, c.w[1], e3);
         c.w[2] = ((a.w[2] + b.w[2]) + e2) + e3;
         if constexpr (A == TW) tw_renorm(c.w[0], c.w[1], c.w[2]);
+        if constexpr (A == QTWE) vec_sum3(c.w[0], c.w[1], c.w[2]);
     }
     return c;
 }
@@ -188,6 +193,7 @@ __device__ __forceinline__ Num<A> mul(const Num<A> &a, const Num<A> &b)
         const double f3 = __builtin_fma(a.w[0], b.w[2], e4);
         c.w[2] = ((f1 + f2) + f3) + e5;
         if constexpr (A == TW) tw_renorm(c.w[0], c.w[1], c.w[2]);
+        if constexpr (A == QTWE) vec_sum3(c.w[0], c.w[1], c.w[2]);
     }
     return c;
 }
@@ -216,6 +222,7 @@ __device__ __forceinline__ Num<A> dxmul(double a, const Num<A> &b)
         two_sum(t, e1, c.w[1], e5);
         c.w[2] = __builtin_fma(a, b.w[2], e2) + e5;
         if constexpr (A == TW) tw_renorm(c.w[0], c.w[1], c.w[2]);
+        if constexpr (A == QTWE) vec_sum3(c.w[0], c.w[1], c.w[2]);
     }
     return c;
 }

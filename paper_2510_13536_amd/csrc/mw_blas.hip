@@ -440,6 +440,8 @@ template int spmv_launch<TW>(const mw_csr_t *, const mw_spmv_plan_t *, const dou
                              const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
 template int spmv_launch<QTW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
                               const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
+template int spmv_launch<QTWE>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
+                               const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
 
 size_t plan_bytes(int32_t n, int32_t nnz) { return plan_layout(n, nnz).bytes; }
 

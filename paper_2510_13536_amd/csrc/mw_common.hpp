@@ -157,7 +157,7 @@ void set_error(const char *msg);
 
 inline int blocks_for(long n, long per) { return (int)((n + per - 1) / per); }
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
-inline bool valid_arith(int a) { return a >= MW_FP64 && a <= MW_QTW; }
+inline bool valid_arith(int a) { return a >= MW_FP64 && a <= MW_QTWE; }
 inline bool valid_csr(const mw_csr_t *A)
 {
     return A && A->n > 0 && A->nnz >= 0 && A->row_ptr && A->col_idx && A->val;
@@ -186,5 +186,6 @@ inline bool valid_csr(const mw_csr_t *A)
     case MW_DW: return fn<mwk::DW>(__VA_ARGS__);         \
     case MW_QDW: return fn<mwk::QDW>(__VA_ARGS__);       \
     case MW_TW: return fn<mwk::TW>(__VA_ARGS__);         \
-    default: return fn<mwk::QTW>(__VA_ARGS__);           \
+    case MW_QTW: return fn<mwk::QTW>(__VA_ARGS__);       \
+    default: return fn<mwk::QTWE>(__VA_ARGS__);          \
     }

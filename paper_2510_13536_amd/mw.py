@@ -16,8 +16,8 @@ import torch
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmwcg.so")
 
-ARITH = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4}
-WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3}
+ARITH = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4, "qtwe": 5}
+WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3, "qtwe": 3}
 OPS = {"add": 0, "mul": 1, "dxmul": 2, "div": 3, "norm": 4, "neg": 5, "tofp64": 6}
 STATUS = {0: "ok", 1: "not_converged", 2: "breakdown"}
 MW_EINVAL, MW_EHIP = -1, -2

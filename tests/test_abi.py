@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_words_and_status_strings(lib):
-    assert [lib.mw_words(a) for a in range(5)] == [1, 2, 2, 3, 3]
+    assert [lib.mw_words(a) for a in range(6)] == [1, 2, 2, 3, 3, 3]
     assert lib.mw_words(7) == -1
     lib.mw_status_string.restype = C.c_char_p
     assert lib.mw_status_string(0) == b"ok"
@@ -63,7 +63,7 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     lib.mw_spmv.argtypes = [C.c_int, vp, vp, vp, vp]
     lib.mw_cg_solve.argtypes = [C.c_int, vp, vp, vp, C.c_double, C.c_int32, vp, vp, vp, vp]
     bogus = vp(0x1000)
-    assert lib.mw_elementwise(5, 0, 10, bogus, bogus, bogus, None) == -1   # arith
+    assert lib.mw_elementwise(6, 0, 10, bogus, bogus, bogus, None) == -1   # arith
     assert lib.mw_elementwise(1, 9, 10, bogus, bogus, bogus, None) == -1   # op
     assert lib.mw_elementwise(1, 0, -1, bogus, bogus, bogus, None) == -1   # n
     assert lib.mw_elementwise(1, 0, 10, bogus, None, bogus, None) == -1    # v needed
@@ -86,7 +86,7 @@ def test_builtin_launch_shapes(lib):
     lib.mw_cg_shape.argtypes = [C.c_int, C.c_int32, C.c_int32, C.c_int32, C.POINTER(Shape)]
     sh = Shape()
     n, nnz = 128 ** 3, 14581760
-    for a in range(5):
+    for a in range(6):
         assert lib.mw_cg_shape(a, n, nnz, 0, C.byref(sh)) == 0
         assert sh.spmv_grid == (1536 if a == 4 else 2048)
         assert (sh.update_grid, sh.update_threads, sh.chunk, sh.us_per_iteration) == (1024, 256, 32, 0.0)

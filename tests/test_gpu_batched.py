@@ -45,7 +45,7 @@ def small_batch():
     return mats, bs, P.batch_from_systems(mats, bs)
 
 
-@pytest.mark.parametrize("arith", ["fp64", "dw", "qdw", "tw", "qtw"])
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qdw", "tw", "qtw", "qtwe"])
 def test_batched_matches_oracle_per_system(mw, small_batch, arith):
     mats, bs, B = small_batch
     Ad = mw.DeviceCSR.from_host(B.A)

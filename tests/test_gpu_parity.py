@@ -20,7 +20,7 @@ from paper_2510_13536_amd import problems as P
 
 pytestmark = pytest.mark.gpu
 
-ARITHS = ["fp64", "dw", "qdw", "tw", "qtw"]
+ARITHS = ["fp64", "dw", "qdw", "tw", "qtw", "qtwe"]
 DOT_BOUND = {1: 2.0 ** -45, 2: 2.0 ** -100, 3: 2.0 ** -145}
 
 
@@ -301,7 +301,7 @@ def test_cg_tight_tolerance(mw, arith):
     A = P.poisson2d(40, 30)
     xs = P.integer_vector(A.n, seed=3)
     b = A.matvec(xs)
-    tol = {"fp64": 1e-14, "dw": 1e-28, "qdw": 1e-28, "tw": 1e-40, "qtw": 1e-40}[arith]
+    tol = {"fp64": 1e-14, "dw": 1e-28, "qdw": 1e-28, "tw": 1e-40, "qtw": 1e-40, "qtwe": 1e-40}[arith]
     xg, ig, io = cg_parity(mw, arith, A, b, tol)
     # x_0 - x* is exact (x_0 is within a few units in the last place of the
     # integer); the lower words are then small enough to add in FP64
@@ -309,7 +309,7 @@ def test_cg_tight_tolerance(mw, arith):
     for w in range(1, xg.shape[0]):
         e = e + xg[w]
     err = np.abs(e).max() / np.abs(xs).max()
-    assert err < {"fp64": 1e-12, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-38}[arith]
+    assert err < {"fp64": 1e-12, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-38, "qtwe": 1e-38}[arith]
 
 
 def _diag_indefinite(seed, n=24):
@@ -332,7 +332,7 @@ def _x_close(arith, xg, xo):
     return np.abs(e).max() / np.abs(xo[0]).max()
 
 
-X_BOUND = {"fp64": 1e-13, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-38}
+X_BOUND = {"fp64": 1e-13, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-38, "qtwe": 1e-38}
 
 
 @pytest.mark.parametrize("arith", ARITHS)
