@@ -678,6 +678,131 @@ done:
 }
 
 /* ------------------------------------------------------------------------
+ * Exported: Jacobi-preconditioned CG (an extension the paper names as
+ * future work, Sec. VI; its algorithm is not in the paper)
+ * ---------------------------------------------------------------------- */
+/*
+ * Reading: the textbook preconditioned CG with M = diag(A), where M^-1 is
+ * the FP64 diagonal matrix of the rounded reciprocals d_i = fl(1 / a_ii)
+ * (so multi-word arithmetic stays in the SpMV, the dots and the vector
+ * updates, and the preconditioner is one FP64 x multi-word product per
+ * row).  The stopping test is the paper's, on the residual r itself.
+ *   r = b - A x;  z = D r (z_i = d_i x r_i, the FP64 x multi-word product);
+ *   p = z;  rho = r^T z;  rr = r^T r;  nb = sqrt(fp64(b^T b))
+ *   rr == 0: return, 0 iterations.
+ *   loop:
+ *     q = A p;  sigma = p^T q;  (sigma <= 0 or not finite: breakdown)
+ *     alpha = rho / sigma
+ *     x = x + alpha p;  r = r + (-(alpha q));  QDW/QTW: r = normalise(r)
+ *       as in mwo_cg_solve (normalise_r = K)
+ *     z = D r;  rho' = r^T z;  rr = r^T r;  iters++
+ *     sqrt(fp64(rr)) / nb < tol: converged
+ *     iters == maxit: not converged
+ *     beta = rho' / rho;  p = z + beta p;  rho = rho'
+ * A row without a stored diagonal entry, or a zero one, makes d_i
+ * infinite, and the solve ends with a breakdown.  FP64 uses fma for every
+ * a*x + y and one rounded product for z.
+ */
+static mwv jacobi_apply(int arith, double d, mwv r)
+{
+    if (arith == MWO_FP64) return mw_promote(f_mul(d, r.w[0]));
+    return mw_dxmul(arith, d, r);
+}
+
+int mwo_pcg_jacobi_solve(int arith, long n, const int32_t *row_ptr, const int32_t *col,
+                         const double *val, const double *b, double *x, double tol,
+                         int32_t maxit, int32_t normalise_r, mwo_cg_info *info, double *hist)
+{
+    int k = words_of(arith);
+    if (k < 0 || n <= 0 || !(tol >= 0.0) || maxit < 0 || !info) return MWO_EINVAL;
+    int quasi = (arith == MWO_QDW || arith == MWO_QTW);
+    double *r = calloc((size_t)k * n, sizeof(double));
+    double *z = calloc((size_t)k * n, sizeof(double));
+    double *p = calloc((size_t)k * n, sizeof(double));
+    double *q = calloc((size_t)k * n, sizeof(double));
+    double *bw = calloc((size_t)k * n, sizeof(double));
+    double *d = calloc((size_t)n, sizeof(double));
+    if (!r || !z || !p || !q || !bw || !d) {
+        free(r); free(z); free(p); free(q); free(bw); free(d);
+        return MWO_EINVAL;
+    }
+    memcpy(bw, b, sizeof(double) * n);
+    for (long i = 0; i < n; i++) {
+        double aii = 0.0;
+        for (int32_t j = row_ptr[i]; j < row_ptr[i + 1]; j++)
+            if (col[j] == i) aii = val[j];
+        d[i] = f_div(1.0, aii);
+    }
+
+    info->iters = 0;
+    info->status = MWO_OK;
+    info->rel_res = 0.0;
+    info->seconds = 0.0;
+
+    spmv_rows(arith, n, row_ptr, col, val, x, q);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; i++) {
+        mwv ri;
+        if (arith == MWO_FP64) ri = mw_promote(f_sub(b[i], q[i]));
+        else ri = mw_add(arith, mw_promote(b[i]), mw_neg(mw_load(k, q, n, i)));
+        mw_store(k, r, n, i, ri);
+        mw_store(k, z, n, i, jacobi_apply(arith, d[i], ri));
+    }
+    memcpy(p, z, sizeof(double) * k * n);
+    mwv rho = dot_seq(arith, n, r, z);
+    double rr = mw_to_fp64(arith, dot_seq(arith, n, r, r));
+    double nb = sqrt(mw_to_fp64(arith, dot_seq(arith, n, bw, bw)));
+    int status = MWO_OK;
+
+    if (rr == 0.0) goto done;
+    info->rel_res = sqrt(rr) / nb;
+    if (maxit == 0) { status = MWO_NOT_CONVERGED; goto done; }
+
+    for (;;) {
+        spmv_rows(arith, n, row_ptr, col, val, p, q);
+        mwv sigma = dot_seq(arith, n, p, q);
+        double s64 = mw_to_fp64(arith, sigma);
+        if (!(s64 > 0.0) || !isfinite(s64)) { status = MWO_BREAKDOWN; break; }
+        mwv alpha = mw_div(arith, rho, sigma);
+        if (!isfinite(mw_to_fp64(arith, alpha))) { status = MWO_BREAKDOWN; break; }
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; i++) {
+            mwv ri;
+            if (arith == MWO_FP64) {
+                x[i] = f_fma(alpha.w[0], p[i], x[i]);
+                ri = mw_promote(f_fma(-alpha.w[0], q[i], r[i]));
+            } else {
+                mwv pi = mw_load(k, p, n, i), qi = mw_load(k, q, n, i);
+                mw_store(k, x, n, i, mw_add(arith, mw_load(k, x, n, i), mw_mul(arith, alpha, pi)));
+                ri = mw_add(arith, mw_load(k, r, n, i), mw_neg(mw_mul(arith, alpha, qi)));
+                if (quasi && normalise_r > 0 && (info->iters + 1) % normalise_r == 0) ri = mw_normalise(arith, ri);
+            }
+            mw_store(k, r, n, i, ri);
+            mw_store(k, z, n, i, jacobi_apply(arith, d[i], ri));
+        }
+        mwv rho_new = dot_seq(arith, n, r, z);
+        rr = mw_to_fp64(arith, dot_seq(arith, n, r, r));
+        info->iters++;
+        if (!isfinite(rr) || !isfinite(mw_to_fp64(arith, rho_new))) { status = MWO_BREAKDOWN; break; }
+        info->rel_res = sqrt(rr) / nb;
+        if (hist && info->iters <= maxit) hist[info->iters - 1] = info->rel_res;
+        if (info->rel_res < tol) break;
+        if (info->iters >= maxit) { status = MWO_NOT_CONVERGED; break; }
+        mwv beta = mw_div(arith, rho_new, rho);
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; i++) {
+            if (arith == MWO_FP64) p[i] = f_fma(beta.w[0], p[i], z[i]);
+            else mw_store(k, p, n, i, mw_add(arith, mw_load(k, z, n, i), mw_mul(arith, beta, mw_load(k, p, n, i))));
+        }
+        rho = rho_new;
+    }
+done:
+    info->status = status;
+    free(r); free(z); free(p); free(q); free(bw); free(d);
+    return status;
+}
+
+/* ------------------------------------------------------------------------
  * Exact references: a long fixed-point (Kulisch) accumulator.
  * The accumulator is a 2304-bit two's-complement integer whose least
  * significant bit weighs 2^-1152; every finite double, and every sum of up

@@ -50,6 +50,8 @@ def _load(name):
     lib.mwo_axpy.argtypes = [C.c_int, C.c_long, _dp, _dp, _dp]
     lib.mwo_cg_solve.argtypes = [C.c_int, C.c_long, _ip, _ip, _dp, _dp, _dp, C.c_double,
                                  C.c_int32, C.c_int32, C.POINTER(CGInfo), _dp]
+    lib.mwo_pcg_jacobi_solve.argtypes = [C.c_int, C.c_long, _ip, _ip, _dp, _dp, _dp, C.c_double,
+                                         C.c_int32, C.c_int32, C.POINTER(CGInfo), _dp]
     lib.mwo_exact_dot_limbs.argtypes = [C.c_int, C.c_long, _dp, _dp, _u64p]
     lib.mwo_exact_sum_limbs.argtypes = [C.c_long, _dp, _u64p]
     lib.mwo_dot_error.argtypes = [C.c_int, C.c_long, _dp, _dp, _dp, _dp, _dp]
@@ -186,11 +188,15 @@ def axpy(arith, alpha, x, y):
     return yy
 
 
-def cg_solve(arith, A, b, x0=None, tol=1e-12, maxit=None, normalise=True, history=False):
+def cg_solve(arith, A, b, x0=None, tol=1e-12, maxit=None, normalise=True, history=False, precond=None):
     """CG per the oracle.  Returns (x (k, n), info dict).
 
     normalise (QDW/QTW): True / 1 normalises r every iteration (Sec. IV-D),
-    False / 0 never; an integer K > 1 in iterations K, 2K, ..."""
+    False / 0 never; an integer K > 1 in iterations K, 2K, ...
+    precond: None (Alg. 1) or "jacobi" (preconditioned CG with the FP64
+    reciprocal diagonal, mwo_pcg_jacobi_solve)."""
+    if precond not in (None, "jacobi"):
+        raise ValueError("precond must be None or 'jacobi'")
     k = WORDS[arith]
     n, rp, ci, va = _csr(A)
     b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
@@ -201,9 +207,9 @@ def cg_solve(arith, A, b, x0=None, tol=1e-12, maxit=None, normalise=True, histor
         maxit = 10 * n
     info = CGInfo()
     hist = np.zeros(max(int(maxit), 1)) if history else None
-    rc = lib().mwo_cg_solve(ARITH[arith], n, _i(rp), _i(ci), _d(va), _d(b), _d(x), float(tol),
-                            int(maxit), int(normalise), C.byref(info),
-                            _d(hist) if history else None)
+    fn = lib().mwo_pcg_jacobi_solve if precond == "jacobi" else lib().mwo_cg_solve
+    rc = fn(ARITH[arith], n, _i(rp), _i(ci), _d(va), _d(b), _d(x), float(tol),
+            int(maxit), int(normalise), C.byref(info), _d(hist) if history else None)
     _check(rc)
     out = {"iters": info.iters, "status": STATUS[info.status], "status_code": info.status,
            "rel_res": info.rel_res}

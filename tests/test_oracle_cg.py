@@ -213,3 +213,69 @@ def test_initial_guess(arith):
     x, info = O.cg_solve(arith, A, b, x0=x0, tol=1e-12)
     assert info["status"] == "ok" and 0 < info["iters"] < 500
     assert np.max(np.abs(x.sum(axis=0) - xstar)) < 1e-8
+
+
+# ------------------------------------------- Jacobi-preconditioned CG
+#
+# Preconditioned CG with M^-1 = diag(fl(1 / a_ii)) (an extension: the paper
+# names preconditioning as future work, Sec. VI).  Pins independent of the
+# implementation:
+#  * diagonal 4 (2D Poisson) or 2 (1D Poisson): M^-1 = I/4 or I/2 is exact and
+#    every product, quotient and dot of PCG is CG's scaled by a power of two,
+#    so PCG reproduces CG bit for bit (x, iterations, residuals);
+#  * a diagonal matrix: M^-1 A = I + E, |E| <= one rounding, so each step cuts
+#    the residual by ~u and a k-word arithmetic converges in at most k steps;
+#  * D A D scaling (the ill-conditioned banded case) is undone by Jacobi.
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_pcg_jacobi_power_of_two_diagonal_is_cg(arith):
+    for A, b in ((lambda c: (c[0], c[1]))(P.case_poisson2d_64()),
+                 (P.poisson1d(300), np.random.default_rng(8).uniform(-1, 1, 300))):
+        x1, i1 = O.cg_solve(arith, A, b, tol=1e-12, history=True)
+        x2, i2 = O.cg_solve(arith, A, b, tol=1e-12, history=True, precond="jacobi")
+        assert i1["iters"] == i2["iters"] and i1["status"] == i2["status"] == "ok"
+        assert np.array_equal(x1.view(np.uint64), x2.view(np.uint64))
+        assert np.array_equal(i1["history"], i2["history"])
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_pcg_jacobi_diagonal_matrix(arith):
+    rng = np.random.default_rng(9)
+    d = rng.uniform(0.3, 7.0, 500)
+    M = P.CSR.from_scipy(sp.diags(d, 0).tocsr())
+    b = rng.uniform(-1, 1, 500)
+    tol = {"fp64": 1e-12, "dw": 1e-28, "qdw": 1e-28, "tw": 1e-40, "qtw": 1e-40, "qtwe": 1e-40}[arith]
+    x, info = O.cg_solve(arith, M, b, tol=tol, precond="jacobi")
+    assert info["status"] == "ok" and info["iters"] <= O.WORDS[arith]
+    _, plain = O.cg_solve(arith, M, b, tol=tol)
+    assert plain["iters"] > 20 * O.WORDS[arith]
+    # the solution itself: x_i = b_i / d_i to the arithmetic's precision
+    xs = np.asarray(x).reshape(O.WORDS[arith], -1)
+    for i in range(0, 500, 37):
+        ex = Fraction(float(b[i])) / Fraction(float(d[i]))
+        got = sum((Fraction(float(xs[w, i])) for w in range(xs.shape[0])), Fraction(0))
+        assert abs(got - ex) <= abs(ex) * 64 * tol
+
+
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qtw"])
+def test_pcg_jacobi_undoes_diagonal_scaling(arith):
+    A, b, _ = P.case_banded_illcond(n=2048)
+    _, plain = O.cg_solve(arith, A, b, tol=1e-10, maxit=2000)
+    x, pc = O.cg_solve(arith, A, b, tol=1e-10, maxit=2000, precond="jacobi")
+    assert plain["status"] == "not_converged"
+    assert pc["status"] == "ok" and pc["iters"] <= 40
+    assert O.true_residual(arith, A, b, x) / np.linalg.norm(b) < 1e-9
+
+
+def test_pcg_jacobi_edge_cases():
+    # a missing (zero) diagonal entry: infinite reciprocal, breakdown at once
+    M = P.CSR.from_scipy(sp.csr_matrix(np.array([[0.0, 1.0], [1.0, 2.0]])))
+    _, info = O.cg_solve("dw", M, np.array([1.0, 1.0]), precond="jacobi")
+    assert info["status"] == "breakdown" and info["iters"] == 0
+    A = P.poisson2d(12)
+    _, info = O.cg_solve("qtw", A, np.zeros(A.n), precond="jacobi")
+    assert info["status"] == "ok" and info["iters"] == 0
+    _, info = O.cg_solve("qtw", A, np.ones(A.n), precond="jacobi", maxit=3, tol=0.0)
+    assert info["status"] == "not_converged" and info["iters"] == 3
+    with pytest.raises(ValueError):
+        O.cg_solve("dw", A, np.ones(A.n), precond="ilu")
