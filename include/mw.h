@@ -168,6 +168,14 @@ typedef struct {
                                 iteration of the chosen shape              */
 } mw_shape_t;
 
+/* Preconditioners of mw_cg_solve (opts->precond). */
+enum {
+    MW_PRECOND_NONE = 0,    /* plain CG, Alg. 1                              */
+    MW_PRECOND_JACOBI = 1   /* M^-1 = diag(fl(1 / a_ii)), an extension: the
+                               paper names preconditioning as future work
+                               (Sec. VI)                                     */
+};
+
 /* Solver options (host memory); pass NULL for the defaults. */
 typedef struct {
     int32_t normalize;  /* QDW/QTW: K >= 1 normalises r right after its
@@ -187,7 +195,9 @@ typedef struct {
                            the solver builds one inside its workspace      */
     int32_t no_graph;   /* nonzero: launch each kernel directly instead of
                            replaying a captured hipGraph of a chunk       */
-    int32_t reserved;
+    int32_t precond;    /* MW_PRECOND_NONE (0): Alg. 1.  MW_PRECOND_JACOBI:
+                           Jacobi-preconditioned CG (see mw_cg_solve); the
+                           batched solver accepts 0 only                  */
     const mw_shape_t *shape;  /* optional launch shape; its set fields take
                            precedence over a tuned shape (mw_cg_tune), which
                            takes precedence over the MW_SGRID / MW_UGRID /
@@ -299,9 +309,10 @@ int mw_csr_grad(mw_arith_t a, const mw_csr_t *A, const double *lam, const double
                 void *stream);
 
 /* Bytes of device workspace mw_cg_solve needs (256-byte aligned): the
- * vectors r and q, the search direction (TW/QTW: two buffers, so that x
- * takes the updates of two iterations in one pass), partial sums, the
- * solver state and room for a SpMV plan of A. */
+ * vectors r and q, the search direction (3-word types: two buffers, so
+ * that x takes the updates of two iterations in one pass), the Jacobi
+ * reciprocals, partial sums, the solver state and room for a SpMV plan of
+ * A. */
 size_t mw_cg_workspace_bytes(mw_arith_t a, int32_t n, int32_t nnz);
 
 /*
@@ -315,6 +326,15 @@ size_t mw_cg_workspace_bytes(mw_arith_t a, int32_t n, int32_t nnz);
  *   rho' = r^T r;  stop when sqrt(fp64(rho')) / ||b|| < tol (MW_OK) or
  *   after maxit iterations (MW_NOT_CONVERGED);  beta = rho' / rho;
  *   p = r + beta p.
+ * With opts->precond = MW_PRECOND_JACOBI the textbook preconditioned CG
+ * runs instead, with M^-1 the FP64 diagonal d_i = fl(1 / a_ii) applied as
+ * the FP64 x multi-word product (FP64: one rounded product):
+ *   r = b - A x;  z = D r;  p = z;  rho = r^T z;  rr = r^T r;  stop at once
+ *   when fp64(rr) = 0;  each iteration as above up to the normalisation of
+ *   r, then z = D r;  rho' = r^T z;  rr = r^T r;  the test uses
+ *   sqrt(fp64(rr)) / ||b|| (the paper's residual test);  beta = rho' / rho;
+ *   p = z + beta p.  A row without a nonzero stored diagonal entry makes
+ *   d_i infinite: MW_BREAKDOWN at the first test.
  * A: FP64 CSR, SPD; b: FP64[n]; x: k planes of n, in/out (pass zeros for
  * the paper's x0 = 0); tol >= 0; maxit >= 0; opts may be NULL; workspace:
  * at least mw_cg_workspace_bytes(a, n, nnz) bytes of device memory; info
@@ -350,7 +370,7 @@ size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int3
  * info (host, may be NULL): iters = the largest count, status = the worst
  * status (MW_OK < MW_NOT_CONVERGED < MW_BREAKDOWN), seconds.  opts:
  * normalize, chunk (default 16), no_graph and shape (spmv_grid, chunk) are
- * honoured.  All systems advance in lockstep, five kernels per iteration
+ * honoured; precond must be MW_PRECOND_NONE (else MW_EINVAL).  All systems advance in lockstep, five kernels per iteration
  * replayed from a captured hipGraph;
  * a converged system's rows cost a flag test per 64-row slice afterwards.
  * Each system gives the same results whatever the other systems are, but

@@ -690,7 +690,8 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
                         int32_t *iters, int32_t *status, double *rel_res, mw_cg_info_t *info, void *stream)
 {
     if (!batched_args_ok(a, nsys, sys_row_off, A, b, x, workspace) || !(tol >= 0.0) || maxit < 0) return MW_EINVAL;
-    if (opts && (!shape_valid(opts->shape) || opts->normalize < 0)) return MW_EINVAL;
+    if (opts && (!shape_valid(opts->shape) || opts->normalize < 0 || opts->precond != MW_PRECOND_NONE))
+        return MW_EINVAL;
     MW_DISPATCH(a, batched_a, nsys, sys_row_off, A, b, x, tol, maxit, opts, workspace, iters, status, rel_res, info,
                 (hipStream_t)stream);
 }

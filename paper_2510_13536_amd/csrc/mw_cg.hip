@@ -26,6 +26,12 @@
 // produces are stored per iteration parity (alpha per buffer), so no
 // workgroup reads what another workgroup of the same kernel writes; the
 // parity and buffer of each launch are kernel arguments.
+// Jacobi-preconditioned CG (opts->precond; preconditioning is future work
+// in Sec. VI): the same three kernels with z = D r formed where r is (D the
+// FP64 reciprocals of A's diagonal, applied as the FP64 x multi-word
+// product): step 2 adds the partials of r^T z beside those of r^T r, step 3
+// recomputes z from r (cheaper than storing it) for p = z + beta p and
+// tests r^T r.
 // After the stop every kernel only passes the stop flag on and exits, so a
 // chunk of iterations is enqueued (or replayed from a captured hipGraph)
 // and the host checks the flag once per chunk.  All reductions use fixed
@@ -43,16 +49,42 @@ namespace {
 // Workspace slot arrays hold the partials of up to this many workgroups.
 constexpr int UGRID_MAX = MAX_GRID;
 
-// r = b - q (q = A x0), p = r, partials of r^T r and b^T b.
+// z_i = d_i r_i, the Jacobi step: the FP64 reciprocal times the multi-word
+// residual (FP64: one rounded product).
 template <int A>
+__device__ __forceinline__ Num<A> jacobi(double d, const Num<A> &r)
+{
+    if constexpr (A == FP64) return promote<A>(d * r.w[0]);
+    else return dxmul<A>(d, r);
+}
+
+// d_i = fl(1 / a_ii) from the CSR rows (the last stored entry in column i;
+// none: 1 / 0 = inf, which ends the solve with a breakdown).
+__global__ void __launch_bounds__(NT) mw_cg_dinv_kernel(int n, const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const double *__restrict__ val, double *__restrict__ dinv)
+{
+    const long i = (long)blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    double aii = 0.0;
+    for (int j = row_ptr[i]; j < row_ptr[i + 1]; ++j)
+        if (col[j] == i) aii = val[j];
+    dinv[i] = 1.0 / aii;
+}
+
+// r = b - q (q = A x0), p = r, partials of r^T r and b^T b.  PC (Jacobi):
+// p = z = D r, partials of r^T z (to slots_rr), b^T b and r^T r (to
+// slots_c).
+template <int A, bool PC>
 __global__ void __launch_bounds__(NT) mw_cg_init_kernel(int n, const double *__restrict__ b,
                                                         const double *__restrict__ q, double *__restrict__ r,
                                                         double *__restrict__ p, double *__restrict__ slots_rr,
-                                                        double *__restrict__ slots_bb)
+                                                        double *__restrict__ slots_bb, const double *__restrict__ dinv,
+                                                        double *__restrict__ slots_c)
 {
     constexpr int K = words(A);
     const TileRange tr = xcd_tiles((n + NT - 1) / NT);
-    Num<A> rr = zero<A>(), bb = zero<A>();
+    Num<A> rr = zero<A>(), bb = zero<A>(), rz = zero<A>();
     for (int t = tr.first; t < tr.end; t += tr.step) {
         const long i = (long)t * NT + threadIdx.x;
         if (i >= n) continue;
@@ -61,33 +93,47 @@ __global__ void __launch_bounds__(NT) mw_cg_init_kernel(int n, const double *__r
         if constexpr (A == FP64) ri = promote<A>(bi.w[0] - q[i]);
         else ri = add<A>(bi, neg<A>(load<A>(q, n, i)));
         store<A>(r, n, i, ri);
-        store_il<A>(p, n, i, ri);
+        if constexpr (PC) {
+            const Num<A> zi = jacobi<A>(dinv[i], ri);
+            store_il<A>(p, n, i, zi);
+            rz = dot_step<A>(rz, ri, zi);
+        } else {
+            store_il<A>(p, n, i, ri);
+        }
         rr = dot_step<A>(rr, ri, ri);
         bb = dot_step<A>(bb, bi, bi);
     }
-    const Num<A> s1 = block_sum<A, NT>(rr);
+    const Num<A> s1 = block_sum<A, NT>(PC ? rz : rr);
     const Num<A> s2 = block_sum<A, NT>(bb);
     if (threadIdx.x == 0) {
         store_scalar<A>(slots_rr + (long)blockIdx.x * K, s1);
         store_scalar<A>(slots_bb + (long)blockIdx.x * K, s2);
     }
+    if constexpr (PC) {
+        const Num<A> s3 = block_sum<A, NT>(rr);
+        if (threadIdx.x == 0) store_scalar<A>(slots_c + (long)blockIdx.x * K, s3);
+    }
 }
 
-// rho0, ||b|| and the initial flags (parity 0).
-template <int A>
+// rho0 (PC: r^T z), ||b|| and the initial flags (parity 0); the start test
+// uses r^T r.
+template <int A, bool PC>
 __global__ void __launch_bounds__(FIN_NT) mw_cg_init_final_kernel(int nslots, const double *__restrict__ slots_rr,
                                                                   const double *__restrict__ slots_bb,
+                                                                  const double *__restrict__ slots_c,
                                                                   CgState *__restrict__ st)
 {
     const Num<A> rho = reduce_slots<A>(nslots, slots_rr);
     const Num<A> bb = reduce_slots<A>(nslots, slots_bb);
+    Num<A> rr = rho;
+    if constexpr (PC) rr = reduce_slots<A>(nslots, slots_c);
     if (threadIdx.x == 0) {
         store_scalar<A>(st->rho[0], rho);
         st->nb = sqrt(to_fp64<A>(bb));
         st->iters[0] = 0;
         st->iters_final = 0;
         st->status = MW_OK;
-        const double r64 = to_fp64<A>(rho);
+        const double r64 = to_fp64<A>(rr);
         int run = 1;
         if (r64 == 0.0) {
             st->rel_res = 0.0;
@@ -109,12 +155,14 @@ __global__ void __launch_bounds__(FIN_NT) mw_cg_init_final_kernel(int nslots, co
 // derive the same sigma and alpha = rho / sigma (stored in slot kpos);
 // breakdown (sigma <= 0 or a non-finite value) stops the solve before r or
 // p change.  Then r = r - alpha q, quasi types normalise r, and the
-// workgroup partial of r^T r goes to slots_out.
-template <int A, int UNT>
+// workgroup partial of r^T r goes to slots_out.  PC (Jacobi): the partial
+// of r^T z (z = D r) goes to slots_out and that of r^T r to slots_out2.
+template <int A, int UNT, bool PC>
 __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in, const double *__restrict__ slots_in,
                                                            const double *__restrict__ q, double *__restrict__ r,
                                                            double *__restrict__ slots_out, CgState *__restrict__ st,
-                                                           int par, int kpos, int rev)
+                                                           int par, int kpos, int rev, const double *__restrict__ dinv,
+                                                           double *__restrict__ slots_out2)
 {
     constexpr int K = words(A);
     __shared__ Num<A> s_alpha;
@@ -168,7 +216,7 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
     // iteration, is Sec. IV-D; 0 never)
     const int NK = st->normalize;
     const bool norm = is_quasi(A) && NK > 0 && (st->iters[par ^ 1] + 1) % NK == 0;
-    Num<A> rr = zero<A>();
+    Num<A> rr = zero<A>(), rz = zero<A>();
     for (int m = 0; m < tw.count; ++m) {
         const long i = (long)tw[m] * UNT + threadIdx.x;
         if (i >= n) continue;
@@ -177,10 +225,15 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
         Num<A> ri = axmy_term<A>(al, qi, rv);
         if (norm) ri = normalise<A>(ri);
         store<A>(r, n, i, ri);
+        if constexpr (PC) rz = dot_step<A>(rz, ri, jacobi<A>(dinv[i], ri));
         rr = dot_step<A>(rr, ri, ri);
     }
-    const Num<A> sum = block_sum<A, UNT>(rr);
+    const Num<A> sum = block_sum<A, UNT>(PC ? rz : rr);
     if (threadIdx.x == 0) store_scalar<A>(slots_out + (long)blockIdx.x * K, sum);
+    if constexpr (PC) {
+        const Num<A> sum2 = block_sum<A, UNT>(rr);
+        if (threadIdx.x == 0) store_scalar<A>(slots_out2 + (long)blockIdx.x * K, sum2);
+    }
 }
 
 // Iteration step 3 (parity par; iteration k with k % XR = kpos, XR =
@@ -194,11 +247,15 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
 // stops here, those of iterations k - kpos .. k - 1 after a breakdown of
 // this iteration's alpha step.  With XR = 2 and kpos = 1 that reads
 // p_{k-1} from po before the same thread stores p_{k+1} there.
-template <int A, int UNT>
+// PC (Jacobi): slots_in holds the r^T z partials (rho'), slots_in2 those of
+// r^T r (the test), and p_{k+1} = z + beta p_k with z = D r recomputed.
+template <int A, int UNT, bool PC>
 __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in, const double *__restrict__ slots_in,
                                                            const double *__restrict__ r, double *__restrict__ pk,
                                                            double *__restrict__ po, double *__restrict__ x,
-                                                           CgState *__restrict__ st, int par, int kpos_arg, int rev)
+                                                           CgState *__restrict__ st, int par, int kpos_arg, int rev,
+                                                           const double *__restrict__ slots_in2,
+                                                           const double *__restrict__ dinv)
 {
     constexpr int XR = xr(A);
     static_assert(XR == 1 || XR == 2, "one or two search-direction buffers");
@@ -239,10 +296,12 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
         r1 = load<A>(r, n, i1);
     }
     const Num<A> rho_new = reduce_slots<A, UNT>(nslots_in, slots_in);
+    Num<A> rr_new = rho_new;
+    if constexpr (PC) rr_new = reduce_slots<A, UNT>(nslots_in, slots_in2);
     if (threadIdx.x == 0) {
         const int it = st->iters[par ^ 1] + 1;
-        const double rr = to_fp64<A>(rho_new);
-        const bool fin = isfinite(rr);
+        const double rr = to_fp64<A>(rr_new);
+        const bool fin = isfinite(rr) && (!PC || isfinite(to_fp64<A>(rho_new)));
         const double rel = fin ? sqrt(rr) / st->nb : rr;
         const bool conv = fin && rel < st->tol;
         const bool stop = !fin || conv || it >= st->maxit;
@@ -282,7 +341,8 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
         }
         if (!stop) {
             const Num<A> rv = m == 0 ? r0 : (m == 1 ? r1 : load<A>(r, n, i));
-            store_il<A>(pn, n, i, axpy_term<A>(be, pi, rv));
+            if constexpr (PC) store_il<A>(pn, n, i, axpy_term<A>(be, pi, jacobi<A>(dinv[i], rv)));
+            else store_il<A>(pn, n, i, axpy_term<A>(be, pi, rv));
         }
     }
 }
@@ -290,7 +350,7 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
 // ------------------------------------------------------------ host side
 
 struct CgLayout {
-    size_t r, p, q, slots_a, slots_b, state, plan, total;
+    size_t r, p, q, slots_a, slots_b, slots_c, dinv, state, plan, total;
     size_t plane;  // bytes of one vector (k planes of n, 256-aligned)
 };
 
@@ -306,7 +366,9 @@ CgLayout cg_layout(int a, int32_t n, int32_t nnz)
     L.q = L.p + (size_t)xr(a) * plane;
     L.slots_a = L.q + plane;
     L.slots_b = L.slots_a + slots;
-    L.state = L.slots_b + slots;
+    L.slots_c = L.slots_b + slots;  // Jacobi: the r^T r partials
+    L.dinv = L.slots_c + slots;     // Jacobi: d_i = fl(1 / a_ii)
+    L.state = L.dinv + align256(sizeof(double) * (size_t)n);
     L.plan = L.state + align256(sizeof(CgState));
     L.total = L.plan + plan_bytes(n, nnz);
     L.plane = plane;
@@ -359,7 +421,10 @@ constexpr int KCLASS[NKERN] = {MW_PROF_SPMV, MW_PROF_UPDATE_R, MW_PROF_UPDATE_P}
 // Everything one chunk of iterations needs.
 struct ChunkArgs {
     int arith, n, nslots_sp, nslots_up, chunk, timed_mask, unt, ugrid;
+    int pc;        // Jacobi preconditioner
     long pstride;  // doubles between the search-direction buffers
+    const double *dinv;
+    double *slots_c;
     const mw_csr_t *M;
     const mw_spmv_plan_t *plan;
     double *r, *p, *q, *x, *slots_a, *slots_b;
@@ -368,7 +433,8 @@ struct ChunkArgs {
 
 bool same_key(const ChunkArgs &a, const ChunkArgs &b)
 {
-    return a.arith == b.arith && a.n == b.n && a.nslots_sp == b.nslots_sp && a.nslots_up == b.nslots_up &&
+    return a.arith == b.arith && a.n == b.n && a.pc == b.pc && a.dinv == b.dinv && a.slots_c == b.slots_c &&
+           a.nslots_sp == b.nslots_sp && a.nslots_up == b.nslots_up &&
            a.chunk == b.chunk && a.pstride == b.pstride && a.timed_mask == b.timed_mask && a.unt == b.unt && a.ugrid == b.ugrid && a.r == b.r && a.p == b.p && a.q == b.q &&
            a.x == b.x && a.slots_a == b.slots_a && a.slots_b == b.slots_b && a.st == b.st && a.plan && b.plan &&
            a.plan->format == b.plan->format && a.plan->nslices == b.plan->nslices &&
@@ -382,18 +448,25 @@ bool same_key(const ChunkArgs &a, const ChunkArgs &b)
 // after a multiple of it: iteration j of the chunk, 0-based, has parity
 // (j + 1) & 1 and uses search-direction buffer j % xr(A)).  With a mask,
 // the kernels of the timed classes carry a pair of events.
-template <int A, int UNT>
+template <int A, int UNT, bool PC>
 void launch_steps(const ChunkArgs &c, int k, int par, int kpos, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const int gu = c.nslots_up;
     // consecutive kernels walk the rows in opposite directions
     if (k == 1)
-        MW_LAUNCH((mw_cg_step_r_kernel<A, UNT>), dim3(gu), dim3(UNT), s, e0, e1, c.n, c.nslots_sp, c.slots_a, c.q,
-                  c.r, c.slots_b, c.st, par, kpos, par ^ 1);
+        MW_LAUNCH((mw_cg_step_r_kernel<A, UNT, PC>), dim3(gu), dim3(UNT), s, e0, e1, c.n, c.nslots_sp, c.slots_a,
+                  c.q, c.r, c.slots_b, c.st, par, kpos, par ^ 1, c.dinv, c.slots_c);
     else
-        MW_LAUNCH((mw_cg_step_p_kernel<A, UNT>), dim3(gu), dim3(UNT), s, e0, e1, c.n, c.nslots_up, c.slots_b, c.r,
-                  c.p + kpos * c.pstride, xr(A) == 1 ? nullptr : c.p + ((kpos + 1) % xr(A)) * c.pstride, c.x, c.st,
-                  par, kpos, par);
+        MW_LAUNCH((mw_cg_step_p_kernel<A, UNT, PC>), dim3(gu), dim3(UNT), s, e0, e1, c.n, c.nslots_up, c.slots_b,
+                  c.r, c.p + kpos * c.pstride, xr(A) == 1 ? nullptr : c.p + ((kpos + 1) % xr(A)) * c.pstride, c.x,
+                  c.st, par, kpos, par, c.slots_c, c.dinv);
+}
+
+template <int A, int UNT>
+void launch_steps_pc(const ChunkArgs &c, int k, int par, int kpos, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    if (c.pc) launch_steps<A, UNT, true>(c, k, par, kpos, s, e0, e1);
+    else launch_steps<A, UNT, false>(c, k, par, kpos, s, e0, e1);
 }
 
 template <int A>
@@ -411,11 +484,11 @@ int enqueue_chunk(const ChunkArgs &c, EventPool *ev, hipStream_t s)
                                               &c.st->run[par], 1, s, nullptr, par, e0, e1, c.nslots_sp);
                 if (rc) return rc;
             } else if (c.unt == 1024) {
-                launch_steps<A, 1024>(c, k, par, kpos, s, e0, e1);
+                launch_steps_pc<A, 1024>(c, k, par, kpos, s, e0, e1);
             } else if (c.unt == 512) {
-                launch_steps<A, 512>(c, k, par, kpos, s, e0, e1);
+                launch_steps_pc<A, 512>(c, k, par, kpos, s, e0, e1);
             } else {
-                launch_steps<A, 256>(c, k, par, kpos, s, e0, e1);
+                launch_steps_pc<A, 256>(c, k, par, kpos, s, e0, e1);
             }
         }
     }
@@ -461,7 +534,10 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     double *q = (double *)(base + L.q);
     double *sa = (double *)(base + L.slots_a);
     double *sb = (double *)(base + L.slots_b);
+    double *sc = (double *)(base + L.slots_c);
+    double *dinv = (double *)(base + L.dinv);
     CgState *st = (CgState *)(base + L.state);
+    const bool pc = opts && opts->precond == MW_PRECOND_JACOBI;
     mw_cg_prof_t *prof = opts ? opts->prof : nullptr;
     const int mask = prof ? (prof->mask ? prof->mask : 0xF) : 0;
     // events recorded by graph nodes cannot be read back: timing uses direct launches
@@ -506,8 +582,15 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
                             sell ? sh.sgrid : 0);
     if (rc) return rc;
     const int gi = persistent_grid(blocks_for(n, NT));
-    hipLaunchKernelGGL((mw_cg_init_kernel<A>), dim3(gi), dim3(NT), 0, s, n, b, q, r, p, sa, sb);
-    hipLaunchKernelGGL((mw_cg_init_final_kernel<A>), dim3(1), dim3(FIN_NT), 0, s, gi, sa, sb, st);
+    if (pc) {
+        hipLaunchKernelGGL(mw_cg_dinv_kernel, dim3(blocks_for(n, NT)), dim3(NT), 0, s, n, M->row_ptr, M->col_idx,
+                           M->val, dinv);
+        hipLaunchKernelGGL((mw_cg_init_kernel<A, true>), dim3(gi), dim3(NT), 0, s, n, b, q, r, p, sa, sb, dinv, sc);
+        hipLaunchKernelGGL((mw_cg_init_final_kernel<A, true>), dim3(1), dim3(FIN_NT), 0, s, gi, sa, sb, sc, st);
+    } else {
+        hipLaunchKernelGGL((mw_cg_init_kernel<A, false>), dim3(gi), dim3(NT), 0, s, n, b, q, r, p, sa, sb, dinv, sc);
+        hipLaunchKernelGGL((mw_cg_init_final_kernel<A, false>), dim3(1), dim3(FIN_NT), 0, s, gi, sa, sb, sc, st);
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(fl, &st->run[0], sizeof(Flags), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -516,6 +599,9 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     c.arith = A;
     c.n = n;
     c.chunk = chunk;
+    c.pc = pc;
+    c.dinv = dinv;
+    c.slots_c = sc;
     c.pstride = (long)(L.plane / sizeof(double));
     c.timed_mask = mask;
     c.M = M;
@@ -619,6 +705,7 @@ int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, dou
         return MW_EINVAL;
     if (opts && opts->plan && (opts->plan->n != A->n || opts->plan->csr.row_ptr != A->row_ptr)) return MW_EINVAL;
     if (opts && (!shape_valid(opts->shape) || opts->normalize < 0)) return MW_EINVAL;
+    if (opts && opts->precond != MW_PRECOND_NONE && opts->precond != MW_PRECOND_JACOBI) return MW_EINVAL;
     MW_DISPATCH(a, cg_a, A, b, x, tol, maxit, opts, workspace, info, (hipStream_t)stream);
 }
 

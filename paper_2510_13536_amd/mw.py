@@ -82,7 +82,10 @@ class Shape(C.Structure):
 class CgOpts(C.Structure):
     _fields_ = [("normalize", C.c_int32), ("chunk", C.c_int32), ("history", _vp),
                 ("prof", C.POINTER(CgProf)), ("plan", C.POINTER(SpmvPlan)), ("no_graph", C.c_int32),
-                ("reserved", C.c_int32), ("shape", C.POINTER(Shape))]
+                ("precond", C.c_int32), ("shape", C.POINTER(Shape))]
+
+
+PRECOND = {None: 0, "jacobi": 1}
 
 
 class MWError(RuntimeError):
@@ -314,13 +317,17 @@ def cg_workspace(arith, A, device=None):
 
 
 def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0, history=False,
-             workspace=None, prof=None, plan=None, graph=True, shape=None):
+             workspace=None, prof=None, plan=None, graph=True, shape=None, precond=None):
     """Solve A x = b by CG in `arith`.  Returns (x (k, n) tensor, info dict).
 
     prof: a CgProf to accumulate per-kernel device times into (optional);
     plan: a Plan of A to reuse (optional; else one is built per call);
     graph: replay captured chunks (True) or launch kernels directly;
-    shape: launch shape (Shape or dict of its fields; optional)."""
+    shape: launch shape (Shape or dict of its fields; optional);
+    precond: None (Alg. 1) or "jacobi" (preconditioned CG, M^-1 the FP64
+    reciprocal diagonal)."""
+    if precond not in PRECOND:
+        raise MWError("precond must be None or 'jacobi'")
     k = WORDS[arith]
     b = b.reshape(-1)
     if not (b.is_cuda and b.dtype == torch.float64 and b.is_contiguous() and b.numel() == A.n):
@@ -336,7 +343,7 @@ def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0
     sh = Shape.of(shape)
     opts = CgOpts(int(normalize), int(chunk), hist.data_ptr() if hist is not None else None,
                   C.pointer(prof) if prof is not None else None,
-                  C.pointer(plan.c) if plan is not None else None, 0 if graph else 1, 0,
+                  C.pointer(plan.c) if plan is not None else None, 0 if graph else 1, PRECOND[precond],
                   C.pointer(sh) if sh is not None else None)
     info = CgInfo()
     csr = A.c()

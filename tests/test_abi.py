@@ -107,13 +107,16 @@ def test_invalid_shapes_and_tuner_arguments_rejected_without_gpu(lib):
 
     class Opts(C.Structure):
         _fields_ = [("normalize", C.c_int32), ("chunk", C.c_int32), ("history", vp), ("prof", vp),
-                    ("plan", vp), ("no_graph", C.c_int32), ("reserved", C.c_int32), ("shape", C.POINTER(Shape))]
+                    ("plan", vp), ("no_graph", C.c_int32), ("precond", C.c_int32), ("shape", C.POINTER(Shape))]
 
     bogus = vp(0x1000)
     A = Csr(64, 64, bogus, bogus, bogus)
     lib.mw_cg_solve.argtypes = [C.c_int, C.POINTER(Csr), vp, vp, C.c_double, C.c_int32, C.POINTER(Opts), vp, vp, vp]
     for bad in (Shape(4, 0, 0, 0, 0.0), Shape(0, 4096, 0, 0, 0.0), Shape(0, 0, 300, 0, 0.0), Shape(0, 0, 0, 5000, 0.0)):
         o = Opts(1, 0, None, None, None, 0, 0, C.pointer(bad))
+        assert lib.mw_cg_solve(4, C.byref(A), bogus, bogus, 1e-12, 10, C.byref(o), bogus, None, None) == -1
+    for bad_pc in (2, -1):   # preconditioners: 0 (none) and 1 (Jacobi) only
+        o = Opts(1, 0, None, None, None, 0, bad_pc, None)
         assert lib.mw_cg_solve(4, C.byref(A), bogus, bogus, 1e-12, 10, C.byref(o), bogus, None, None) == -1
     lib.mw_cg_tune.argtypes = [C.c_int, C.POINTER(Csr), vp, vp, C.c_int32, vp, C.POINTER(Shape), vp]
     best = Shape()

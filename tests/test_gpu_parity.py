@@ -242,10 +242,10 @@ def test_dot_empty(mw):
 
 # ----------------------------------------------------------------------- CG
 
-def cg_parity(mw, arith, A, b, tol, maxit=None):
-    xo, io = O.cg_solve(arith, A, b, tol=tol, maxit=maxit)
+def cg_parity(mw, arith, A, b, tol, maxit=None, precond=None):
+    xo, io = O.cg_solve(arith, A, b, tol=tol, maxit=maxit, precond=precond)
     Ad = mw.DeviceCSR.from_host(A)
-    xg, ig = mw.cg_solve(arith, Ad, dev(b), tol=tol, maxit=maxit)
+    xg, ig = mw.cg_solve(arith, Ad, dev(b), tol=tol, maxit=maxit, precond=precond)
     xg = host(xg)
     assert ig["status"] == io["status"], (ig, io)
     assert abs(ig["iters"] - io["iters"]) <= max(1, int(0.02 * io["iters"])), (ig["iters"], io["iters"])
@@ -356,6 +356,61 @@ def test_cg_x_after_each_stop_position(mw, arith):
         assert io["status"] == ig["status"] == "breakdown", (seed, io, ig)
         assert io["iters"] == ig["iters"] == iters, (seed, io, ig)
         assert _x_close(arith, host(xg), np.asarray(xo).reshape(-1, M.n)) < X_BOUND[arith], seed
+
+
+# ------------------------------------- Jacobi-preconditioned CG (extension)
+
+def _shifted_laplacian(seed=12):
+    """2D Laplacian with a random diagonal shift: a non-constant diagonal."""
+    A = P.poisson2d(30, 27).to_scipy().tolil()
+    rng = np.random.default_rng(seed)
+    for i in range(A.shape[0]):
+        A[i, i] = A[i, i] + rng.uniform(0.0, 3.0)
+    A = P.CSR.from_scipy(A.tocsr())
+    return A, A.matvec(rng.uniform(-1, 1, A.n))
+
+
+PCG_CASES = {
+    "banded_scaled": lambda: P.case_banded_illcond(n=2048)[:2],
+    "poisson3d_16": lambda: P.case_poisson3d(nx=16)[:2],
+    "shifted_laplacian": _shifted_laplacian,
+}
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+@pytest.mark.parametrize("case", list(PCG_CASES))
+def test_pcg_jacobi_parity(mw, arith, case):
+    A, b = PCG_CASES[case]()
+    xg, ig, io = cg_parity(mw, arith, A, b, 1e-10, maxit=3000, precond="jacobi")
+    assert ig["status"] == "ok"
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_pcg_jacobi_diagonal_four_is_cg(mw, arith):
+    """Diagonal 4: M^-1 = I/4 is exact and PCG is CG scaled by powers of two
+    throughout, so on the GPU too it reproduces the plain solve bit for bit."""
+    A, b, _ = P.case_poisson2d_64()
+    Ad = mw.DeviceCSR.from_host(A)
+    x1, i1 = mw.cg_solve(arith, Ad, dev(b), tol=1e-12)
+    x2, i2 = mw.cg_solve(arith, Ad, dev(b), tol=1e-12, precond="jacobi")
+    assert i1["iters"] == i2["iters"] and i1["rel_res"] == i2["rel_res"]
+    assert np.array_equal(host(x1).view(np.uint64), host(x2).view(np.uint64))
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_pcg_jacobi_stop_positions_and_breakdown(mw, arith):
+    A, b = _shifted_laplacian(seed=13)
+    Ad = mw.DeviceCSR.from_host(A)
+    for m in range(1, 7):
+        xo, io = O.cg_solve(arith, A, b, tol=0.0, maxit=m, precond="jacobi")
+        xg, ig = mw.cg_solve(arith, Ad, dev(b), tol=0.0, maxit=m, precond="jacobi")
+        assert ig["status"] == io["status"] == "not_converged" and ig["iters"] == io["iters"] == m
+        assert _x_close(arith, host(xg), np.asarray(xo).reshape(-1, A.n)) < X_BOUND[arith], m
+    M = P.CSR.from_scipy(sp.csr_matrix(np.array([[0.0, 1.0], [1.0, 2.0]])))
+    _, info = mw.cg_solve(arith, mw.DeviceCSR.from_host(M), dev(np.array([1.0, 1.0])), precond="jacobi")
+    assert info["status"] == "breakdown" and info["iters"] == 0
+    with pytest.raises(mw.MWError):
+        mw.cg_solve(arith, Ad, dev(b), precond="ilu")
 
 
 @pytest.mark.parametrize("arith", ARITHS)
