@@ -140,7 +140,8 @@ def bench_illcond(mw, P, torch, dev, maxit=20000):
     """Ill-conditioned banded SPD (n = 2^20, 27 nnz/row, D A D scaled):
     planned SpMV GB/s (Infinity Cache read-flushed) and a CG run of at most
     `maxit` iterations toward 1e-10 in FP64, DW and QTW (relative residual
-    reached, time per iteration)."""
+    reached, time per iteration); Jacobi-preconditioned CG to 1e-10 and
+    1e-20."""
     A, b, _ = P.case_banded_illcond()
     Ad = mw.DeviceCSR.from_host(A, dev)
     bd = torch.as_tensor(b, device=dev)
@@ -173,6 +174,17 @@ def bench_illcond(mw, P, torch, dev, maxit=20000):
         out[ar] = {"spmv_GBps_planned_flushed": round(gbs, 1), "iters": info["iters"], "status": info["status"],
                    "rel_res": info["rel_res"], "seconds": round(sec, 3),
                    "per_iteration_us": round(1e6 * sec / max(info["iters"], 1), 1)}
+        # Jacobi-preconditioned CG (an extension; it removes the D A D
+        # scaling): iterations, time and the exactly formed true residual
+        for ptol in (1e-10, 1e-20):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, pinfo = mw.cg_solve(ar, Ad, bd, x=x, tol=ptol, maxit=maxit, precond="jacobi")
+            torch.cuda.synchronize()
+            out[ar]["jacobi_tol_%g" % ptol] = {"status": pinfo["status"], "iters": pinfo["iters"],
+                                               "seconds": round(time.perf_counter() - t0, 5),
+                                               "true_rel_res": true_rel_residual(mw, torch, Ad, bd, x)}
         log("ill-conditioned %s: %s" % (ar, out[ar]))
     return out
 
