@@ -34,8 +34,7 @@
  *                         DW without the closing QuickTwoSum.)
  *   Alg. 1              : the CG iteration.
  *
- * Readings where the paper is silent (each is listed with its reason in the
- * design notes of the repository):
+ * Readings where the paper is silent:
  *   - multi-operand sums inside one fl(...) are evaluated left to right;
  *   - TW: the paper uses the "fast" triple-word algorithms of Fabiano, Muller
  *     and Picot (2019) without printing them.  Here a TW operation is the

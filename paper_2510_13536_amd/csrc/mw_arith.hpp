@@ -1,11 +1,11 @@
 // mw_arith.hpp -- device-side multi-word arithmetic for gfx950.
 //
-// Values of the five arithmetics are register tuples Num<A> of K = words(A)
-// FP64 words, w[0] the leading one.  Every operation below is one IEEE
-// binary64 instruction with round-to-nearest-even (v_add_f64, v_mul_f64,
-// v_fma_f64); contraction is disabled for this file so the compiler can
-// neither fuse nor split them, and every intended fused multiply-add is an
-// explicit __builtin_fma.
+// Values of the six arithmetics (the paper's five and QTWE) are register
+// tuples Num<A> of K = words(A) FP64 words, w[0] the leading one.  Every
+// operation below is one IEEE binary64 instruction with round-to-nearest-
+// even (v_add_f64, v_mul_f64, v_fma_f64); contraction is disabled for this
+// file so the compiler can neither fuse nor split them, and every intended
+// fused multiply-add is an explicit __builtin_fma.
 //
 // Algorithms (Mukunoki & Ozaki, arXiv 2510.13536, Sec. III):
 //   TwoSum (Alg. 2), QuickTwoSum (Alg. 3), TwoProdFMA (Alg. 4);

@@ -1,12 +1,14 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Bars (see the design notes):
-  * element-wise ops and AXPY: bit-identical for all five arithmetics;
+Bars:
+  * element-wise ops and AXPY: bit-identical in every arithmetic (the
+    paper's five and QTWE);
   * SpMV: bit-identical (both sum each row sequentially in CSR order);
   * DOT: within the format's bound against the exact dot:
     |d - x^T y| <= 2^-100 (2 words) / 2^-145 (3 words) * sum |x_i y_i|;
-  * CG: same stopping criterion, iteration counts within 2 %, true
-    residual (formed exactly by the oracle) within 10x of the oracle's.
+  * CG (plain, and Jacobi-preconditioned): same stopping criterion,
+    iteration counts within 2 %, true residual (formed exactly by the
+    oracle) within 10x of the oracle's.
 """
 import zlib
 
