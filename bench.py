@@ -305,6 +305,42 @@ def bench_error_history(mw, P, torch, dev, nx=128, seed=6,
     return out
 
 
+def bench_table1(mw, P, torch, dev, iters=100):
+    """Per-iteration CG time of every arithmetic on banded stand-ins of the
+    paper's Table I matrices (same n and nonzeros per row; P.TABLE1), and
+    the ratio to FP64 -- the quantity of the paper's relative-time figure
+    (Sec. V-B), measured here on one MI355X.  `iters` iterations (tol 0),
+    after one short warm-up solve; plan built once per matrix."""
+    import numpy as np
+    out = {"iterations": iters}
+    for name, _, _ in P.TABLE1:
+        A = P.table1_standin(name)
+        Ad = mw.DeviceCSR.from_host(A, dev)
+        b = torch.as_tensor(A.matvec(np.random.default_rng(7).uniform(-1, 1, A.n)), device=dev)
+        plan = mw.Plan(Ad)
+        row = {"n": A.n, "nnz": A.nnz}
+        for ar in WORDS:
+            ws = mw.cg_workspace(ar, Ad)
+            x = torch.zeros((WORDS[ar], A.n), dtype=torch.float64, device=dev)
+            mw.cg_solve(ar, Ad, b, x=x, tol=0.0, maxit=4, workspace=ws, plan=plan)
+            best = None
+            for _ in range(2):
+                x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = mw.cg_solve(ar, Ad, b, x=x, tol=0.0, maxit=iters, workspace=ws, plan=plan)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                best = t if best is None else min(best, t)
+            row[ar] = round(1e6 * best / max(info["iters"], 1), 1)
+        row["over_fp64"] = {ar: round(row[ar] / row["fp64"], 2) for ar in WORDS if ar != "fp64"}
+        row["qtw_over_dw"] = round(row["qtw"] / row["dw"], 2)
+        out[name] = row
+        log("table I stand-in %s: %s" % (name, row))
+        del Ad, plan
+    return out
+
+
 def bench_shard(mw, P, torch, dev, parts=8, iters=200):
     """One GPU's share of the 128^3 problem split into `parts` z-slabs: the
     rows of 128^3 / parts planes plus one halo plane on each side (the
@@ -398,6 +434,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=16)
     ap.add_argument("--prof-steps", type=int, default=2, help="event-timed solves for the roofline")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape tuner (built-in shapes)")
+    ap.add_argument("--table1", action="store_true",
+                    help="also time iterations on banded stand-ins of the paper's Table I matrices")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -573,6 +611,8 @@ def main():
         extra["tolerances"] = bench_tolerances(mw, torch, Ad, bd, A.n)
         extra["error_history"] = bench_error_history(mw, P, torch, dev)
         extra["shard_8way"] = bench_shard(mw, P, torch, dev)
+    if args.table1:
+        extra["table1_standins"] = bench_table1(mw, P, torch, dev)
 
     cpu = None
     if not args.no_cpu:

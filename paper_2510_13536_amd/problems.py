@@ -118,6 +118,25 @@ def banded_spd(n, half_bw=13, seed=3, dseed=33, margin=1.0, scale=True):
     return CSR.from_scipy(A)
 
 
+# The paper's test matrices (Table I: SuiteSparse SPD matrices, not
+# available here) by name, n and number of nonzeros.  Their stand-ins are
+# banded SPD matrices (banded_spd, unscaled) of the same n and about the same
+# nonzeros per row (half bandwidth (nnz/n - 1)/2): the shape that sets the
+# cost of an iteration, for timing a fixed number of iterations.
+TABLE1 = [("Hook_1498", 1498023, 60917445), ("bone010", 986703, 47851783), ("nd24k", 72000, 28715634),
+          ("crankseg_2", 63838, 14148858), ("crankseg_1", 52804, 10614210), ("nd6k", 18000, 6897316),
+          ("consph", 83334, 6010480), ("pdb1HYS", 36417, 4344765)]
+
+
+def table1_standin(name, seed=70):
+    """Banded SPD stand-in for the Table I matrix `name` (see TABLE1)."""
+    for i, (nm, n, nnz) in enumerate(TABLE1):
+        if nm == name:
+            half_bw = max(1, int(round((nnz / n - 1.0) / 2.0)))
+            return banded_spd(n, half_bw=half_bw, seed=seed + i, scale=False)
+    raise KeyError(name)
+
+
 def circulant_laplacian(n, offsets, weights, shift=1e-3):
     """Weighted circulant-graph Laplacian plus shift*I: each offset o with
     weight w links i and (i +- o) mod n.  SPD for shift > 0."""
