@@ -80,21 +80,26 @@ def log(*a):
 
 
 def copy_ceiling(torch, dev, nbytes=1 << 30, reps=10):
-    """Device-to-device copy bandwidth: bytes read + written over the median
-    time of `reps` copies of a 1 GiB buffer (four times the Infinity Cache)."""
+    """Device copy bandwidth: bytes read + written over the median time of
+    `reps` copies of a 1 GiB buffer (four times the Infinity Cache), the
+    better of the runtime's copy (b.copy_(a)) and an elementwise kernel
+    (b = a * 1)."""
     a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
     b = torch.empty_like(a)
-    ts = []
-    for rep in range(reps + 2):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        b.copy_(a)
-        e1.record()
-        torch.cuda.synchronize()
-        if rep >= 2:
-            ts.append(e0.elapsed_time(e1))
+    best = 0.0
+    for op in (lambda: b.copy_(a), lambda: torch.mul(a, 1.0, out=b)):
+        ts = []
+        for rep in range(reps + 2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            op()
+            e1.record()
+            torch.cuda.synchronize()
+            if rep >= 2:
+                ts.append(e0.elapsed_time(e1))
+        best = max(best, 2 * nbytes / (statistics.median(ts) * 1e-3) / 1e9)
     del a, b
-    return 2 * nbytes / (statistics.median(ts) * 1e-3) / 1e9
+    return best
 
 
 def bench_batched(mw, P, torch, dev, nsys=512, tune=True):
@@ -578,28 +583,34 @@ def main():
         extra["spmv_GBps_planned_flushed"] = gbs
         extra["spmv_GBps_csr_flushed"] = gbs_csr
         log("SpMV GB/s planned: %s  csr: %s" % (gbs, gbs_csr))
-        # time to solution of every arithmetic (best of three solves, after
-        # tuning and a warm-up, with the same prebuilt plan)
-        tts = {}
+        # time to solution of every arithmetic: every arithmetic tuned and
+        # warmed up first, then three rounds that each solve once in every
+        # arithmetic (so a slow drift of the GPU's clocks over the run does
+        # not favour the arithmetics measured first), best solve of each;
+        # the same prebuilt plan throughout
+        tts, state = {}, {}
         for ar in WORDS:
-            kk = WORDS[ar]
             wsa = mw.cg_workspace(ar, Ad)
-            xa = torch.zeros((kk, A.n), dtype=torch.float64, device=dev)
+            xa = torch.zeros((WORDS[ar], A.n), dtype=torch.float64, device=dev)
             if not args.no_tune:
                 mw.cg_tune(ar, Ad, bd, iters=32, workspace=wsa)
-            mw.cg_solve(ar, Ad, bd, x=xa, tol=tol, maxit=50, workspace=wsa)
-            best = None
-            for _ in range(3):
+            mw.cg_solve(ar, Ad, bd, x=xa, tol=tol, maxit=50, workspace=wsa, plan=splan)
+            state[ar] = (wsa, xa)
+        for _ in range(3):
+            for ar in WORDS:
+                wsa, xa = state[ar]
                 xa.zero_()
                 torch.cuda.synchronize()
                 s0 = time.perf_counter()
                 _, ia = mw.cg_solve(ar, Ad, bd, x=xa, tol=tol, maxit=maxit, workspace=wsa, plan=splan)
                 torch.cuda.synchronize()
                 t_ar = time.perf_counter() - s0
-                best = t_ar if best is None else min(best, t_ar)
-            tts[ar] = {"seconds": round(best, 5), "iters": ia["iters"], "status": ia["status"],
-                       "shape": mw.cg_shape(ar, A.n, A.nnz)[1]}
+                if ar not in tts or t_ar < tts[ar]["seconds"]:
+                    tts[ar] = {"seconds": round(t_ar, 5), "iters": ia["iters"], "status": ia["status"],
+                               "shape": mw.cg_shape(ar, A.n, A.nnz)[1]}
+        for ar in WORDS:
             log("%s: %s" % (ar, tts[ar]))
+        del state
         extra["time_to_solution"] = tts
         extra["qtw_over_dw"] = round(tts["qtw"]["seconds"] / tts["dw"]["seconds"], 3)
 

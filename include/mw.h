@@ -344,8 +344,9 @@ size_t mw_cg_workspace_bytes(mw_arith_t a, int32_t n, int32_t nnz);
  * `stream`, and is complete when the call returns.  Iterations are enqueued
  * in chunks (opts->chunk, default 32, rounded up to an even number) as a
  * captured hipGraph that is reused by later calls with the same arguments
- * on the same thread; every kernel exits at once after the stop, and the
- * host checks the stop flag once per chunk.  The result is run-to-run
+ * on the same thread (up to eight captured chunks per thread, the least
+ * recently used replaced); every kernel exits at once after the stop, and
+ * the host checks the stop flag once per chunk.  The result is run-to-run
  * reproducible.
  */
 int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, double tol,

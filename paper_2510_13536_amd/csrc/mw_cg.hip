@@ -496,9 +496,11 @@ int enqueue_chunk(const ChunkArgs &c, EventPool *ev, hipStream_t s)
     return MW_OK;
 }
 
-// A captured chunk, kept per thread and reused while the arguments match.
-struct GraphCache {
+// A captured chunk, reused by later solves whose arguments (arithmetic,
+// shape, every buffer and matrix pointer) all match.
+struct GraphEntry {
     bool valid = false;
+    unsigned long long used = 0;
     ChunkArgs key{};
     mw_csr_t M{};
     mw_spmv_plan_t plan{};
@@ -511,6 +513,30 @@ struct GraphCache {
         exec = nullptr;
         graph = nullptr;
         valid = false;
+    }
+};
+
+// Up to NGRAPH captured chunks per thread (least recently used evicted),
+// so a caller alternating between a few arithmetics, matrices or
+// workspaces does not capture again on every solve.
+struct GraphCache {
+    static constexpr int NGRAPH = 8;
+    GraphEntry e[NGRAPH];
+    unsigned long long tick = 0;
+    GraphEntry *find(const ChunkArgs &c)
+    {
+        for (GraphEntry &g : e)
+            if (g.valid && same_key(g.key, c)) return &g;
+        return nullptr;
+    }
+    GraphEntry *victim()
+    {
+        GraphEntry *v = &e[0];
+        for (GraphEntry &g : e) {
+            if (!g.valid) return &g;
+            if (g.used < v->used) v = &g;
+        }
+        return v;
     }
 };
 
@@ -618,26 +644,31 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     c.nslots_sp = sell ? sh.sgrid : blocks_for(n, NT);
     c.nslots_up = sh.ugrid;
 
+    hipGraphExec_t exec = nullptr;
     if (!fl->stopped) {
         if (use_graph) {
-            GraphCache &G = graph_cache();
-            if (!(G.valid && same_key(G.key, c))) {
-                G.release();
+            GraphCache &GC = graph_cache();
+            GraphEntry *G = GC.find(c);
+            if (!G) {
+                G = GC.victim();
+                G->release();
                 HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
                 rc = enqueue_chunk<A>(c, nullptr, s);
                 hipGraph_t g = nullptr;
                 const hipError_t ce = hipStreamEndCapture(s, &g);
                 if (rc) return rc;
                 if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-                G.graph = g;
-                HIP_TRY(hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0));
-                G.key = c;
-                G.M = *M;
-                G.plan = *plan;
-                G.key.M = &G.M;
-                G.key.plan = &G.plan;
-                G.valid = true;
+                G->graph = g;
+                HIP_TRY(hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0));
+                G->key = c;
+                G->M = *M;
+                G->plan = *plan;
+                G->key.M = &G->M;
+                G->key.plan = &G->plan;
+                G->valid = true;
             }
+            G->used = ++GC.tick;
+            exec = G->exec;
         } else if (mask) {
             if ((rc = ev.init(2 * NKERN * chunk))) return rc;
         }
@@ -646,7 +677,7 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     int iters_before = 0;
     while (!fl->stopped) {
         if (use_graph) {
-            HIP_TRY(hipGraphLaunch(graph_cache().exec, s));
+            HIP_TRY(hipGraphLaunch(exec, s));
         } else {
             rc = enqueue_chunk<A>(c, mask ? &ev : nullptr, s);
             if (rc) return rc;

@@ -442,6 +442,34 @@ def test_cg_deterministic(mw, arith):
     assert np.array_equal(host(x1).view(np.uint64), host(x2).view(np.uint64))
 
 
+def test_cg_graph_cache_alternating_configurations(mw):
+    """Ten solve configurations (arithmetic x matrix x preconditioner), more
+    than the per-thread cache of captured chunks holds, cycled twice: every
+    solve equals the same solve with direct launches, bit for bit, whether
+    its graph was reused, evicted or captured again."""
+    mats = [P.case_poisson3d(nx=14)[:2], P.case_poisson2d_64()[:2]]
+    devs = [(mw.DeviceCSR.from_host(A), dev(b)) for A, b in mats]
+    configs = [(ar, m, pc) for m in range(2) for ar in ("fp64", "dw", "qtw", "tw", "qtwe") for pc in (None,)]
+    configs = configs[:8] + [("dw", 0, "jacobi"), ("qtw", 1, "jacobi")]
+    import torch
+    ref, bufs = {}, {}
+    for cfg in configs:
+        ar, m, pc = cfg
+        Ad, bd = devs[m]
+        # one workspace and one x per configuration: the graph key holds their addresses
+        bufs[cfg] = (mw.cg_workspace(ar, Ad), torch.zeros((mw.WORDS[ar], Ad.n), dtype=torch.float64, device="cuda"))
+        x, _ = mw.cg_solve(ar, Ad, bd, tol=1e-12, precond=pc, graph=False, chunk=8)
+        ref[cfg] = host(x)
+    for _ in range(2):
+        for cfg in configs:
+            ar, m, pc = cfg
+            ws, x = bufs[cfg]
+            x.zero_()
+            _, info = mw.cg_solve(ar, devs[m][0], devs[m][1], x=x, tol=1e-12, precond=pc, chunk=8, workspace=ws)
+            assert info["status"] == "ok"
+            assert np.array_equal(host(x).view(np.uint64), ref[cfg].view(np.uint64)), cfg
+
+
 def test_cg_history_and_nn(mw):
     A = P.poisson2d(24, 20)
     b = A.matvec(P.integer_vector(A.n, seed=3))
