@@ -315,16 +315,27 @@ def bench_table1(mw, P, torch, dev, iters=100):
     paper's Table I matrices (same n and nonzeros per row; P.TABLE1), and
     the ratio to FP64 -- the quantity of the paper's relative-time figure
     (Sec. V-B), measured here on one MI355X.  `iters` iterations (tol 0),
-    after one short warm-up solve; plan built once per matrix."""
+    after one short warm-up solve; the SpMV plan is the one the solver
+    builds for itself (vector rows for the matrices of at most 2^18 rows,
+    with the lanes per row of its rule; else SELL-64), built once per
+    matrix and arithmetic."""
     import numpy as np
     out = {"iterations": iters}
     for name, _, _ in P.TABLE1:
         A = P.table1_standin(name)
         Ad = mw.DeviceCSR.from_host(A, dev)
         b = torch.as_tensor(A.matvec(np.random.default_rng(7).uniform(-1, 1, A.n)), device=dev)
-        plan = mw.Plan(Ad)
-        row = {"n": A.n, "nnz": A.nnz}
+        sell = None
+        row = {"n": A.n, "nnz": A.nnz, "plan": {}}
         for ar in WORDS:
+            lanes = mw.cg_shape(ar, A.n, A.nnz)[1]["lanes"]
+            if lanes:
+                plan = mw.Plan(Ad, rows=lanes)
+                row["plan"][ar] = "rows/%d" % lanes
+            else:
+                sell = sell or mw.Plan(Ad)
+                plan = sell
+                row["plan"][ar] = plan.format
             ws = mw.cg_workspace(ar, Ad)
             x = torch.zeros((WORDS[ar], A.n), dtype=torch.float64, device=dev)
             mw.cg_solve(ar, Ad, b, x=x, tol=0.0, maxit=4, workspace=ws, plan=plan)
@@ -342,7 +353,7 @@ def bench_table1(mw, P, torch, dev, iters=100):
         row["qtw_over_dw"] = round(row["qtw"] / row["dw"], 2)
         out[name] = row
         log("table I stand-in %s: %s" % (name, row))
-        del Ad, plan
+        del Ad, plan, sell
     return out
 
 

@@ -95,7 +95,9 @@ typedef struct {
 /* Storage formats of a SpMV plan. */
 enum {
     MW_FMT_CSR = 0,     /* the caller's CSR arrays are used as given        */
-    MW_FMT_SELL64 = 1   /* sliced ELLPACK, 64-row slices (see mw_spmv_plan) */
+    MW_FMT_SELL64 = 1,  /* sliced ELLPACK, 64-row slices (see mw_spmv_plan) */
+    MW_FMT_CSRVEC = 2   /* the CSR arrays, several lanes per row
+                           (see mw_spmv_plan_rows)                          */
 };
 
 /* A SpMV plan (host struct; the arrays it points to live in the caller's
@@ -105,7 +107,9 @@ enum {
  * longest row. */
 typedef struct {
     int32_t n, nnz;
-    int32_t format;             /* MW_FMT_SELL64, or MW_FMT_CSR as fallback    */
+    int32_t format;             /* MW_FMT_SELL64 (or MW_FMT_CSR as fallback)
+                                   from mw_spmv_plan; MW_FMT_CSRVEC from
+                                   mw_spmv_plan_rows                          */
     int32_t nslices;            /* ceil(n / 64)                               */
     int64_t stored;             /* SELL64: entries stored, padding included    */
     const int32_t *slice_ptr;   /* SELL64: nslices + 1 offsets (entries)      */
@@ -119,7 +123,7 @@ typedef struct {
                                    64 s + l has an entry in that slot; 0 for
                                    every slot of an explicit-column slice     */
     int32_t ndiag;              /* SELL64: slices stored as diagonal slots    */
-    int32_t reserved;
+    int32_t lanes;              /* CSRVEC: lanes per row (2, 4, ..., 64)      */
     mw_csr_t csr;               /* the source matrix                          */
 } mw_spmv_plan_t;
 
@@ -164,6 +168,9 @@ typedef struct {
     int32_t update_threads;  /* single system: threads per update
                                 workgroup, 256, 512 or 1024                 */
     int32_t chunk;           /* iterations per captured chunk, 1 .. 4096   */
+    int32_t lanes;           /* single system: lanes per row when the solver
+                                builds a vector-row plan itself
+                                (MW_FMT_CSRVEC), 2, 4, ..., 64             */
     double us_per_iteration; /* set by the tuners: measured device time per
                                 iteration of the chosen shape              */
 } mw_shape_t;
@@ -191,8 +198,15 @@ typedef struct {
                            receives the relative residual after iteration
                            i+1.  NULL = not recorded.                      */
     mw_cg_prof_t *prof; /* optional HOST struct for per-kernel timing      */
-    const mw_spmv_plan_t *plan;  /* optional plan of A from mw_spmv_plan; NULL:
-                           the solver builds one inside its workspace      */
+    const mw_spmv_plan_t *plan;  /* optional plan of A (mw_spmv_plan or
+                           mw_spmv_plan_rows).  NULL: the solver builds one
+                           -- vector rows (MW_FMT_CSRVEC) when n <= 2^18 and
+                           rows average 32 or more entries, or when SELL64
+                           would pad too much (the CSR fallback) and rows
+                           average 16 or more; else SELL64 inside the
+                           workspace.  Its lanes per row: shape->lanes,
+                           else a tuned shape's, else about 8 entries per
+                           lane in MW_FP64 and 16 in the other arithmetics */
     int32_t no_graph;   /* nonzero: launch each kernel directly instead of
                            replaying a captured hipGraph of a chunk       */
     int32_t precond;    /* MW_PRECOND_NONE (0): Alg. 1.  MW_PRECOND_JACOBI:
@@ -292,8 +306,26 @@ size_t mw_spmv_plan_bytes(int32_t n, int32_t nnz);
  */
 int mw_spmv_plan(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *plan, void *stream);
 
-/* y = A x with a plan: the same result, bit for bit, as mw_spmv.
- * Asynchronous. */
+/*
+ * A plan for matrices with few, long rows (a set-up step, not part of the
+ * paper's method): the SpMV of a SELL64 plan gives each row one lane, so
+ * such a matrix (say 18,000 rows of ~400 entries) leaves most of the GPU
+ * idle.  This format keeps A's CSR arrays and gives each row `lanes` lanes
+ * (2, 4, ..., 64; 0 chooses about eight entries per lane for the average
+ * row): lane t adds the row's entries t, t + lanes, ... in CSR order from
+ * zero, and the lanes' sums are combined by a fixed halving tree (lane t
+ * adds lane t + d for d = lanes/2, ..., 1).  The result is deterministic but
+ * associated differently from mw_spmv's CSR order: within the format's
+ * accuracy bound (Sec. III error of a sum of len products, over a path of
+ * ceil(len / lanes) + log2(lanes) operations), not bit-identical.  No
+ * device memory; A's arrays must stay valid while the plan is used.
+ * Returns MW_EINVAL for another `lanes`.  Host only (no stream work).
+ */
+int mw_spmv_plan_rows(const mw_csr_t *A, int32_t lanes, mw_spmv_plan_t *plan);
+
+/* y = A x with a plan: for MW_FMT_SELL64 and MW_FMT_CSR plans the same
+ * result, bit for bit, as mw_spmv; for MW_FMT_CSRVEC plans the row order
+ * described at mw_spmv_plan_rows.  Asynchronous. */
 int mw_spmv_planned(mw_arith_t a, const mw_spmv_plan_t *plan, const double *x, double *y, void *stream);
 
 /*
@@ -390,8 +422,10 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
  * Times `iters` CG iterations (tol = 0, so every candidate runs the same
  * iterations; x is scratch and overwritten, b as for mw_cg_solve, b != 0)
  * for each candidate shape -- SpMV grids 1024, 1280, 1536, 1792, 2048 x
- * update grids 512, 1024, 2048 at 256 threads, candidates that clamp to
- * the same launch counted once -- on `stream`'s device, each timed as the
+ * update grids 512, 1024, 2048 at 256 threads, and when the solver would
+ * build a vector-row plan (see opts->plan), x its lanes per row, half and
+ * twice that; candidates that clamp to the same launch counted once -- on
+ * `stream`'s device, each timed as the
  * best of three runs after one that captures its graph.  The fastest
  * (the untuned shape unless another is more than 1 % faster) goes to *best
  * and into a per-process table keyed by (a, n, nnz): later mw_cg_solve
@@ -419,8 +453,11 @@ int mw_cg_batched_tune(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, c
  * mw_cg_solve_batched of nsys systems, whose slice grid depends on the
  * systems' slice count, reported here as 0 when not tuned): a tuned shape,
  * else the environment overrides, else the built-in one, with grids
- * clamped to what the matrix needs.  us_per_iteration: the tuned value, 0
- * if not tuned.  Returns 1 if a tuned shape applies, 0 if not, or
+ * clamped to what the matrix needs.  lanes: the lanes per row when a solve
+ * would build a vector-row plan by the matrix's size (see opts->plan), else
+ * 0 and the grid of SELL64 (a matrix that a solve gives vector rows for
+ * its irregular rows is not seen from n and nnz).  us_per_iteration: the
+ * tuned value, 0 if not tuned.  Returns 1 if a tuned shape applies, 0 if not, or
  * MW_EINVAL.
  */
 int mw_cg_shape(mw_arith_t a, int32_t n, int32_t nnz, int32_t nsys, mw_shape_t *shape);

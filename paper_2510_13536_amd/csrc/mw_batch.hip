@@ -708,7 +708,7 @@ int mw_cg_batched_tune(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, c
     mw_shape_t win{};
     int last = -1;
     for (int g : grids) {
-        mw_shape_t cand{g, 0, 0, iters, 0.0};
+        mw_shape_t cand{g, 0, 0, iters, 0, 0.0};
         mw_cg_opts_t o{};
         o.normalize = 1;
         o.shape = &cand;

@@ -20,6 +20,14 @@
 //                        entries (col -1) are skipped, not added as zeros.
 // Both sum every row sequentially from zero in CSR order, so both are
 // bit-identical to that definition, whatever the launch shape.
+//   mw_vec_spmv_kernel   the vector-row plan (MW_FMT_CSRVEC), for matrices
+//                        with few, long rows: L lanes per row, lane t adds
+//                        the row's entries t, t + L, t + 2L, ... in order
+//                        from zero, then the L partial sums are combined by
+//                        a fixed halving tree.  Deterministic; the row's
+//                        sum is associated differently from CSR order
+//                        (longest accumulation path ceil(len / L) + log2 L
+//                        operations instead of len).
 #include "mw_blas.hpp"
 
 #include <cstdlib>
@@ -261,6 +269,57 @@ __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const i
     }
 }
 
+// Vector-row SpMV (plan format MW_FMT_CSRVEC): L lanes per row, 64 / L
+// rows per wavefront, NWAVE * 64 / L rows per tile of the persistent walk.
+// MODE 1 (CG): x is p in the gather layout; the row group's first lane
+// forms p_i q_i, and the workgroup sum of those goes to slots[blockIdx.x].
+template <int A, int MODE, int L>
+__global__ void __launch_bounds__(NT) mw_vec_spmv_kernel(int n, const int32_t *__restrict__ row_ptr,
+                                                         const int32_t *__restrict__ col,
+                                                         const double *__restrict__ val,
+                                                         const double *__restrict__ x, double *__restrict__ y,
+                                                         double *__restrict__ slots, const int32_t *__restrict__ run_prev,
+                                                         int32_t *__restrict__ run_cur, int rev)
+{
+    constexpr int K = words(A);
+    constexpr int RPW = 64 / L;          // rows per wavefront
+    constexpr int RPT = NWAVE * RPW;     // rows per tile
+    if constexpr (MODE == 1) {
+        if (!*run_prev) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) *run_cur = 0;
+            return;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int t = lane % L;
+    const TileWalk tw = xcd_walk((n + RPT - 1) / RPT, rev);
+    Num<A> part = zero<A>();
+    for (int m = 0; m < tw.count; ++m) {
+        const long row = (long)tw[m] * RPT + wave * RPW + lane / L;
+        Num<A> acc = zero<A>();
+        if (row < n) {
+            const int re = row_ptr[row + 1];
+            for (int j = row_ptr[row] + t; j < re; j += L)
+                acc = row_step<A>(acc, val[j], load_v<A, MODE>(x, n, col[j]));
+        }
+        // fixed halving tree inside the row's group of L lanes (the whole
+        // wavefront takes part in every shuffle)
+#pragma unroll
+        for (int d = L / 2; d > 0; d >>= 1) {
+            const Num<A> o = shfl_down<A>(acc, d);
+            if (t < d) acc = add<A>(acc, o);
+        }
+        if (t == 0 && row < n) {
+            store<A>(y, n, row, acc);
+            if constexpr (MODE == 1) part = dot_step<A>(part, load_v<A, MODE>(x, n, row), acc);
+        }
+    }
+    if constexpr (MODE == 1) {
+        const Num<A> sum = block_sum<A, NT>(part);
+        if (threadIdx.x == 0) store_scalar<A>(slots + (long)blockIdx.x * K, sum);
+    }
+}
+
 // ------------------------------------------------- gradient on a pattern
 //
 // grad_val[k] = -(lam_i * x_j) for the k-th stored entry (i, j): the
@@ -395,6 +454,74 @@ int launch_sell_scan(int ns, const int32_t *width, int32_t *slice_ptr, long long
     return MW_OK;
 }
 
+template <int A, int L>
+void rc_launch_vec(const mw_csr_t *M, const double *x, double *y, double *slots, const int32_t *run_prev,
+                   int32_t *run_cur, int mode, hipStream_t s, int rev, hipEvent_t ev0, hipEvent_t ev1, int g)
+{
+    if (mode == 0)
+        MW_LAUNCH((mw_vec_spmv_kernel<A, 0, L>), dim3(g), dim3(NT), s, ev0, ev1, M->n, M->row_ptr, M->col_idx,
+                  M->val, x, y, slots, run_prev, run_cur, rev);
+    else
+        MW_LAUNCH((mw_vec_spmv_kernel<A, 1, L>), dim3(g), dim3(NT), s, ev0, ev1, M->n, M->row_ptr, M->col_idx,
+                  M->val, x, y, slots, run_prev, run_cur, rev);
+}
+
+int spmv_tiles(const mw_spmv_plan_t *plan)
+{
+    if (plan->format == MW_FMT_CSRVEC) {
+        const long rpt = (long)NWAVE * (64 / plan->lanes);
+        return (int)((plan->n + rpt - 1) / rpt);
+    }
+    return blocks_for(plan->nslices, NWAVE);
+}
+
+int plan_rows(const mw_csr_t *A, int lanes, mw_spmv_plan_t *plan)
+{
+    if (lanes == 0) {
+        // about eight entries per lane for the average row
+        const double avg = A->n > 0 ? (double)A->nnz / A->n : 0.0;
+        lanes = 2;
+        while (lanes < 64 && lanes * 8 < avg) lanes *= 2;
+    }
+    if (lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64) return MW_EINVAL;
+    memset(plan, 0, sizeof(*plan));
+    plan->n = A->n;
+    plan->nnz = A->nnz;
+    plan->format = MW_FMT_CSRVEC;
+    plan->nslices = (A->n + 63) / 64;
+    plan->lanes = lanes;
+    plan->csr = *A;
+    return MW_OK;
+}
+
+// Measured on MI355X (SpMV alone, SELL-64 against vector rows of 2 .. 64
+// lanes): SELL-64 is faster for n >= 1M whatever the row length (16K or
+// more slices fill the GPU), vector rows for n <= 83K with 73 .. 400
+// entries per row (2 .. 7x) and for irregular rows whose SELL padding
+// forces the CSR fallback (6 .. 20x at 25 .. 280 entries per row).  The
+// best lanes per row: about 8 entries per lane in FP64, 16 in the
+// multi-word arithmetics (within 15 % of the best of 2 .. 64).
+bool rows_by_size(int n, int nnz) { return n <= (1 << 18) && (long)nnz >= 32L * n; }
+
+int rows_lanes(int a, int n, int nnz, int lanes)
+{
+    if (lanes > 0) return lanes;
+    const double avg = n > 0 ? (double)nnz / n : 0.0;
+    const int per = words(a) == 1 ? 8 : 16;
+    int L = 2;
+    while (L < 64 && L * per < avg) L *= 2;
+    return L;
+}
+
+int plan_auto(int a, const mw_csr_t *A, int lanes, void *buffer, size_t bytes, mw_spmv_plan_t *plan, hipStream_t s)
+{
+    if (rows_by_size(A->n, A->nnz)) return plan_rows(A, rows_lanes(a, A->n, A->nnz, lanes), plan);
+    const int rc = plan_build(A, buffer, bytes, plan, s);
+    if (rc == MW_OK && plan->format == MW_FMT_CSR && (long)A->nnz >= 16L * A->n)
+        return plan_rows(A, rows_lanes(a, A->n, A->nnz, lanes), plan);
+    return rc;
+}
+
 int spmv_max_slots(int32_t n)
 {
     const int csr = blocks_for(n, NT);
@@ -406,9 +533,20 @@ int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, 
                 const int32_t *run_prev, int32_t *run_cur, int mode, hipStream_t s, int *nslots, int rev,
                 hipEvent_t ev0, hipEvent_t ev1, int grid)
 {
-    if (plan && plan->format == MW_FMT_SELL64) {
+    if (plan && plan->format == MW_FMT_CSRVEC) {
+        const int g = grid > 0 ? grid : cg_shape(A, M->n, M->nnz, spmv_tiles(plan), nullptr, 0).sgrid;
+        switch (plan->lanes) {
+        case 2: rc_launch_vec<A, 2>(M, x, y, slots, run_prev, run_cur, mode, s, rev, ev0, ev1, g); break;
+        case 4: rc_launch_vec<A, 4>(M, x, y, slots, run_prev, run_cur, mode, s, rev, ev0, ev1, g); break;
+        case 8: rc_launch_vec<A, 8>(M, x, y, slots, run_prev, run_cur, mode, s, rev, ev0, ev1, g); break;
+        case 16: rc_launch_vec<A, 16>(M, x, y, slots, run_prev, run_cur, mode, s, rev, ev0, ev1, g); break;
+        case 32: rc_launch_vec<A, 32>(M, x, y, slots, run_prev, run_cur, mode, s, rev, ev0, ev1, g); break;
+        default: rc_launch_vec<A, 64>(M, x, y, slots, run_prev, run_cur, mode, s, rev, ev0, ev1, g); break;
+        }
+        if (nslots) *nslots = g;
+    } else if (plan && plan->format == MW_FMT_SELL64) {
         const int ns = plan->nslices;
-        const int g = grid > 0 ? grid : cg_shape(A, M->n, M->nnz, ns, nullptr, 0).sgrid;
+        const int g = grid > 0 ? grid : cg_shape(A, M->n, M->nnz, spmv_tiles(plan), nullptr, 0).sgrid;
         if (mode == 0)
             MW_LAUNCH((mw_sell_spmv_kernel<A, 0>), dim3(g), dim3(NT), s, ev0, ev1, M->n, ns, plan->slice_ptr,
                       plan->col, plan->slot_off, plan->slot_mask, plan->val, x, y, slots, run_prev, run_cur, rev);
@@ -647,9 +785,18 @@ int mw_spmv_plan(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *
     return mwh::plan_build(A, buffer, bytes, plan, (hipStream_t)stream);
 }
 
+int mw_spmv_plan_rows(const mw_csr_t *A, int32_t lanes, mw_spmv_plan_t *plan)
+{
+    if (!valid_csr(A) || !plan) return MW_EINVAL;
+    return mwh::plan_rows(A, lanes, plan);
+}
+
 int mw_spmv_planned(mw_arith_t a, const mw_spmv_plan_t *plan, const double *x, double *y, void *stream)
 {
     if (!valid_arith(a) || !plan || !valid_csr(&plan->csr) || !x || !y || x == y) return MW_EINVAL;
+    const int L = plan->lanes;
+    if (plan->format == MW_FMT_CSRVEC && !(L == 2 || L == 4 || L == 8 || L == 16 || L == 32 || L == 64))
+        return MW_EINVAL;
     if (plan->format == MW_FMT_SELL64 && (!plan->slice_ptr || !plan->col || !plan->val)) return MW_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     MW_DISPATCH(a, spmv_planned_a, plan, x, y, s);

@@ -235,6 +235,24 @@ int plan_build(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *pl
 // Most reduction slots any CG-mode SpMV launch writes for n rows.
 int spmv_max_slots(int32_t n);
 
+// Vector-row plans (MW_FMT_CSRVEC): fill `plan` with `lanes` lanes per row
+// (0: about eight entries per lane for the average row).
+int plan_rows(const mw_csr_t *A, int lanes, mw_spmv_plan_t *plan);
+// Whether a solve in arithmetic a takes vector rows for A on its row
+// count and length alone (too few 64-row slices to fill the GPU), and the
+// lanes per row it then takes (`lanes` > 0: that many).
+bool rows_by_size(int n, int nnz);
+int rows_lanes(int a, int n, int nnz, int lanes);
+// The plan a solve builds for itself: vector rows when rows_by_size, or
+// when SELL-64 would pad too much (irregular rows, the CSR fallback) and
+// rows average 16 entries or more; else SELL-64 (or the CSR fallback) in
+// `buffer`.  Synchronises s unless vector rows are chosen by size.
+int plan_auto(int a, const mw_csr_t *A, int lanes, void *buffer, size_t bytes, mw_spmv_plan_t *plan,
+              hipStream_t s);
+// Workgroup tiles of a plan's SpMV (SELL-64: four slices; vector rows:
+// 4 * 64 / lanes rows); a persistent grid larger than this idles.
+int spmv_tiles(const mw_spmv_plan_t *plan);
+
 // y = A x.  plan == nullptr or plan->format == MW_FMT_CSR: CSR kernel on M
 // (one workgroup per NT rows); else the SELL-64 kernel on `grid`
 // workgroups (0: the built-in shape, cg_shape).  mode 1 (CG): x is p, y is
@@ -252,16 +270,17 @@ int spmv_launch(const mw_csr_t *M, const mw_spmv_plan_t *plan, const double *x, 
 // MW_SGRID / MW_UGRID / MW_UNT environment overrides, then the built-in
 // shape.
 struct CgShape {
-    int sgrid;  // workgroups of the SELL SpMV
+    int sgrid;  // workgroups of the SpMV (SELL-64 or vector rows)
     int unt;    // threads per update workgroup (256, 512, 1024)
     int ugrid;  // workgroups of the update kernels
     int chunk;  // iterations per chunk (even)
+    int lanes;  // lanes per row of a vector-row plan the solver builds (0: its rule)
 };
 struct BatchShape {
     int grid;   // workgroups of the slice kernels
     int chunk;  // iterations per chunk
 };
-CgShape cg_shape(int a, int n, int nnz, int ns, const mw_shape_t *explicit_shape, int opts_chunk);
+CgShape cg_shape(int a, int n, int nnz, int tiles, const mw_shape_t *explicit_shape, int opts_chunk);
 BatchShape batch_shape(int a, int n, int nnz, int nsys, int ns, const mw_shape_t *explicit_shape, int opts_chunk);
 void tuned_put(int a, int n, int nnz, int nsys, const mw_shape_t &s);
 bool tuned_get(int a, int n, int nnz, int nsys, mw_shape_t *s);

@@ -437,7 +437,7 @@ bool same_key(const ChunkArgs &a, const ChunkArgs &b)
            a.nslots_sp == b.nslots_sp && a.nslots_up == b.nslots_up &&
            a.chunk == b.chunk && a.pstride == b.pstride && a.timed_mask == b.timed_mask && a.unt == b.unt && a.ugrid == b.ugrid && a.r == b.r && a.p == b.p && a.q == b.q &&
            a.x == b.x && a.slots_a == b.slots_a && a.slots_b == b.slots_b && a.st == b.st && a.plan && b.plan &&
-           a.plan->format == b.plan->format && a.plan->nslices == b.plan->nslices &&
+           a.plan->format == b.plan->format && a.plan->nslices == b.plan->nslices && a.plan->lanes == b.plan->lanes &&
            a.plan->slice_ptr == b.plan->slice_ptr && a.plan->col == b.plan->col && a.plan->val == b.plan->val &&
            a.plan->slot_off == b.plan->slot_off && a.plan->slot_mask == b.plan->slot_mask &&
            a.M->row_ptr == b.M->row_ptr && a.M->col_idx == b.M->col_idx && a.M->val == b.M->val &&
@@ -582,11 +582,14 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     HIP_TRY(hipStreamWaitEvent(s, e_in, 0));
     HIP_TRY(hipEventRecord(e0, s));
 
-    // SpMV plan: given by the caller or built here
+    // SpMV plan: given by the caller or chosen here (plan_auto; the lanes
+    // of vector rows from the launch shape)
+    const mw_shape_t *xshape = opts ? opts->shape : nullptr;
     mw_spmv_plan_t own_plan;
     const mw_spmv_plan_t *plan = opts ? opts->plan : nullptr;
     if (!plan) {
-        const int rc = plan_build(M, base + L.plan, L.total - L.plan, &own_plan, s);
+        const int lanes = cg_shape(A, n, M->nnz, 1, xshape, 0).lanes;
+        const int rc = plan_auto(A, M, lanes, base + L.plan, L.total - L.plan, &own_plan, s);
         if (rc) return rc;
         plan = &own_plan;
     }
@@ -599,13 +602,13 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     h.history = opts ? opts->history : nullptr;
     HIP_TRY(hipMemcpyAsync(st, &h, sizeof(CgState), hipMemcpyHostToDevice, s));
 
-    const CgShape sh = cg_shape(A, n, M->nnz, plan->nslices, opts ? opts->shape : nullptr, opts ? opts->chunk : 0);
+    const CgShape sh = cg_shape(A, n, M->nnz, spmv_tiles(plan), xshape, opts ? opts->chunk : 0);
     const int chunk = sh.chunk;
-    const bool sell = plan->format == MW_FMT_SELL64;
+    const bool sell = plan->format == MW_FMT_SELL64, vec = plan->format == MW_FMT_CSRVEC;
 
     // r0 = b - A x0, p0 = r0, rho0, ||b||
     int rc = spmv_launch<A>(M, plan, x, q, nullptr, nullptr, nullptr, 0, s, nullptr, 0, nullptr, nullptr,
-                            sell ? sh.sgrid : 0);
+                            sell || vec ? sh.sgrid : 0);
     if (rc) return rc;
     const int gi = persistent_grid(blocks_for(n, NT));
     if (pc) {
@@ -641,7 +644,7 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     c.st = st;
     c.unt = sh.unt;
     c.ugrid = sh.ugrid;
-    c.nslots_sp = sell ? sh.sgrid : blocks_for(n, NT);
+    c.nslots_sp = sell || vec ? sh.sgrid : blocks_for(n, NT);
     c.nslots_up = sh.ugrid;
 
     hipGraphExec_t exec = nullptr;
@@ -748,61 +751,70 @@ int mw_cg_tune(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, int3
     const int n = A->n;
     const CgLayout L = cg_layout(a, n, A->nnz);
     hipStream_t s = (hipStream_t)stream;
-    // one plan for every candidate
-    mw_spmv_plan_t plan;
-    int rc = plan_build(A, (char *)workspace + L.plan, L.total - L.plan, &plan, s);
+    // the plan a solve would build (plan_auto); for vector rows also half
+    // and twice its lanes per row
+    const CgShape cur = cg_shape(a, n, A->nnz, 1, nullptr, 0);
+    mw_spmv_plan_t plans[3];
+    int rc = plan_auto(a, A, cur.lanes, (char *)workspace + L.plan, L.total - L.plan, &plans[0], s);
     if (rc) return rc;
-    const int ns = plan.nslices;
+    int np = 1;
+    const int lanes0 = plans[0].format == MW_FMT_CSRVEC ? plans[0].lanes : 0;
+    for (int l : {lanes0 / 2, lanes0 * 2})
+        if (lanes0 && l >= 2 && l <= 64 && plan_rows(A, l, &plans[np]) == MW_OK) ++np;
+    const bool gridded = plans[0].format == MW_FMT_SELL64 || plans[0].format == MW_FMT_CSRVEC;
     const int sgs[] = {1024, 1280, 1536, 1792, 2048};
     const int ugs[] = {512, 1024, 2048};
-    // the shape a solve would use untuned; kept unless a candidate is more
+    // the shape a solve would use now; kept unless a candidate is more
     // than 1 % faster (candidates differ by little; noise must not decide)
-    const CgShape builtin = cg_shape(a, n, A->nnz, ns, nullptr, 0);
-    int seen[16][2];
+    const CgShape builtin = cg_shape(a, n, A->nnz, spmv_tiles(&plans[0]), nullptr, 0);
+    int seen[48][3];
     int nseen = 0;
     double best_t = 0.0, builtin_t = 0.0;
     mw_shape_t win{};
     const size_t xbytes = sizeof(double) * (size_t)mw_words(a) * (size_t)n;
-    for (int sg : sgs) {
-        for (int ug : ugs) {
-            mw_shape_t cand{sg, ug, 256, iters + (iters & 1), 0.0};
-            const CgShape eff = cg_shape(a, n, A->nnz, ns, &cand, 0);
-            const int key[2] = {plan.format == MW_FMT_SELL64 ? eff.sgrid : 0, eff.ugrid};
-            bool dup = false;
-            for (int i = 0; i < nseen; ++i) dup = dup || (seen[i][0] == key[0] && seen[i][1] == key[1]);
-            if (dup) continue;
-            seen[nseen][0] = key[0];
-            seen[nseen][1] = key[1];
-            ++nseen;
-            mw_cg_opts_t o{};
-            o.normalize = 1;
-            o.plan = &plan;
-            o.shape = &cand;
-            double t = 0.0;
-            for (int rep = 0; rep < 4; ++rep) {  // the first run captures the chunk's graph
-                HIP_TRY(hipMemsetAsync(x, 0, xbytes, s));
-                mw_cg_info_t info{};
-                rc = mw_cg_solve(a, A, b, x, 0.0, iters, &o, workspace, &info, stream);
-                if (rc < 0) return rc;
-                if (info.iters < iters) {
-                    set_error("mw_cg_tune: the iterations stopped early (b = 0 or breakdown)");
-                    return MW_EINVAL;
+    for (int ip = 0; ip < np; ++ip) {
+        const mw_spmv_plan_t &plan = plans[ip];
+        const int lanes = plan.format == MW_FMT_CSRVEC ? plan.lanes : 0;
+        const int tiles = spmv_tiles(&plan);
+        for (int sg : sgs) {
+            for (int ug : ugs) {
+                mw_shape_t cand{sg, ug, 256, iters + (iters & 1), lanes, 0.0};
+                const CgShape eff = cg_shape(a, n, A->nnz, tiles, &cand, 0);
+                const int key[3] = {gridded ? eff.sgrid : 0, eff.ugrid, lanes};
+                bool dup = false;
+                for (int i = 0; i < nseen; ++i)
+                    dup = dup || (seen[i][0] == key[0] && seen[i][1] == key[1] && seen[i][2] == key[2]);
+                if (dup) continue;
+                for (int j = 0; j < 3; ++j) seen[nseen][j] = key[j];
+                ++nseen;
+                mw_cg_opts_t o{};
+                o.normalize = 1;
+                o.plan = &plan;
+                o.shape = &cand;
+                double t = 0.0;
+                for (int rep = 0; rep < 4; ++rep) {  // the first run captures the chunk's graph
+                    HIP_TRY(hipMemsetAsync(x, 0, xbytes, s));
+                    mw_cg_info_t info{};
+                    rc = mw_cg_solve(a, A, b, x, 0.0, iters, &o, workspace, &info, stream);
+                    if (rc < 0) return rc;
+                    if (info.iters < iters) {
+                        set_error("mw_cg_tune: the iterations stopped early (b = 0 or breakdown)");
+                        return MW_EINVAL;
+                    }
+                    if (rep == 1 || (rep > 1 && info.seconds < t)) t = info.seconds;
                 }
-                if (rep == 1 || (rep > 1 && info.seconds < t)) t = info.seconds;
-            }
-            const bool is_builtin = key[0] == (plan.format == MW_FMT_SELL64 ? builtin.sgrid : 0) &&
-                                    key[1] == builtin.ugrid;
-            if (is_builtin) builtin_t = t;
-            if (best_t == 0.0 || t < best_t) {
-                best_t = t;
-                win = cand;
-                win.spmv_grid = key[0] > 0 ? key[0] : sg;
-                win.update_grid = key[1];
+                if (ip == 0 && key[0] == (gridded ? builtin.sgrid : 0) && key[1] == builtin.ugrid) builtin_t = t;
+                if (best_t == 0.0 || t < best_t) {
+                    best_t = t;
+                    win = cand;
+                    win.spmv_grid = key[0] > 0 ? key[0] : sg;
+                    win.update_grid = key[1];
+                }
             }
         }
     }
     if (builtin_t > 0.0 && best_t > builtin_t / 1.01) {
-        win = mw_shape_t{builtin.sgrid, builtin.ugrid, builtin.unt, 0, 0.0};
+        win = mw_shape_t{builtin.sgrid, builtin.ugrid, builtin.unt, 0, lanes0, 0.0};
         best_t = builtin_t;
     }
     win.us_per_iteration = 1e6 * best_t / iters;

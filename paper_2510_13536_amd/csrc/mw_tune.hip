@@ -69,7 +69,8 @@ bool shape_valid(const mw_shape_t *s)
     if (!s) return true;
     const int t = s->update_threads;
     return in_range(s->spmv_grid, 8, MAX_GRID) && in_range(s->update_grid, 8, MAX_GRID) &&
-           (t <= 0 || t == 256 || t == 512 || t == 1024) && in_range(s->chunk, 1, 4096);
+           (t <= 0 || t == 256 || t == 512 || t == 1024) && in_range(s->chunk, 1, 4096) &&
+           (s->lanes <= 0 || (s->lanes >= 2 && s->lanes <= 64 && (s->lanes & (s->lanes - 1)) == 0));
 }
 
 // The fields set in `over` replace those of `base`.
@@ -80,10 +81,11 @@ static mw_shape_t overlay(mw_shape_t base, const mw_shape_t *over)
     if (over->update_grid > 0) base.update_grid = over->update_grid;
     if (over->update_threads > 0) base.update_threads = over->update_threads;
     if (over->chunk > 0) base.chunk = over->chunk;
+    if (over->lanes > 0) base.lanes = over->lanes;
     return base;
 }
 
-CgShape cg_shape(int a, int n, int nnz, int ns, const mw_shape_t *explicit_shape, int opts_chunk)
+CgShape cg_shape(int a, int n, int nnz, int tiles, const mw_shape_t *explicit_shape, int opts_chunk)
 {
     mw_shape_t s{};
     (void)tuned_get(a, n, nnz, 0, &s);
@@ -98,7 +100,7 @@ CgShape cg_shape(int a, int n, int nnz, int ns, const mw_shape_t *explicit_shape
         const int e = env_int("MW_SGRID");
         if (e >= 8 && e <= MAX_GRID) cap = e;
     }
-    const int g = persistent_grid(blocks_for(ns, NWAVE));
+    const int g = persistent_grid(tiles);
     r.sgrid = g < cap ? g : cap;
     // vector updates: 256 threads, at most 1024 workgroups (best of the
     // swept 256/512/1024-thread, 256 .. 2048-workgroup shapes on MI355X)
@@ -120,6 +122,7 @@ CgShape cg_shape(int a, int n, int nnz, int ns, const mw_shape_t *explicit_shape
     // even (a multiple of xr(a) <= 2): the parity pattern and the
     // search-direction buffers repeat per chunk
     r.chunk += r.chunk & 1;
+    r.lanes = s.lanes;
     return r;
 }
 
@@ -146,11 +149,17 @@ int mw_cg_shape(mw_arith_t a, int32_t n, int32_t nnz, int32_t nsys, mw_shape_t *
     const bool tuned = tuned_get(a, n, nnz, nsys, &t);
     *shape = mw_shape_t{};
     if (nsys == 0) {
-        const CgShape c = cg_shape(a, n, nnz, (n + 63) / 64, nullptr, 0);
+        // the plan format by size alone (plan_auto); irregular rows are not
+        // seen from n and nnz
+        const bool vec = rows_by_size(n, nnz);
+        const int lanes = vec ? rows_lanes(a, n, nnz, cg_shape(a, n, nnz, 1, nullptr, 0).lanes) : 0;
+        const long rpt = vec ? (long)NWAVE * (64 / lanes) : 64L * NWAVE;
+        const CgShape c = cg_shape(a, n, nnz, (int)((n + rpt - 1) / rpt), nullptr, 0);
         shape->spmv_grid = c.sgrid;
         shape->update_grid = c.ugrid;
         shape->update_threads = c.unt;
         shape->chunk = c.chunk;
+        shape->lanes = lanes;
     } else {
         shape->spmv_grid = tuned ? t.spmv_grid : 0;
         shape->chunk = tuned && t.chunk > 0 ? t.chunk : 16;

@@ -54,19 +54,19 @@ class CgProf(C.Structure):
                 for i, c in enumerate(PROF_CLASSES)}
 
 
-FMT = {0: "csr", 1: "sell64"}
+FMT = {0: "csr", 1: "sell64", 2: "csrvec"}
 
 
 class SpmvPlan(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("format", C.c_int32), ("nslices", C.c_int32),
                 ("stored", C.c_int64), ("slice_ptr", _vp), ("col", _vp), ("val", _vp), ("slot_off", _vp),
-                ("slot_mask", _vp), ("ndiag", C.c_int32), ("reserved", C.c_int32), ("csr", Csr)]
+                ("slot_mask", _vp), ("ndiag", C.c_int32), ("lanes", C.c_int32), ("csr", Csr)]
 
 
 class Shape(C.Structure):
     """Launch shape (mw_shape_t); a field <= 0 is "not set"."""
     _fields_ = [("spmv_grid", C.c_int32), ("update_grid", C.c_int32), ("update_threads", C.c_int32),
-                ("chunk", C.c_int32), ("us_per_iteration", C.c_double)]
+                ("chunk", C.c_int32), ("lanes", C.c_int32), ("us_per_iteration", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -131,6 +131,7 @@ def lib():
     L.mw_spmv_plan_bytes.restype = C.c_size_t
     L.mw_spmv_plan.argtypes = [C.POINTER(Csr), _vp, C.c_size_t, C.POINTER(SpmvPlan), _vp]
     L.mw_spmv_planned.argtypes = [C.c_int, C.POINTER(SpmvPlan), _vp, _vp, _vp]
+    L.mw_spmv_plan_rows.argtypes = [C.POINTER(Csr), C.c_int32, C.POINTER(SpmvPlan)]
     L.mw_cg_workspace_bytes.argtypes = [C.c_int, C.c_int32, C.c_int32]
     L.mw_cg_workspace_bytes.restype = C.c_size_t
     L.mw_cg_solve.argtypes = [C.c_int, C.POINTER(Csr), _vp, _vp, C.c_double, C.c_int32,
@@ -263,16 +264,27 @@ def spmv(arith, A, x, y=None):
 
 
 class Plan:
-    """A SpMV plan of a DeviceCSR (SELL-64 layout, or the CSR fallback)."""
+    """A SpMV plan of a DeviceCSR: SELL-64 (or the CSR fallback), bit-identical
+    to spmv; with rows=L (0 = chosen from the average row length) the
+    vector-row format (mw_spmv_plan_rows), L lanes per row."""
 
-    def __init__(self, A):
+    def __init__(self, A, rows=None):
         self.A = A
-        nbytes = lib().mw_spmv_plan_bytes(A.n, A.nnz)
-        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=A.val.device)
         self.c = SpmvPlan()
         self._csr = A.c()
+        if rows is not None:
+            self.buffer = None
+            _check(lib().mw_spmv_plan_rows(C.byref(self._csr), int(rows), C.byref(self.c)), "mw_spmv_plan_rows")
+            return
+        nbytes = lib().mw_spmv_plan_bytes(A.n, A.nnz)
+        self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=A.val.device)
         _check(lib().mw_spmv_plan(C.byref(self._csr), _ptr(self.buffer), nbytes, C.byref(self.c), _stream()),
                "mw_spmv_plan")
+
+    @property
+    def lanes(self):
+        """Lanes per row (vector-row plans only)."""
+        return int(self.c.lanes)
 
     @property
     def format(self):
@@ -289,7 +301,8 @@ class Plan:
 
 
 def spmv_planned(arith, plan, x, y=None):
-    """y = A x with a Plan (bit-identical to spmv)."""
+    """y = A x with a Plan (bit-identical to spmv, except for vector-row
+    plans: see Plan)."""
     k = WORDS[arith]
     x = _vec(x, k, plan.A.n, name="x")
     if y is None:

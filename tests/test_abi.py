@@ -76,7 +76,7 @@ def test_invalid_arguments_rejected_without_gpu(lib):
 
 class Shape(C.Structure):
     _fields_ = [("spmv_grid", C.c_int32), ("update_grid", C.c_int32), ("update_threads", C.c_int32),
-                ("chunk", C.c_int32), ("us_per_iteration", C.c_double)]
+                ("chunk", C.c_int32), ("lanes", C.c_int32), ("us_per_iteration", C.c_double)]
 
 
 def test_builtin_launch_shapes(lib):
@@ -89,12 +89,21 @@ def test_builtin_launch_shapes(lib):
     for a in range(6):
         assert lib.mw_cg_shape(a, n, nnz, 0, C.byref(sh)) == 0
         assert sh.spmv_grid == (1536 if a == 4 else 2048)
-        assert (sh.update_grid, sh.update_threads, sh.chunk, sh.us_per_iteration) == (1024, 256, 32, 0.0)
+        assert (sh.update_grid, sh.update_threads, sh.chunk, sh.lanes, sh.us_per_iteration) == (1024, 256, 32, 0, 0.0)
     # a small matrix clamps the grids to its tiles: 4096 rows = 16 tiles of 4 slices, 16 update blocks
     assert lib.mw_cg_shape(4, 4096, 20224, 0, C.byref(sh)) == 0
     assert (sh.spmv_grid, sh.update_grid) == (16, 16)
     assert lib.mw_cg_shape(4, 4096, 20224, 3, C.byref(sh)) == 0          # batched: untuned
     assert (sh.spmv_grid, sh.chunk) == (0, 16)
+    # few, long rows (18000 rows of ~381): vector rows, about 8 entries per
+    # lane in FP64 (64 lanes, 4 rows per tile) and 16 otherwise (32 lanes, 8)
+    for a, lanes, grid in ((0, 64, 2048), (1, 32, 2048), (4, 32, 1536)):
+        assert lib.mw_cg_shape(a, 18000, 6857328, 0, C.byref(sh)) == 0
+        assert (sh.lanes, sh.spmv_grid) == (lanes, grid)
+    assert lib.mw_cg_shape(4, 2000, 80000, 0, C.byref(sh)) == 0      # 40 per row: 4 lanes, 64 rows per tile
+    assert (sh.lanes, sh.spmv_grid) == (4, 32)
+    assert lib.mw_cg_shape(4, 1 << 19, 64 << 19, 0, C.byref(sh)) == 0  # more rows: SELL-64
+    assert sh.lanes == 0
     assert lib.mw_cg_shape(7, 4096, 20224, 0, C.byref(sh)) == -1
     assert lib.mw_cg_shape(4, 0, 20224, 0, C.byref(sh)) == -1
 
@@ -112,7 +121,9 @@ def test_invalid_shapes_and_tuner_arguments_rejected_without_gpu(lib):
     bogus = vp(0x1000)
     A = Csr(64, 64, bogus, bogus, bogus)
     lib.mw_cg_solve.argtypes = [C.c_int, C.POINTER(Csr), vp, vp, C.c_double, C.c_int32, C.POINTER(Opts), vp, vp, vp]
-    for bad in (Shape(4, 0, 0, 0, 0.0), Shape(0, 4096, 0, 0, 0.0), Shape(0, 0, 300, 0, 0.0), Shape(0, 0, 0, 5000, 0.0)):
+    for bad in (Shape(4, 0, 0, 0, 0, 0.0), Shape(0, 4096, 0, 0, 0, 0.0), Shape(0, 0, 300, 0, 0, 0.0),
+                Shape(0, 0, 0, 5000, 0, 0.0), Shape(0, 0, 0, 0, 3, 0.0), Shape(0, 0, 0, 0, 128, 0.0),
+                Shape(0, 0, 0, 0, 1, 0.0)):
         o = Opts(1, 0, None, None, None, 0, 0, C.pointer(bad))
         assert lib.mw_cg_solve(4, C.byref(A), bogus, bogus, 1e-12, 10, C.byref(o), bogus, None, None) == -1
     for bad_pc in (2, -1):   # preconditioners: 0 (none) and 1 (Jacobi) only
@@ -126,3 +137,30 @@ def test_invalid_shapes_and_tuner_arguments_rejected_without_gpu(lib):
     lib.mw_cg_batched_tune.argtypes = [C.c_int, C.c_int32, vp, C.POINTER(Csr), vp, vp, C.c_int32, vp,
                                        C.POINTER(Shape), vp]
     assert lib.mw_cg_batched_tune(4, 1, None, C.byref(A), bogus, bogus, 1, bogus, C.byref(best), None) == -1
+
+
+def test_vector_row_plan_is_host_only_and_validates_lanes(lib):
+    """mw_spmv_plan_rows fills the plan on the host (no GPU needed): lanes
+    2..64 powers of two, 0 = about eight entries per lane for the average
+    row; anything else is rejected."""
+    vp = C.c_void_p
+
+    class Csr(C.Structure):
+        _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", vp), ("col_idx", vp), ("val", vp)]
+
+    class Plan(C.Structure):
+        _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("format", C.c_int32), ("nslices", C.c_int32),
+                    ("stored", C.c_int64), ("slice_ptr", vp), ("col", vp), ("val", vp), ("slot_off", vp),
+                    ("slot_mask", vp), ("ndiag", C.c_int32), ("lanes", C.c_int32), ("csr", Csr)]
+
+    lib.mw_spmv_plan_rows.argtypes = [C.POINTER(Csr), C.c_int32, C.POINTER(Plan)]
+    bogus = vp(0x1000)
+    pl = Plan()
+    for n, nnz, want in ((18000, 6897316, 64), (36417, 4344765, 16), (1000, 7000, 2), (1000, 40000, 8)):
+        A = Csr(n, nnz, bogus, bogus, bogus)
+        assert lib.mw_spmv_plan_rows(C.byref(A), 0, C.byref(pl)) == 0
+        assert (pl.format, pl.lanes, pl.n, pl.nnz, pl.nslices) == (2, want, n, nnz, (n + 63) // 64)
+    A = Csr(1000, 7000, bogus, bogus, bogus)
+    for L in (1, 3, 128, -2):
+        assert lib.mw_spmv_plan_rows(C.byref(A), L, C.byref(pl)) == -1
+    assert lib.mw_spmv_plan_rows(C.byref(A), 32, C.byref(pl)) == 0 and pl.lanes == 32

@@ -360,6 +360,86 @@ def test_cg_x_after_each_stop_position(mw, arith):
         assert _x_close(arith, host(xg), np.asarray(xo).reshape(-1, M.n)) < X_BOUND[arith], seed
 
 
+# ------------------------------------------ vector-row SpMV plans (CSRVEC)
+
+def _wide_matrix(seed=21, n=3001):
+    """Rows of 0..600 entries (empty rows, long rows, random columns), n not
+    a multiple of any rows-per-tile count."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, 600, n)
+    lens[::97] = 0
+    rows, cols = [], []
+    for i, ln in enumerate(lens):
+        c = np.unique(rng.integers(0, n, ln))
+        rows.append(np.full(c.size, i))
+        cols.append(c)
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    vals = rng.standard_normal(rows.size) * 2.0 ** rng.integers(-8, 8, rows.size)
+    return P.CSR.from_scipy(sp.csr_matrix((vals, (rows, cols)), shape=(n, n)))
+
+
+VEC_MATRICES = {
+    "wide_random": _wide_matrix,
+    "banded_150": lambda: P.banded_spd(2000, half_bw=150, seed=5, scale=False),
+    "poisson3d": lambda: P.poisson3d(17, 9, 6),
+}
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+@pytest.mark.parametrize("mat", list(VEC_MATRICES))
+@pytest.mark.parametrize("lanes", [2, 8, 64])
+def test_spmv_rows_within_bound(mw, arith, mat, lanes):
+    """Vector-row plan: each row's sum is associated differently from CSR
+    order, so it is checked against the exact row sum: |y_i - (Ax)_i| <=
+    8 (path + 2) u^k sum_j |a_ij x_j|, path = ceil(len / L) + log2 L
+    (u = 2^-53); and reproducible run to run."""
+    A = VEC_MATRICES[mat]()
+    k = O.WORDS[arith]
+    x = rand_mw(np.random.default_rng(31), k, A.n, emin=-4, emax=4)
+    Ad = mw.DeviceCSR.from_host(A)
+    plan = mw.Plan(Ad, rows=lanes)
+    assert plan.format == "csrvec" and plan.lanes == lanes
+    y1 = host(mw.spmv_planned(arith, plan, dev(x)))
+    y2 = host(mw.spmv_planned(arith, plan, dev(x)))
+    assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
+    err, sc = O.spmv_error(arith, A, x, y1)
+    lens = np.diff(A.row_ptr)
+    path = np.ceil(lens / lanes) + np.log2(lanes)
+    bound = 8 * (path + 2) * 2.0 ** (-53 * k) * sc
+    assert np.all(err <= bound), np.max(err / np.maximum(bound, 1e-300))
+    empty = lens == 0
+    assert np.all(y1[:, empty] == 0.0)
+
+
+def _normal_matrix(seed=9, n=3000, k=6, shift=0.01):
+    """B^T B + shift I, B random sparse (k entries per row on average): SPD,
+    rows of 1 to ~100 entries (about 37 on average), ~400 CG iterations."""
+    B = sp.random(n, n, density=k / n, random_state=np.random.default_rng(seed), format="csr")
+    return P.CSR.from_scipy((B.T @ B + shift * sp.eye(n)).tocsr())
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_cg_with_vector_row_plans(mw, arith):
+    """CG on a matrix with long rows: with the plan the solver picks itself
+    for such a matrix (average row length >= 32, n <= 2^18: vector rows) and
+    with explicit vector-row plans.  The row sums are associated differently
+    from the oracle's CSR order, so the iteration counts may drift a little
+    further apart in FP64 (5 %) than in the multi-word arithmetics (2 %)."""
+    A = _normal_matrix()
+    b = A.matvec(np.random.default_rng(3).uniform(-1, 1, A.n))
+    xo, io = O.cg_solve(arith, A, b, tol=1e-12)
+    nb = np.linalg.norm(b)
+    tro = O.true_residual(arith, A, b, xo) / nb
+    Ad = mw.DeviceCSR.from_host(A)
+    slack = 0.05 if arith == "fp64" else 0.02
+    for lanes in (None, 4, 32):
+        plan = None if lanes is None else mw.Plan(Ad, rows=lanes)
+        xg, ig = mw.cg_solve(arith, Ad, dev(b), tol=1e-12, plan=plan)
+        assert ig["status"] == io["status"] == "ok", (lanes, ig, io)
+        assert abs(ig["iters"] - io["iters"]) <= max(1, int(slack * io["iters"])), (lanes, ig["iters"], io["iters"])
+        assert O.true_residual(arith, A, b, host(xg)) / nb <= 10 * tro, lanes
+
+
 # ------------------------------------- Jacobi-preconditioned CG (extension)
 
 def _shifted_laplacian(seed=12):

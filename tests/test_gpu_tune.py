@@ -58,6 +58,35 @@ def test_tuned_shape_is_recorded_and_used(mw, arith):
     assert abs(i1["iters"] - i2["iters"]) <= max(1, int(0.02 * i2["iters"]))
 
 
+@pytest.mark.parametrize("arith", ["fp64", "qtw"])
+def test_tuner_sweeps_lanes_of_vector_rows(mw, arith):
+    """A matrix the solver gives vector rows (3000 rows of ~37 entries:
+    4 lanes in QTW, 8 in FP64 by the built-in rule): the tuner also tries
+    half and twice the lanes; the winner is recorded and used, and the
+    solve keeps the oracle-parity bar (5 % iterations in FP64: the rows are
+    summed in another order than the oracle's)."""
+    import scipy.sparse as sp
+    n = 3000
+    Bm = sp.random(n, n, density=6 / n, random_state=np.random.default_rng(9), format="csr")
+    A = P.CSR.from_scipy((Bm.T @ Bm + 0.01 * sp.eye(n)).tocsr())
+    b = A.matvec(np.random.default_rng(3).uniform(-1, 1, A.n))
+    Ad = mw.DeviceCSR.from_host(A)
+    bd = dev(b)
+    tuned, before = mw.cg_shape(arith, A.n, A.nnz)
+    assert not tuned and before["lanes"] == (8 if arith == "fp64" else 4)
+    best = mw.cg_tune(arith, Ad, bd, iters=16)
+    L = before["lanes"]
+    assert best["lanes"] in (L // 2, L, 2 * L) and best["us_per_iteration"] > 0
+    tuned, now = mw.cg_shape(arith, A.n, A.nnz)
+    assert tuned and now["lanes"] == best["lanes"]
+    x, info = mw.cg_solve(arith, Ad, bd, tol=1e-12)
+    xo, oinfo = O.cg_solve(arith, A, b, tol=1e-12)
+    assert info["status"] == oinfo["status"] == "ok"
+    slack = 0.05 if arith == "fp64" else 0.02
+    assert abs(info["iters"] - oinfo["iters"]) <= max(1, int(slack * oinfo["iters"]))
+    assert O.true_residual(arith, A, b, x.cpu().numpy()) <= 10 * O.true_residual(arith, A, b, xo)
+
+
 @pytest.mark.parametrize("arith", ["dw", "qtw"])
 def test_explicit_shape_keeps_parity(mw, arith):
     A, b, _ = P.case_poisson3d(nx=40)
