@@ -325,17 +325,10 @@ def bench_table1(mw, P, torch, dev, iters=100):
         A = P.table1_standin(name)
         Ad = mw.DeviceCSR.from_host(A, dev)
         b = torch.as_tensor(A.matvec(np.random.default_rng(7).uniform(-1, 1, A.n)), device=dev)
-        sell = None
         row = {"n": A.n, "nnz": A.nnz, "plan": {}}
         for ar in WORDS:
-            lanes = mw.cg_shape(ar, A.n, A.nnz)[1]["lanes"]
-            if lanes:
-                plan = mw.Plan(Ad, rows=lanes)
-                row["plan"][ar] = "rows/%d" % lanes
-            else:
-                sell = sell or mw.Plan(Ad)
-                plan = sell
-                row["plan"][ar] = plan.format
+            plan = mw.Plan(Ad, solver=ar)
+            row["plan"][ar] = "rows/%d" % plan.lanes if plan.format == "csrvec" else plan.format
             ws = mw.cg_workspace(ar, Ad)
             x = torch.zeros((WORDS[ar], A.n), dtype=torch.float64, device=dev)
             mw.cg_solve(ar, Ad, b, x=x, tol=0.0, maxit=4, workspace=ws, plan=plan)
@@ -353,7 +346,7 @@ def bench_table1(mw, P, torch, dev, iters=100):
         row["qtw_over_dw"] = round(row["qtw"] / row["dw"], 2)
         out[name] = row
         log("table I stand-in %s: %s" % (name, row))
-        del Ad, plan, sell
+        del Ad, plan
     return out
 
 

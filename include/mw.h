@@ -385,6 +385,21 @@ int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, dou
                 int32_t maxit, const mw_cg_opts_t *opts, void *workspace, mw_cg_info_t *info,
                 void *stream);
 
+/*
+ * The SpMV plan mw_cg_solve builds for itself in arithmetic a when
+ * opts->plan is NULL (a set-up step, not part of the paper's method; the
+ * rule is described at opts->plan): vector rows (MW_FMT_CSRVEC, nothing
+ * written to `buffer`), or SELL64 / its CSR fallback in `buffer`, which
+ * must then hold mw_spmv_plan_bytes(n, nnz) bytes of device memory (else
+ * MW_EINVAL; NULL with bytes = 0 is fine for vector rows).  lanes: 0 = the
+ * solver's own (a tuned shape's, else its rule), or 2, 4, ..., 64.  Passed
+ * as opts->plan it gives the solver's default results without its per-call
+ * set-up.  plan: host struct filled on success.  Synchronises `stream`
+ * unless vector rows are taken for the matrix's size.
+ */
+int mw_cg_plan(mw_arith_t a, const mw_csr_t *A, int32_t lanes, void *buffer, size_t bytes, mw_spmv_plan_t *plan,
+               void *stream);
+
 /* Bytes of device workspace mw_cg_solve_batched needs for nsys systems of
  * n rows and nnz entries in total (256-byte aligned). */
 size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int32_t nnz);
@@ -425,12 +440,17 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
  * update grids 512, 1024, 2048 at 256 threads, and when the solver would
  * build a vector-row plan (see opts->plan), x its lanes per row, half and
  * twice that; candidates that clamp to the same launch counted once -- on
- * `stream`'s device, each timed as the
- * best of three runs after one that captures its graph.  The fastest
- * (the untuned shape unless another is more than 1 % faster) goes to *best
- * and into a per-process table keyed by (a, n, nnz): later mw_cg_solve
- * calls on matrices of that size use it unless opts->shape sets a field.
- * iters: 2 .. 4096.  workspace: as mw_cg_solve.  Synchronises `stream`.
+ * `stream`'s device, each timed as the best of three runs after one that
+ * captures its graph.  The fastest (the untuned shape unless another is
+ * more than 1 % faster) goes to *best and into a per-process table keyed
+ * by (a, n, nnz): later mw_cg_solve calls on matrices of that size use it
+ * unless opts->shape sets a field.  With MW_TUNE_CACHE=<file> in the
+ * environment the table is also kept in that file, one JSON object per
+ * line keyed by the device (architecture and compute units) and the size:
+ * read at the process's first shape lookup (the current device's lines),
+ * rewritten after every tuner result (mw_cg_batched_tune's too) through a
+ * temporary file renamed over it; a file that cannot be read or written
+ * is skipped.  iters: 2 .. 4096.  workspace: as mw_cg_solve.  Synchronises `stream`.
  * Returns MW_OK or a negative error (MW_EINVAL also when b = 0 or the
  * iterations break down before iters).
  */

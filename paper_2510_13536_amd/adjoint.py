@@ -17,8 +17,9 @@ class MWCGSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, val, b, row_ptr, col_idx, arith, tol, maxit, info_out):
         A = mw.DeviceCSR(b.numel(), row_ptr, col_idx, val.detach().contiguous())
-        # one SpMV plan and workspace serve the forward and the adjoint solve
-        plan = mw.Plan(A)
+        # one SpMV plan (the solver's own choice) and workspace serve the
+        # forward and the adjoint solve
+        plan = mw.Plan(A, solver=arith)
         ws = mw.cg_workspace(arith, A)
         x, info = mw.cg_solve(arith, A, b.detach().contiguous(), tol=tol, maxit=maxit, plan=plan, workspace=ws)
         if info["status"] != "ok":

@@ -732,6 +732,15 @@ size_t mw_cg_workspace_bytes(mw_arith_t a, int32_t n, int32_t nnz)
     return cg_layout(a, n, nnz).total;
 }
 
+int mw_cg_plan(mw_arith_t a, const mw_csr_t *A, int32_t lanes, void *buffer, size_t bytes, mw_spmv_plan_t *plan,
+               void *stream)
+{
+    if (!valid_arith(a) || !valid_csr(A) || !plan) return MW_EINVAL;
+    if (lanes != 0 && !(lanes >= 2 && lanes <= 64 && (lanes & (lanes - 1)) == 0)) return MW_EINVAL;
+    const int l = lanes ? lanes : cg_shape(a, A->n, A->nnz, 1, nullptr, 0).lanes;
+    return plan_auto(a, A, l, buffer, bytes, plan, (hipStream_t)stream);
+}
+
 int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, double tol, int32_t maxit,
                 const mw_cg_opts_t *opts, void *workspace, mw_cg_info_t *info, void *stream)
 {

@@ -1,12 +1,17 @@
 // mw_tune.hip -- launch shapes of the solvers: the built-in shapes, the
-// environment overrides, the per-process table the tuners fill, and their
-// precedence (explicit > tuned > environment > built-in).  The tuners
-// themselves run the solvers and live beside them (mw_cg.hip,
-// mw_batch.hip).
+// environment overrides, the per-process table the tuners fill (and its
+// copy in a file, MW_TUNE_CACHE), and their precedence (explicit > tuned >
+// environment > built-in).  The tuners themselves run the solvers and live
+// beside them (mw_cg.hip, mw_batch.hip).
 #include "mw_blas.hpp"
 
+#include <unistd.h>
+
+#include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <mutex>
+#include <string>
 
 using namespace mwk;
 using namespace mwh;
@@ -32,13 +37,8 @@ int env_int(const char *name)
 
 bool in_range(int v, int lo, int hi) { return v <= 0 || (v >= lo && v <= hi); }
 
-}  // namespace
-
-namespace mwh {
-
-void tuned_put(int a, int n, int nnz, int nsys, const mw_shape_t &s)
+void put_locked(int a, int n, int nnz, int nsys, const mw_shape_t &s)
 {
-    std::lock_guard<std::mutex> lk(g_mu);
     for (int i = 0; i < g_used; ++i) {
         TunedEntry &e = g_tab[i];
         if (e.a == a && e.n == n && e.nnz == nnz && e.nsys == nsys) {
@@ -51,9 +51,126 @@ void tuned_put(int a, int n, int nnz, int nsys, const mw_shape_t &s)
     if (g_used < TABLE_SIZE) ++g_used;
 }
 
+// ---- the table's file (MW_TUNE_CACHE): one JSON object per line, keyed by
+// the device (architecture name / compute units) and (arith, n, nnz, nsys).
+// Read into the table at the first lookup; every tuner result rewrites the
+// file (a temporary file renamed over it), keeping the lines of other
+// devices and sizes.  A file that cannot be read or written is skipped.
+
+constexpr int DEV_LEN = 96;
+bool g_loaded = false;
+
+const char *cache_path()
+{
+    const char *p = getenv("MW_TUNE_CACHE");
+    return p && *p ? p : nullptr;
+}
+
+bool device_key(char *out)
+{
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    std::string arch(p.gcnArchName);
+    arch = arch.substr(0, arch.find(':'));
+    snprintf(out, DEV_LEN, "%s/%d", arch.c_str(), p.multiProcessorCount);
+    return true;
+}
+
+struct CacheLine {
+    char dev[DEV_LEN];
+    int a, n, nnz, nsys;
+    mw_shape_t s;
+};
+
+bool parse_line(const char *line, CacheLine *c)
+{
+    *c = CacheLine{};
+    const int got = sscanf(line,
+                           "{\"device\": \"%95[^\"]\", \"arith\": %d, \"n\": %d, \"nnz\": %d, \"nsys\": %d, "
+                           "\"spmv_grid\": %d, \"update_grid\": %d, \"update_threads\": %d, \"chunk\": %d, "
+                           "\"lanes\": %d, \"us_per_iteration\": %lf}",
+                           c->dev, &c->a, &c->n, &c->nnz, &c->nsys, &c->s.spmv_grid, &c->s.update_grid,
+                           &c->s.update_threads, &c->s.chunk, &c->s.lanes, &c->s.us_per_iteration);
+    return got == 11 && valid_arith(c->a) && c->n > 0 && c->nnz >= 0 && c->nsys >= 0 && shape_valid(&c->s);
+}
+
+void format_line(char *out, size_t len, const CacheLine &c)
+{
+    snprintf(out, len,
+             "{\"device\": \"%s\", \"arith\": %d, \"n\": %d, \"nnz\": %d, \"nsys\": %d, \"spmv_grid\": %d, "
+             "\"update_grid\": %d, \"update_threads\": %d, \"chunk\": %d, \"lanes\": %d, "
+             "\"us_per_iteration\": %.6f}\n",
+             c.dev, c.a, c.n, c.nnz, c.nsys, c.s.spmv_grid, c.s.update_grid, c.s.update_threads, c.s.chunk,
+             c.s.lanes, c.s.us_per_iteration);
+}
+
+void load_locked()
+{
+    if (g_loaded) return;
+    g_loaded = true;
+    const char *path = cache_path();
+    char dev[DEV_LEN];
+    if (!path || !device_key(dev)) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    CacheLine c;
+    while (fgets(line, sizeof(line), f))
+        if (parse_line(line, &c) && strcmp(c.dev, dev) == 0) put_locked(c.a, c.n, c.nnz, c.nsys, c.s);
+    fclose(f);
+}
+
+void save_locked(int a, int n, int nnz, int nsys, const mw_shape_t &s)
+{
+    const char *path = cache_path();
+    CacheLine me{};
+    if (!path || !device_key(me.dev)) return;
+    me.a = a;
+    me.n = n;
+    me.nnz = nnz;
+    me.nsys = nsys;
+    me.s = s;
+    std::string text;
+    char line[512];
+    if (FILE *f = fopen(path, "r")) {
+        CacheLine c;
+        while (fgets(line, sizeof(line), f))
+            if (parse_line(line, &c) && !(strcmp(c.dev, me.dev) == 0 && c.a == a && c.n == n && c.nnz == nnz &&
+                                          c.nsys == nsys)) {
+                format_line(line, sizeof(line), c);
+                text += line;
+            }
+        fclose(f);
+    }
+    format_line(line, sizeof(line), me);
+    text += line;
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size();
+    if (fclose(f) != 0 || !ok || rename(tmp.c_str(), path) != 0) remove(tmp.c_str());
+}
+
+}  // namespace
+
+namespace mwh {
+
+void tuned_put(int a, int n, int nnz, int nsys, const mw_shape_t &s)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_locked();
+    put_locked(a, n, nnz, nsys, s);
+    save_locked(a, n, nnz, nsys, s);
+}
+
 bool tuned_get(int a, int n, int nnz, int nsys, mw_shape_t *s)
 {
     std::lock_guard<std::mutex> lk(g_mu);
+    load_locked();
     for (int i = 0; i < g_used; ++i) {
         const TunedEntry &e = g_tab[i];
         if (e.a == a && e.n == n && e.nnz == nnz && e.nsys == nsys) {

@@ -132,6 +132,7 @@ def lib():
     L.mw_spmv_plan.argtypes = [C.POINTER(Csr), _vp, C.c_size_t, C.POINTER(SpmvPlan), _vp]
     L.mw_spmv_planned.argtypes = [C.c_int, C.POINTER(SpmvPlan), _vp, _vp, _vp]
     L.mw_spmv_plan_rows.argtypes = [C.POINTER(Csr), C.c_int32, C.POINTER(SpmvPlan)]
+    L.mw_cg_plan.argtypes = [C.c_int, C.POINTER(Csr), C.c_int32, _vp, C.c_size_t, C.POINTER(SpmvPlan), _vp]
     L.mw_cg_workspace_bytes.argtypes = [C.c_int, C.c_int32, C.c_int32]
     L.mw_cg_workspace_bytes.restype = C.c_size_t
     L.mw_cg_solve.argtypes = [C.c_int, C.POINTER(Csr), _vp, _vp, C.c_double, C.c_int32,
@@ -266,12 +267,23 @@ def spmv(arith, A, x, y=None):
 class Plan:
     """A SpMV plan of a DeviceCSR: SELL-64 (or the CSR fallback), bit-identical
     to spmv; with rows=L (0 = chosen from the average row length) the
-    vector-row format (mw_spmv_plan_rows), L lanes per row."""
+    vector-row format (mw_spmv_plan_rows), L lanes per row; with
+    solver=arith the plan cg_solve builds for itself in that arithmetic
+    (mw_cg_plan; rows then overrides its lanes per row)."""
 
-    def __init__(self, A, rows=None):
+    def __init__(self, A, rows=None, solver=None):
         self.A = A
         self.c = SpmvPlan()
         self._csr = A.c()
+        if solver is not None:
+            # the plan cg_solve(solver, A) builds for itself (mw_cg_plan)
+            nbytes = lib().mw_spmv_plan_bytes(A.n, A.nnz)
+            self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=A.val.device)
+            _check(lib().mw_cg_plan(ARITH[solver], C.byref(self._csr), int(rows or 0), _ptr(self.buffer), nbytes,
+                                    C.byref(self.c), _stream()), "mw_cg_plan")
+            if self.c.format == 2:
+                self.buffer = None
+            return
         if rows is not None:
             self.buffer = None
             _check(lib().mw_spmv_plan_rows(C.byref(self._csr), int(rows), C.byref(self.c)), "mw_spmv_plan_rows")
@@ -334,7 +346,8 @@ def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0
     """Solve A x = b by CG in `arith`.  Returns (x (k, n) tensor, info dict).
 
     prof: a CgProf to accumulate per-kernel device times into (optional);
-    plan: a Plan of A to reuse (optional; else one is built per call);
+    plan: a Plan of A to reuse (optional; else the solver builds its own
+    per call, as Plan(A, solver=arith) does);
     graph: replay captured chunks (True) or launch kernels directly;
     shape: launch shape (Shape or dict of its fields; optional);
     precond: None (Alg. 1) or "jacobi" (preconditioned CG, M^-1 the FP64

@@ -164,3 +164,11 @@ def test_vector_row_plan_is_host_only_and_validates_lanes(lib):
     for L in (1, 3, 128, -2):
         assert lib.mw_spmv_plan_rows(C.byref(A), L, C.byref(pl)) == -1
     assert lib.mw_spmv_plan_rows(C.byref(A), 32, C.byref(pl)) == 0 and pl.lanes == 32
+    # the solver's own plan, chosen by size alone: host-only vector rows
+    lib.mw_cg_plan.argtypes = [C.c_int, C.POINTER(Csr), C.c_int32, vp, C.c_size_t, C.POINTER(Plan), vp]
+    A = Csr(18000, 6857328, bogus, bogus, bogus)
+    for a, lanes, want in ((0, 0, 64), (4, 0, 32), (1, 0, 32), (4, 16, 16)):
+        assert lib.mw_cg_plan(a, C.byref(A), lanes, None, 0, C.byref(pl), None) == 0
+        assert (pl.format, pl.lanes) == (2, want)
+    assert lib.mw_cg_plan(4, C.byref(A), 3, None, 0, C.byref(pl), None) == -1
+    assert lib.mw_cg_plan(6, C.byref(A), 0, None, 0, C.byref(pl), None) == -1

@@ -440,6 +440,52 @@ def test_cg_with_vector_row_plans(mw, arith):
         assert O.true_residual(arith, A, b, host(xg)) / nb <= 10 * tro, lanes
 
 
+def _irregular_spd(n=20000, seed=4):
+    """Symmetric, strictly diagonally dominant, rows of 2 .. 2269 entries
+    (23.5 on average): SELL-64 would store 2.3x the entries, so a plan falls
+    back to CSR and the solver takes vector rows instead."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, 25, n)
+    rows = np.repeat(np.arange(n), lens)
+    cols = np.clip(rows + rng.integers(-3000, 3001, rows.size), 0, n - 1)
+    S = sp.csr_matrix((rng.standard_normal(rows.size), (rows, cols)), shape=(n, n))
+    M = (S + S.T).tocsr()
+    M.setdiag(0)
+    M.eliminate_zeros()
+    d = np.asarray(abs(M).sum(axis=1)).ravel() + 1.0
+    return P.CSR.from_scipy((M + sp.diags(d)).tocsr())
+
+
+@pytest.mark.parametrize("arith", ARITHS)
+def test_solver_plan_choice_and_irregular_rows(mw, arith):
+    """mw_cg_plan gives the plan the solver builds for itself: SELL-64 for a
+    Poisson matrix, vector rows by size for few long rows, vector rows for
+    irregular rows (SELL's CSR fallback).  On the irregular matrix the
+    solver's own choice keeps the parity bar, and passing that plan
+    explicitly gives the same bits."""
+    lanes_by_size = 8 if arith == "fp64" else 4      # ~37 entries per row
+    lanes_irregular = 4 if arith == "fp64" else 2    # ~23.5 entries per row
+    assert mw.Plan(mw.DeviceCSR.from_host(P.poisson3d(20)), solver=arith).format == "sell64"
+    pw = mw.Plan(mw.DeviceCSR.from_host(_normal_matrix()), solver=arith)
+    assert (pw.format, pw.lanes) == ("csrvec", lanes_by_size)
+    A = _irregular_spd()
+    Ad = mw.DeviceCSR.from_host(A)
+    assert mw.Plan(Ad).format == "csr"
+    pl = mw.Plan(Ad, solver=arith)
+    assert (pl.format, pl.lanes) == ("csrvec", lanes_irregular)
+    b = A.matvec(np.random.default_rng(3).uniform(-1, 1, A.n))
+    xo, io = O.cg_solve(arith, A, b, tol=1e-12)
+    x1, i1 = mw.cg_solve(arith, Ad, dev(b), tol=1e-12)
+    x2, i2 = mw.cg_solve(arith, Ad, dev(b), tol=1e-12, plan=pl)
+    assert i1["iters"] == i2["iters"]
+    assert np.array_equal(host(x1).view(np.uint64), host(x2).view(np.uint64))
+    assert i1["status"] == io["status"] == "ok"
+    slack = 0.05 if arith == "fp64" else 0.02
+    assert abs(i1["iters"] - io["iters"]) <= max(1, int(slack * io["iters"])), (i1["iters"], io["iters"])
+    nb = np.linalg.norm(b)
+    assert O.true_residual(arith, A, b, host(x1)) / nb <= 10 * O.true_residual(arith, A, b, xo) / nb
+
+
 # ------------------------------------- Jacobi-preconditioned CG (extension)
 
 def _shifted_laplacian(seed=12):

@@ -126,3 +126,41 @@ def test_batched_tuner_and_grid_independence(mw):
     assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
     assert np.array_equal(got[0].cpu().numpy().view(np.uint64), ref[0].cpu().numpy().view(np.uint64))
     assert got[4]["status"] == "ok"
+
+
+def test_tune_cache_file_carries_shapes_across_processes(tmp_path):
+    """MW_TUNE_CACHE: what the tuner records in one process is the tuned
+    shape of the next one (read at its first shape lookup); a line of
+    another device is kept in the file but not applied, a malformed line is
+    dropped."""
+    import json
+    import os
+    import subprocess
+    import sys
+    repo = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    A = P.poisson3d(40)
+    cache = tmp_path / "tune.jsonl"
+    other = ('{"device": "gfx000/1", "arith": 1, "n": %d, "nnz": %d, "nsys": 0, "spmv_grid": 8, "update_grid": 8, '
+             '"update_threads": 256, "chunk": 0, "lanes": 0, "us_per_iteration": 1.000000}' % (A.n, A.nnz))
+    cache.write_text(other + "\nnot a cache line\n")
+    env = dict(os.environ, MW_TUNE_CACHE=str(cache))
+    pre = ("import json, numpy as np, torch; from paper_2510_13536_amd import mw, problems as P; "
+           "A = P.poisson3d(40); ")
+    tune = pre + ("Ad = mw.DeviceCSR.from_host(A); "
+                  "b = torch.as_tensor(A.matvec(np.random.default_rng(3).uniform(-1, 1, A.n)), device='cuda'); "
+                  "print(json.dumps([mw.cg_shape('dw', A.n, A.nnz)[0], mw.cg_tune('dw', Ad, b, iters=8)]))")
+    look = pre + "print(json.dumps(mw.cg_shape('dw', A.n, A.nnz)))"
+    for code in (tune, look):
+        print("subprocess:", code[-60:], flush=True)
+        r = subprocess.run([sys.executable, "-c", code], env=env, cwd=repo, capture_output=True, text=True,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        out = json.loads(r.stdout.strip().splitlines()[-1])
+        if code is tune:
+            tuned_before, best = out
+            assert not tuned_before                       # the other device's line is not applied
+        else:
+            tuned, now = out
+    assert tuned and all(now[f] == best[f] for f in ("spmv_grid", "update_grid", "update_threads", "lanes"))
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 2 and lines[0] == other and '"arith": 1' in lines[1] and '"gfx000/1"' not in lines[1]
