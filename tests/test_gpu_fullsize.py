@@ -7,6 +7,9 @@ benchmark uses (planned SELL-64 SpMV, graph-replayed CG chunks):
   format's precision (only the dot association differs);
 * complete 128^3 solves: iterations within 2 % of the oracle's FP64 solve,
   exact true residual consistent with the recursive one;
+* the largest vector-row workload (the banded stand-in of nd24k, 72,000
+  rows of ~400 entries, with the plan the solver picks): sampled rows
+  within the bound of the reassociated row sum, all arithmetics;
 * the 512-system batch: sampled systems against oracle solves;
 * the adjoint problem at 100^3: gradients against central differences.
 """
@@ -59,6 +62,28 @@ def test_full_spmv_bit_exact(mods, request, case, arith):
     got = mw.spmv_planned(arith, plan, torch.as_tensor(x, device="cuda")).cpu().numpy()
     want = O.spmv(arith, A, x)
     assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+@pytest.fixture(scope="module")
+def nd24k():
+    return P.table1_standin("nd24k")
+
+
+@pytest.mark.parametrize("arith", ARITHS + ["qtwe"])
+def test_full_vector_row_spmv_sampled(mods, nd24k, arith):
+    torch, mw = mods
+    A = nd24k
+    k = O.WORDS[arith]
+    x = _rand_words(k, A.n, 22)
+    plan = mw.Plan(mw.DeviceCSR.from_host(A), solver=arith)
+    assert plan.format == "csrvec" and plan.lanes in (32, 64)
+    got = mw.spmv_planned(arith, plan, torch.as_tensor(x, device="cuda")).cpu().numpy()
+    rows = np.random.default_rng(5).choice(A.n, 2000, replace=False)
+    rows = np.concatenate([rows, [0, A.n - 1]])
+    err, sc = O.spmv_error(arith, A, x, got, rows=rows)
+    lens = np.diff(A.row_ptr)[rows]
+    bound = 8 * (np.ceil(lens / plan.lanes) + np.log2(plan.lanes) + 2) * 2.0 ** (-53 * k) * sc
+    assert np.all(err <= bound), np.max(err / bound)
 
 
 def _word_diff(arith, a, b):
