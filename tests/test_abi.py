@@ -55,6 +55,29 @@ def test_workspace_sizes(lib):
     assert lib.mw_cg_workspace_bytes(0, 0, 0) == 0
 
 
+def test_sizes_at_the_int32_limits(lib):
+    """n = nnz = 2^31 - 1 (the largest the int32 CSR allows): every byte
+    count is formed in 64 bits (a QTW workspace is then ~150 GB, inside one
+    GPU's 288 GB), the plan and shape helpers stay consistent."""
+    lib.mw_cg_workspace_bytes.restype = C.c_size_t
+    lib.mw_spmv_plan_bytes.restype = C.c_size_t
+    lib.mw_cg_batched_workspace_bytes.restype = C.c_size_t
+    big = 2 ** 31 - 1
+    for a, k in enumerate([1, 2, 2, 3, 3, 3]):
+        ws = lib.mw_cg_workspace_bytes(a, big, big)
+        assert ws >= 3 * k * big * 8 and ws % 256 == 0
+        assert ws > lib.mw_cg_workspace_bytes(a, big // 2, big // 2)
+        assert lib.mw_cg_batched_workspace_bytes(a, 1, big, big) >= 3 * k * big * 8
+    assert lib.mw_spmv_plan_bytes(big, big) >= 12 * big
+    class Shape(C.Structure):
+        _fields_ = [("spmv_grid", C.c_int32), ("update_grid", C.c_int32), ("update_threads", C.c_int32),
+                    ("chunk", C.c_int32), ("lanes", C.c_int32), ("us_per_iteration", C.c_double)]
+    lib.mw_cg_shape.argtypes = [C.c_int, C.c_int32, C.c_int32, C.c_int32, C.POINTER(Shape)]
+    sh = Shape()
+    assert lib.mw_cg_shape(4, big, big, 0, C.byref(sh)) == 0
+    assert (sh.spmv_grid, sh.update_grid, sh.lanes) == (1536, 1024, 0)
+
+
 def test_invalid_arguments_rejected_without_gpu(lib):
     vp = C.c_void_p
     lib.mw_elementwise.argtypes = [C.c_int, C.c_int, C.c_int32, vp, vp, vp, vp]
