@@ -206,7 +206,9 @@ typedef struct {
                            average 16 or more; else SELL64 inside the
                            workspace.  Its lanes per row: shape->lanes,
                            else a tuned shape's, else about 8 entries per
-                           lane in MW_FP64 and 16 in the other arithmetics */
+                           lane in MW_FP64 and 16 in the other arithmetics.
+                           A plan of another matrix, or whose fields do not
+                           fit its format (see mw_spmv_planned): MW_EINVAL */
     int32_t no_graph;   /* nonzero: launch each kernel directly instead of
                            replaying a captured hipGraph of a chunk       */
     int32_t precond;    /* MW_PRECOND_NONE (0): Alg. 1.  MW_PRECOND_JACOBI:
@@ -325,7 +327,9 @@ int mw_spmv_plan_rows(const mw_csr_t *A, int32_t lanes, mw_spmv_plan_t *plan);
 
 /* y = A x with a plan: for MW_FMT_SELL64 and MW_FMT_CSR plans the same
  * result, bit for bit, as mw_spmv; for MW_FMT_CSRVEC plans the row order
- * described at mw_spmv_plan_rows.  Asynchronous. */
+ * described at mw_spmv_plan_rows.  A plan whose fields do not fit its
+ * format (unknown format, SELL64 arrays missing, lanes not 2, 4, ..., 64,
+ * n not its matrix's): MW_EINVAL.  Asynchronous. */
 int mw_spmv_planned(mw_arith_t a, const mw_spmv_plan_t *plan, const double *x, double *y, void *stream);
 
 /*

@@ -513,6 +513,18 @@ int plan_rows(const mw_csr_t *A, int lanes, mw_spmv_plan_t *plan)
     return MW_OK;
 }
 
+bool plan_valid(const mw_spmv_plan_t *plan)
+{
+    if (!plan || !valid_csr(&plan->csr) || plan->n != plan->csr.n) return false;
+    const int L = plan->lanes;
+    switch (plan->format) {
+    case MW_FMT_CSR: return true;
+    case MW_FMT_SELL64: return plan->slice_ptr && plan->col && plan->val && plan->nslices == (plan->n + 63) / 64;
+    case MW_FMT_CSRVEC: return L >= 2 && L <= 64 && (L & (L - 1)) == 0;
+    default: return false;
+    }
+}
+
 // Measured on MI355X (SpMV alone, SELL-64 against vector rows of 2 .. 64
 // lanes): SELL-64 is faster for n >= 1M whatever the row length (16K or
 // more slices fill the GPU), vector rows for n <= 83K with 73 .. 400
@@ -812,11 +824,7 @@ int mw_spmv_plan_rows(const mw_csr_t *A, int32_t lanes, mw_spmv_plan_t *plan)
 
 int mw_spmv_planned(mw_arith_t a, const mw_spmv_plan_t *plan, const double *x, double *y, void *stream)
 {
-    if (!valid_arith(a) || !plan || !valid_csr(&plan->csr) || !x || !y || x == y) return MW_EINVAL;
-    const int L = plan->lanes;
-    if (plan->format == MW_FMT_CSRVEC && !(L == 2 || L == 4 || L == 8 || L == 16 || L == 32 || L == 64))
-        return MW_EINVAL;
-    if (plan->format == MW_FMT_SELL64 && (!plan->slice_ptr || !plan->col || !plan->val)) return MW_EINVAL;
+    if (!valid_arith(a) || !plan_valid(plan) || !x || !y || x == y) return MW_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     MW_DISPATCH(a, spmv_planned_a, plan, x, y, s);
 }

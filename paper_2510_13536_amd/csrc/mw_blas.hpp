@@ -235,6 +235,9 @@ int plan_build(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *pl
 // Most reduction slots any CG-mode SpMV launch writes for n rows.
 int spmv_max_slots(int32_t n);
 
+// A plan's fields are consistent with its format (for plans a caller
+// hands in: a known format, SELL arrays present, lanes a power of two).
+bool plan_valid(const mw_spmv_plan_t *plan);
 // Vector-row plans (MW_FMT_CSRVEC): fill `plan` with `lanes` lanes per row
 // (0: about eight entries per lane for the average row).
 int plan_rows(const mw_csr_t *A, int lanes, mw_spmv_plan_t *plan);

@@ -746,7 +746,8 @@ int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, dou
 {
     if (!valid_arith(a) || !valid_csr(A) || !b || !x || !workspace || !(tol >= 0.0) || maxit < 0)
         return MW_EINVAL;
-    if (opts && opts->plan && (opts->plan->n != A->n || opts->plan->csr.row_ptr != A->row_ptr)) return MW_EINVAL;
+    if (opts && opts->plan && (!plan_valid(opts->plan) || opts->plan->n != A->n || opts->plan->csr.row_ptr != A->row_ptr))
+        return MW_EINVAL;
     if (opts && (!shape_valid(opts->shape) || opts->normalize < 0)) return MW_EINVAL;
     if (opts && opts->precond != MW_PRECOND_NONE && opts->precond != MW_PRECOND_JACOBI) return MW_EINVAL;
     MW_DISPATCH(a, cg_a, A, b, x, tol, maxit, opts, workspace, info, (hipStream_t)stream);

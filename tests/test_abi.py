@@ -195,3 +195,21 @@ def test_vector_row_plan_is_host_only_and_validates_lanes(lib):
         assert (pl.format, pl.lanes) == (2, want)
     assert lib.mw_cg_plan(4, C.byref(A), 3, None, 0, C.byref(pl), None) == -1
     assert lib.mw_cg_plan(6, C.byref(A), 0, None, 0, C.byref(pl), None) == -1
+    # plans a caller fills in are checked against their format before any GPU work
+    lib.mw_spmv_planned.argtypes = [C.c_int, C.POINTER(Plan), vp, vp, vp]
+
+    class Opts(C.Structure):
+        _fields_ = [("normalize", C.c_int32), ("chunk", C.c_int32), ("history", vp), ("prof", vp),
+                    ("plan", C.POINTER(Plan)), ("no_graph", C.c_int32), ("precond", C.c_int32), ("shape", vp)]
+
+    lib.mw_cg_solve.argtypes = [C.c_int, C.POINTER(Csr), vp, vp, C.c_double, C.c_int32, C.POINTER(Opts), vp, vp, vp]
+    assert lib.mw_cg_plan(4, C.byref(A), 0, None, 0, C.byref(pl), None) == 0
+    for field, bad in (("lanes", 0), ("lanes", 3), ("lanes", 128), ("format", 7), ("n", 17999)):
+        p2 = Plan.from_buffer_copy(pl)
+        setattr(p2, field, bad)
+        assert lib.mw_spmv_planned(4, C.byref(p2), bogus, vp(0x2000), None) == -1, (field, bad)
+        o = Opts(1, 0, None, None, C.pointer(p2), 0, 0, None)
+        assert lib.mw_cg_solve(4, C.byref(A), bogus, bogus, 1e-12, 10, C.byref(o), bogus, None, None) == -1
+    p2 = Plan.from_buffer_copy(pl)
+    p2.format = 1                                   # SELL64 without its arrays
+    assert lib.mw_spmv_planned(4, C.byref(p2), bogus, vp(0x2000), None) == -1
