@@ -150,6 +150,13 @@ __global__ void __launch_bounds__(FIN_NT) mw_cg_init_final_kernel(int nslots, co
     }
 }
 
+// Tiles whose operands the update kernels load before their reduction of
+// the previous kernel's partials, so that those loads overlap it.  Measured
+// on MI355X (3D Poisson 128^3): four against two, FP64 and DW solves -2.5 %,
+// QTW -1 %; TW +0.6 % (its heavier arithmetic needs the registers), so TW
+// and QTWE, the two with the most arithmetic per element, keep two.
+__host__ __device__ constexpr int prefetch_tiles(int a) { return a == TW || a == QTWE ? 2 : 4; }
+
 // Iteration step 2 (parity par; iteration k, 0-based, with k % xr(A) = kpos):
 // every workgroup reduces the p^T q partials in the same fixed order, so all
 // derive the same sigma and alpha = rho / sigma (stored in slot kpos);
@@ -171,20 +178,20 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
         if (blockIdx.x == 0 && threadIdx.x == 0) st->run[par] = 0;
         return;
     }
-    // the first two tiles' operands are loaded before the reduction, so
-    // that their latency overlaps it (measured on MI355X: one tile hides
-    // part of the reduction's latency, two hide more; QTW solve -1 %)
+    // the first D tiles' operands are loaded before the reduction, so that
+    // their latency overlaps it (prefetch_tiles)
     const TileWalk tw = xcd_walk((n + UNT - 1) / UNT, rev);
-    const long i0 = tw.count > 0 ? (long)tw[0] * UNT + threadIdx.x : (long)n;
-    const long i1 = tw.count > 1 ? (long)tw[1] * UNT + threadIdx.x : (long)n;
-    Num<A> q0 = zero<A>(), r0 = zero<A>(), q1 = zero<A>(), r1 = zero<A>();
-    if (i0 < n) {
-        q0 = load<A>(q, n, i0);
-        r0 = load<A>(r, n, i0);
-    }
-    if (i1 < n) {
-        q1 = load<A>(q, n, i1);
-        r1 = load<A>(r, n, i1);
+    constexpr int D = prefetch_tiles(A);
+    Num<A> qpre[D], rpre[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+        qpre[u] = zero<A>();
+        rpre[u] = zero<A>();
+        const long iu = tw.count > u ? (long)tw[u] * UNT + threadIdx.x : (long)n;
+        if (iu < n) {
+            qpre[u] = load<A>(q, n, iu);
+            rpre[u] = load<A>(r, n, iu);
+        }
     }
     const Num<A> sigma = reduce_slots<A, UNT>(nslots_in, slots_in);
     if (threadIdx.x == 0) {
@@ -220,8 +227,20 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_r_kernel(int n, int nslots_in,
     for (int m = 0; m < tw.count; ++m) {
         const long i = (long)tw[m] * UNT + threadIdx.x;
         if (i >= n) continue;
-        const Num<A> qi = m == 0 ? q0 : (m == 1 ? q1 : load<A>(q, n, i));
-        const Num<A> rv = m == 0 ? r0 : (m == 1 ? r1 : load<A>(r, n, i));
+        Num<A> qi, rv;
+        if (m < D) {
+            qi = qpre[0];
+            rv = rpre[0];
+#pragma unroll
+            for (int u = 1; u < D; ++u)
+                if (m == u) {
+                    qi = qpre[u];
+                    rv = rpre[u];
+                }
+        } else {
+            qi = load<A>(q, n, i);
+            rv = load<A>(r, n, i);
+        }
         Num<A> ri = axmy_term<A>(al, qi, rv);
         if (norm) ri = normalise<A>(ri);
         store<A>(r, n, i, ri);
@@ -280,20 +299,21 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
         }
         return;
     }
-    // the first two tiles' operands are loaded before the reduction (as in
+    // the first D tiles' operands are loaded before the reduction (as in
     // step r); x of the first tile where it is due
     const bool xdue = kpos == XR - 1;
-    const long i0 = tw.count > 0 ? (long)tw[0] * UNT + threadIdx.x : (long)n;
-    const long i1 = tw.count > 1 ? (long)tw[1] * UNT + threadIdx.x : (long)n;
-    Num<A> p0 = zero<A>(), x0 = zero<A>(), r0 = zero<A>(), p1 = zero<A>(), r1 = zero<A>();
-    if (i0 < n) {
-        p0 = load_il<A>(pk, n, i0);
-        if (xdue) x0 = load<A>(x, n, i0);
-        r0 = load<A>(r, n, i0);
-    }
-    if (i1 < n) {
-        p1 = load_il<A>(pk, n, i1);
-        r1 = load<A>(r, n, i1);
+    constexpr int D = prefetch_tiles(A);
+    Num<A> ppre[D], rpre[D], x0 = zero<A>();
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+        ppre[u] = zero<A>();
+        rpre[u] = zero<A>();
+        const long iu = tw.count > u ? (long)tw[u] * UNT + threadIdx.x : (long)n;
+        if (iu < n) {
+            ppre[u] = load_il<A>(pk, n, iu);
+            if (u == 0 && xdue) x0 = load<A>(x, n, iu);
+            rpre[u] = load<A>(r, n, iu);
+        }
     }
     const Num<A> rho_new = reduce_slots<A, UNT>(nslots_in, slots_in);
     Num<A> rr_new = rho_new;
@@ -333,14 +353,26 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
     for (int m = 0; m < tw.count; ++m) {
         const long i = (long)tw[m] * UNT + threadIdx.x;
         if (i >= n) continue;
-        const Num<A> pi = m == 0 ? p0 : (m == 1 ? p1 : load_il<A>(pk, n, i));
+        Num<A> pi, rv;
+        if (m < D) {
+            pi = ppre[0];
+            rv = rpre[0];
+#pragma unroll
+            for (int u = 1; u < D; ++u)
+                if (m == u) {
+                    pi = ppre[u];
+                    rv = rpre[u];
+                }
+        } else {
+            pi = load_il<A>(pk, n, i);
+            if (!stop) rv = load<A>(r, n, i);
+        }
         if (xnow) {
             Num<A> xi = (m == 0 && xdue) ? x0 : load<A>(x, n, i);
             if (two) xi = axpy_term<A>(a0, load_il<A>(po, n, i), xi);
             store<A>(x, n, i, axpy_term<A>(ak, pi, xi));
         }
         if (!stop) {
-            const Num<A> rv = m == 0 ? r0 : (m == 1 ? r1 : load<A>(r, n, i));
             if constexpr (PC) store_il<A>(pn, n, i, axpy_term<A>(be, pi, jacobi<A>(dinv[i], rv)));
             else store_il<A>(pn, n, i, axpy_term<A>(be, pi, rv));
         }
