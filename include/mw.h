@@ -212,8 +212,8 @@ typedef struct {
     int32_t no_graph;   /* nonzero: launch each kernel directly instead of
                            replaying a captured hipGraph of a chunk       */
     int32_t precond;    /* MW_PRECOND_NONE (0): Alg. 1.  MW_PRECOND_JACOBI:
-                           Jacobi-preconditioned CG (see mw_cg_solve); the
-                           batched solver accepts 0 only                  */
+                           Jacobi-preconditioned CG (see mw_cg_solve), for
+                           the single and the batched solver              */
     const mw_shape_t *shape;  /* optional launch shape; its set fields take
                            precedence over a tuned shape (mw_cg_tune), which
                            takes precedence over the MW_SGRID / MW_UGRID /
@@ -421,9 +421,10 @@ size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int3
  * double[nsys] output, each system's last relative residual (may be NULL).
  * info (host, may be NULL): iters = the largest count, status = the worst
  * status (MW_OK < MW_NOT_CONVERGED < MW_BREAKDOWN), seconds.  opts:
- * normalize, chunk (default 16), no_graph and shape (spmv_grid, chunk) are
- * honoured; precond must be MW_PRECOND_NONE (else MW_EINVAL).  All systems advance in lockstep, five kernels per iteration
- * replayed from a captured hipGraph;
+ * normalize, chunk (default 16), no_graph, shape (spmv_grid, chunk) and
+ * precond (Jacobi per system as in mw_cg_solve, each system's d_i from its
+ * own rows) are honoured.  All systems advance in lockstep, five kernels
+ * per iteration replayed from a captured hipGraph;
  * a converged system's rows cost a flag test per 64-row slice afterwards.
  * Each system gives the same results whatever the other systems are, but
  * its dots are summed per 64-row slice, so they need not be bit-identical

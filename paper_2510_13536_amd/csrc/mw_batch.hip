@@ -23,7 +23,9 @@
 //      stopped in step 4 of this iteration)
 // Converged systems cost only a flag test per slice.  The host polls the
 // number of running systems once per chunk.  All orders are fixed, so the
-// batch is run-to-run reproducible.
+// batch is run-to-run reproducible.  Jacobi preconditioning (PC) follows
+// the single-system solver: z = D r with d_i = fl(1 / a_ii), rho = r^T z,
+// the stopping test on r^T r, p = z + beta p.
 #include "mw_blas.hpp"
 
 #include <cstdlib>
@@ -53,6 +55,7 @@ struct BatchDev {
     int32_t *alist;                // slices of the systems running at the start of
                                    // the current chunk (nullptr: every slice)
     int32_t *n_alist;              // their count
+    const double *dinv;            // PC: fl(1 / a_ii) per row
     const double *tol;             // solve parameters in device memory
     const int32_t *maxit, *normalize;
     int nsys, ns, n;
@@ -151,12 +154,13 @@ __global__ void __launch_bounds__(BNT) mw_batch_spmv_kernel(BatchDev d, const do
     }
 }
 
-// r = b - q, p = r, slice partials of r^T r and b^T b.
-template <int A>
+// r = b - q, p = r, slice partials of r^T r and b^T b.  PC: p = z = D r,
+// slots_rr takes the partials of r^T z and slots_c those of r^T r.
+template <int A, bool PC>
 __global__ void __launch_bounds__(BNT) mw_batch_init_kernel(BatchDev d, const double *__restrict__ b,
                                                             const double *__restrict__ q, double *__restrict__ r,
                                                             double *__restrict__ p, double *__restrict__ slots_rr,
-                                                            double *__restrict__ slots_bb)
+                                                            double *__restrict__ slots_bb, double *__restrict__ slots_c)
 {
     constexpr int K = words(A);
     const int lane = threadIdx.x & 63, wave = wave_id();
@@ -166,7 +170,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_init_kernel(BatchDev d, const do
         const int idx = t * NWAVE + wave;
         if (idx >= nl) continue;
         const int s = slice_at(d, idx);
-        Num<A> rr = zero<A>(), bb = zero<A>();
+        Num<A> rr = zero<A>(), bb = zero<A>(), rz = zero<A>();
         if (lane < d.slice_rows[s]) {
             const long i = (long)d.slice_row0[s] + lane;
             const Num<A> bi = promote<A>(b[i]);
@@ -174,15 +178,23 @@ __global__ void __launch_bounds__(BNT) mw_batch_init_kernel(BatchDev d, const do
             if constexpr (A == FP64) ri = promote<A>(bi.w[0] - q[i]);
             else ri = add<A>(bi, neg<A>(load<A>(q, d.n, i)));
             store<A>(r, d.n, i, ri);
-            store_il<A>(p, d.n, i, ri);
+            if constexpr (PC) {
+                const Num<A> zi = jacobi<A>(d.dinv[i], ri);
+                store_il<A>(p, d.n, i, zi);
+                rz = dot_step<A>(rz, ri, zi);
+            } else {
+                store_il<A>(p, d.n, i, ri);
+            }
             rr = dot_step<A>(rr, ri, ri);
             bb = dot_step<A>(bb, bi, bi);
         }
         rr = wave_sum<A>(rr);
         bb = wave_sum<A>(bb);
+        if constexpr (PC) rz = wave_sum<A>(rz);
         if (lane == 0) {
-            store_scalar<A>(slots_rr + (long)s * K, rr);
+            store_scalar<A>(slots_rr + (long)s * K, PC ? rz : rr);
             store_scalar<A>(slots_bb + (long)s * K, bb);
+            if constexpr (PC) store_scalar<A>(slots_c + (long)s * K, rr);
         }
     }
 }
@@ -196,20 +208,23 @@ __device__ __forceinline__ Num<A> system_sum(const BatchDev &d, int sys, const d
     return reduce_slots<A, BNT>(s1 - s0, slots + (long)s0 * K);
 }
 
-template <int A>
+template <int A, bool PC>
 __global__ void __launch_bounds__(BNT) mw_batch_init_final_kernel(BatchDev d, const double *__restrict__ slots_rr,
-                                                                  const double *__restrict__ slots_bb)
+                                                                  const double *__restrict__ slots_bb,
+                                                                  const double *__restrict__ slots_c)
 {
     constexpr int K = words(A);
     const int sys = blockIdx.x;
     const Num<A> rho = system_sum<A>(d, sys, slots_rr);
     const Num<A> bb = system_sum<A>(d, sys, slots_bb);
+    Num<A> rr = rho;
+    if constexpr (PC) rr = system_sum<A>(d, sys, slots_c);
     if (threadIdx.x == 0) {
         store_scalar<A>(d.rho + (long)sys * K, rho);
         d.nb[sys] = sqrt(to_fp64<A>(bb));
         d.iters[sys] = 0;
         d.xdue[sys] = 0;
-        const double r64 = to_fp64<A>(rho);
+        const double r64 = to_fp64<A>(rr);
         int run = 1, status = MW_OK;
         if (r64 == 0.0) {
             d.rel[sys] = 0.0;
@@ -256,9 +271,12 @@ __global__ void __launch_bounds__(BNT) mw_batch_alpha_kernel(BatchDev d, const d
     }
 }
 
-template <int A>
+// r = r - alpha q (quasi types normalise it), slice partials of r^T r
+// (PC: of r^T z to slots, of r^T r to slots_c).
+template <int A, bool PC>
 __global__ void __launch_bounds__(BNT) mw_batch_step_r_kernel(BatchDev d, const double *__restrict__ q,
-                                                              double *__restrict__ r, double *__restrict__ slots)
+                                                              double *__restrict__ r, double *__restrict__ slots,
+                                                              double *__restrict__ slots_c)
 {
     constexpr int K = words(A);
     const int lane = threadIdx.x & 63, wave = wave_id();
@@ -274,32 +292,40 @@ __global__ void __launch_bounds__(BNT) mw_batch_step_r_kernel(BatchDev d, const 
         if (!d.active[sys]) continue;
         const bool norm = is_quasi(A) && NK > 0 && (d.iters[sys] + 1) % NK == 0;
         const Num<A> al = load_scalar<A>(d.alpha + (long)sys * K);
-        Num<A> rr = zero<A>();
+        Num<A> rr = zero<A>(), rz = zero<A>();
         if (lane < d.slice_rows[s]) {
             const long i = (long)d.slice_row0[s] + lane;
             Num<A> ri = axmy_term<A>(al, load<A>(q, d.n, i), load<A>(r, d.n, i));
             if (norm) ri = normalise<A>(ri);
             store<A>(r, d.n, i, ri);
+            if constexpr (PC) rz = dot_step<A>(rz, ri, jacobi<A>(d.dinv[i], ri));
             rr = dot_step<A>(rr, ri, ri);
         }
         rr = wave_sum<A>(rr);
-        if (lane == 0) store_scalar<A>(slots + (long)s * K, rr);
+        if constexpr (PC) rz = wave_sum<A>(rz);
+        if (lane == 0) {
+            store_scalar<A>(slots + (long)s * K, PC ? rz : rr);
+            if constexpr (PC) store_scalar<A>(slots_c + (long)s * K, rr);
+        }
     }
 }
 
-// rho', the FP64 test and beta per running system.
-template <int A>
-__global__ void __launch_bounds__(BNT) mw_batch_beta_kernel(BatchDev d, const double *__restrict__ slots)
+// rho', the FP64 test (on r^T r) and beta per running system.
+template <int A, bool PC>
+__global__ void __launch_bounds__(BNT) mw_batch_beta_kernel(BatchDev d, const double *__restrict__ slots,
+                                                            const double *__restrict__ slots_c)
 {
     constexpr int K = words(A);
     const int sys = blockIdx.x;
     if (!d.active[sys]) return;
     const Num<A> rho_new = system_sum<A>(d, sys, slots);
+    Num<A> rr_new = rho_new;
+    if constexpr (PC) rr_new = system_sum<A>(d, sys, slots_c);
     if (threadIdx.x == 0) {
         const int it = d.iters[sys] + 1;
         d.iters[sys] = it;
-        const double rr = to_fp64<A>(rho_new);
-        const bool fin = isfinite(rr);
+        const double rr = to_fp64<A>(rr_new);
+        const bool fin = isfinite(rr) && (!PC || isfinite(to_fp64<A>(rho_new)));
         const double rel = fin ? sqrt(rr) / d.nb[sys] : rr;
         const bool conv = fin && rel < *d.tol;
         if (fin) d.rel[sys] = rel;
@@ -315,7 +341,8 @@ __global__ void __launch_bounds__(BNT) mw_batch_beta_kernel(BatchDev d, const do
     }
 }
 
-template <int A>
+// x = x + alpha p; p = r + beta p (PC: z + beta p, z = D r).
+template <int A, bool PC>
 __global__ void __launch_bounds__(BNT) mw_batch_step_p_kernel(BatchDev d, const double *__restrict__ r,
                                                               double *__restrict__ p, double *__restrict__ x)
 {
@@ -337,7 +364,9 @@ __global__ void __launch_bounds__(BNT) mw_batch_step_p_kernel(BatchDev d, const 
         store<A>(x, d.n, i, axpy_term<A>(al, pi, load<A>(x, d.n, i)));
         if (run) {
             const Num<A> be = load_scalar<A>(d.beta + (long)sys * K);
-            store_il<A>(p, d.n, i, axpy_term<A>(be, pi, load<A>(r, d.n, i)));
+            const Num<A> ri = load<A>(r, d.n, i);
+            if constexpr (PC) store_il<A>(p, d.n, i, axpy_term<A>(be, pi, jacobi<A>(d.dinv[i], ri)));
+            else store_il<A>(p, d.n, i, axpy_term<A>(be, pi, ri));
         }
     }
 }
@@ -367,7 +396,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_list_kernel(BatchDev d)
 // ------------------------------------------------------------ host side
 
 struct BatchLayout {
-    size_t r, p, q, slots_a, slots_b, sys_slice_off, slice_sys, slice_row0, slice_rows, dscal, iscal, params, width,
+    size_t r, p, q, slots_a, slots_b, slots_c, dinv, sys_slice_off, slice_sys, slice_row0, slice_rows, dscal, iscal, params, width,
         slice_ptr, total, alist, n_alist, soff, smask, col, val, bytes;
     long long ns_max, cap;
 };
@@ -389,6 +418,8 @@ BatchLayout batch_layout(int a, int32_t nsys, int32_t n, int32_t nnz)
     L.q = take(sizeof(double) * K * n);
     L.slots_a = take(sizeof(double) * K * L.ns_max);
     L.slots_b = take(sizeof(double) * K * L.ns_max);
+    L.slots_c = take(sizeof(double) * K * L.ns_max);
+    L.dinv = take(sizeof(double) * n);
     L.sys_slice_off = take(sizeof(int32_t) * (nsys + 1));
     L.slice_sys = take(sizeof(int32_t) * L.ns_max);
     L.slice_row0 = take(sizeof(int32_t) * L.ns_max);
@@ -429,11 +460,12 @@ int32_t *pinned_count()
 }
 
 struct BatchKey {
-    int arith, nsys, ns, n, chunk, grid;
+    int arith, nsys, ns, n, chunk, grid, pc;
     const void *ptrs[8];
     bool operator==(const BatchKey &o) const
     {
-        if (arith != o.arith || nsys != o.nsys || ns != o.ns || n != o.n || chunk != o.chunk || grid != o.grid)
+        if (arith != o.arith || nsys != o.nsys || ns != o.ns || n != o.n || chunk != o.chunk || grid != o.grid ||
+            pc != o.pc)
             return false;
         for (int i = 0; i < 8; ++i)
             if (ptrs[i] != o.ptrs[i]) return false;
@@ -463,9 +495,9 @@ BatchGraph &batch_graph()
     return *g;
 }
 
-template <int A>
+template <int A, bool PC>
 int enqueue_batch_chunk(const BatchDev &d, int chunk, int g, double *r, double *p, double *q, double *x, double *sa,
-                        double *sb, hipStream_t s)
+                        double *sb, double *sc, hipStream_t s)
 {
     const int gl = blocks_for(d.ns > 0 ? d.ns : 1, BNT) < 1024 ? blocks_for(d.ns > 0 ? d.ns : 1, BNT) : 1024;
     hipLaunchKernelGGL(mw_batch_list_reset_kernel, dim3(1), dim3(BNT), 0, s, d);
@@ -473,12 +505,20 @@ int enqueue_batch_chunk(const BatchDev &d, int chunk, int g, double *r, double *
     for (int it = 0; it < chunk; ++it) {
         hipLaunchKernelGGL((mw_batch_spmv_kernel<A, 1>), dim3(g), dim3(BNT), 0, s, d, p, q, sa);
         hipLaunchKernelGGL((mw_batch_alpha_kernel<A>), dim3(d.nsys), dim3(BNT), 0, s, d, sa);
-        hipLaunchKernelGGL((mw_batch_step_r_kernel<A>), dim3(g), dim3(BNT), 0, s, d, q, r, sb);
-        hipLaunchKernelGGL((mw_batch_beta_kernel<A>), dim3(d.nsys), dim3(BNT), 0, s, d, sb);
-        hipLaunchKernelGGL((mw_batch_step_p_kernel<A>), dim3(g), dim3(BNT), 0, s, d, r, p, x);
+        hipLaunchKernelGGL((mw_batch_step_r_kernel<A, PC>), dim3(g), dim3(BNT), 0, s, d, q, r, sb, sc);
+        hipLaunchKernelGGL((mw_batch_beta_kernel<A, PC>), dim3(d.nsys), dim3(BNT), 0, s, d, sb, sc);
+        hipLaunchKernelGGL((mw_batch_step_p_kernel<A, PC>), dim3(g), dim3(BNT), 0, s, d, r, p, x);
     }
     HIP_TRY(hipGetLastError());
     return MW_OK;
+}
+
+template <int A>
+int enqueue_batch_chunk_pc(bool pc, const BatchDev &d, int chunk, int g, double *r, double *p, double *q, double *x,
+                           double *sa, double *sb, double *sc, hipStream_t s)
+{
+    return pc ? enqueue_batch_chunk<A, true>(d, chunk, g, r, p, q, x, sa, sb, sc, s)
+              : enqueue_batch_chunk<A, false>(d, chunk, g, r, p, q, x, sa, sb, sc, s);
 }
 
 template <int A>
@@ -491,6 +531,7 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     const BatchLayout L = batch_layout(A, nsys, n, M->nnz);
     char *base = (char *)ws;
     const bool use_graph = !(opts && opts->no_graph);
+    const bool pc = opts && opts->precond == MW_PRECOND_JACOBI;
 
     // slices: each system starts a new 64-row slice
     std::vector<int32_t> h_sso(nsys + 1), h_sys, h_row0, h_rows;
@@ -549,6 +590,7 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     d.tol = &prm->tol;
     d.maxit = &prm->maxit;
     d.normalize = &prm->normalize;
+    d.dinv = (const double *)(base + L.dinv);
     d.nsys = nsys;
     d.ns = ns;
     d.n = n;
@@ -557,6 +599,7 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     double *q = (double *)(base + L.q);
     double *sa = (double *)(base + L.slots_a);
     double *sb = (double *)(base + L.slots_b);
+    double *sc = (double *)(base + L.slots_c);
     int32_t *width = (int32_t *)(base + L.width);
     long long *total = (long long *)(base + L.total);
 
@@ -590,8 +633,14 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     const int g = bsh.grid;
     HIP_TRY(hipMemsetAsync(d.n_active, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL((mw_batch_spmv_kernel<A, 0>), dim3(g), dim3(BNT), 0, s, d, x, q, sa);
-    hipLaunchKernelGGL((mw_batch_init_kernel<A>), dim3(g), dim3(BNT), 0, s, d, b, q, r, p, sa, sb);
-    hipLaunchKernelGGL((mw_batch_init_final_kernel<A>), dim3(nsys), dim3(BNT), 0, s, d, sa, sb);
+    if (pc) {
+        launch_jacobi_dinv(M, (double *)d.dinv, s);
+        hipLaunchKernelGGL((mw_batch_init_kernel<A, true>), dim3(g), dim3(BNT), 0, s, d, b, q, r, p, sa, sb, sc);
+        hipLaunchKernelGGL((mw_batch_init_final_kernel<A, true>), dim3(nsys), dim3(BNT), 0, s, d, sa, sb, sc);
+    } else {
+        hipLaunchKernelGGL((mw_batch_init_kernel<A, false>), dim3(g), dim3(BNT), 0, s, d, b, q, r, p, sa, sb, sc);
+        hipLaunchKernelGGL((mw_batch_init_final_kernel<A, false>), dim3(nsys), dim3(BNT), 0, s, d, sa, sb, sc);
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(hcount, d.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -600,11 +649,11 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     int chunks = 0;
     if (*hcount > 0 && use_graph) {
         BatchGraph &G = batch_graph();
-        BatchKey key{A, nsys, ns, n, chunk, g, {r, p, q, x, sa, sb, d.sp, base}};
+        BatchKey key{A, nsys, ns, n, chunk, g, pc ? 1 : 0, {r, p, q, x, sa, sb, d.sp, base}};
         if (!(G.valid && G.key == key)) {
             G.release();
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            rc = enqueue_batch_chunk<A>(d, chunk, g, r, p, q, x, sa, sb, s);
+            rc = enqueue_batch_chunk_pc<A>(pc, d, chunk, g, r, p, q, x, sa, sb, sc, s);
             hipGraph_t gr = nullptr;
             const hipError_t ce = hipStreamEndCapture(s, &gr);
             if (rc) return rc;
@@ -619,7 +668,7 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
         if (use_graph) {
             HIP_TRY(hipGraphLaunch(batch_graph().exec, s));
         } else {
-            rc = enqueue_batch_chunk<A>(d, chunk, g, r, p, q, x, sa, sb, s);
+            rc = enqueue_batch_chunk_pc<A>(pc, d, chunk, g, r, p, q, x, sa, sb, sc, s);
             if (rc) return rc;
         }
         ++chunks;
@@ -690,7 +739,8 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
                         int32_t *iters, int32_t *status, double *rel_res, mw_cg_info_t *info, void *stream)
 {
     if (!batched_args_ok(a, nsys, sys_row_off, A, b, x, workspace) || !(tol >= 0.0) || maxit < 0) return MW_EINVAL;
-    if (opts && (!shape_valid(opts->shape) || opts->normalize < 0 || opts->precond != MW_PRECOND_NONE))
+    if (opts && (!shape_valid(opts->shape) || opts->normalize < 0 ||
+                 (opts->precond != MW_PRECOND_NONE && opts->precond != MW_PRECOND_JACOBI)))
         return MW_EINVAL;
     MW_DISPATCH(a, batched_a, nsys, sys_row_off, A, b, x, tol, maxit, opts, workspace, iters, status, rel_res, info,
                 (hipStream_t)stream);

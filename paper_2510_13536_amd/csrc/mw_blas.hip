@@ -357,6 +357,22 @@ __global__ void __launch_bounds__(NT) mw_csr_grad_kernel(int n, const int32_t *_
     for (int z = row_ptr[i]; z < row_ptr[i + 1]; ++z) grad[z] = -to_fp64<A>(mul<A>(li, load<A>(x, n, col[z])));
 }
 
+// ------------------------------------------------------ Jacobi reciprocal
+//
+// d_i = fl(1 / a_ii) from the CSR rows (the last stored entry in column i;
+// none: 1 / 0 = inf, which ends a preconditioned solve with a breakdown).
+__global__ void __launch_bounds__(NT) mw_jacobi_dinv_kernel(int n, const int32_t *__restrict__ row_ptr,
+                                                            const int32_t *__restrict__ col,
+                                                            const double *__restrict__ val, double *__restrict__ dinv)
+{
+    const long i = (long)blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    double aii = 0.0;
+    for (int j = row_ptr[i]; j < row_ptr[i + 1]; ++j)
+        if (col[j] == i) aii = val[j];
+    dinv[i] = 1.0 / aii;
+}
+
 // -------------------------------------------------------------- SELL plan
 
 // Width (longest row) of every 64-row slice: one wavefront per slice.
@@ -551,6 +567,12 @@ int plan_auto(int a, const mw_csr_t *A, int lanes, void *buffer, size_t bytes, m
     if (rc == MW_OK && plan->format == MW_FMT_CSR && (long)A->nnz >= 16L * A->n)
         return plan_rows(A, rows_lanes(a, A->n, A->nnz, lanes), plan);
     return rc;
+}
+
+void launch_jacobi_dinv(const mw_csr_t *A, double *dinv, hipStream_t s)
+{
+    hipLaunchKernelGGL(mw_jacobi_dinv_kernel, dim3(blocks_for(A->n, NT)), dim3(NT), 0, s, A->n, A->row_ptr,
+                       A->col_idx, A->val, dinv);
 }
 
 int spmv_max_slots(int32_t n)

@@ -217,6 +217,16 @@ __device__ __forceinline__ Num<A> wave_sum(Num<A> v)
     return v;
 }
 
+// z_i = d_i r_i, the Jacobi step of the preconditioned solvers: the FP64
+// reciprocal of a_ii times the multi-word residual (FP64: one rounded
+// product).
+template <int A>
+__device__ __forceinline__ Num<A> jacobi(double d, const Num<A> &r)
+{
+    if constexpr (A == FP64) return promote<A>(d * r.w[0]);
+    else return dxmul<A>(d, r);
+}
+
 }  // namespace mwk
 
 namespace mwh {
@@ -231,6 +241,10 @@ size_t plan_bytes(int32_t n, int32_t nnz);
 
 // Builds a plan (SELL-64, or the CSR fallback) in `buffer`; synchronises s.
 int plan_build(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *plan, hipStream_t s);
+
+// dinv[i] = fl(1 / a_ii) for every row of A (the Jacobi preconditioner;
+// see launch_jacobi_dinv in mw_blas.hip).
+void launch_jacobi_dinv(const mw_csr_t *A, double *dinv, hipStream_t s);
 
 // Most reduction slots any CG-mode SpMV launch writes for n rows.
 int spmv_max_slots(int32_t n);

@@ -49,29 +49,6 @@ namespace {
 // Workspace slot arrays hold the partials of up to this many workgroups.
 constexpr int UGRID_MAX = MAX_GRID;
 
-// z_i = d_i r_i, the Jacobi step: the FP64 reciprocal times the multi-word
-// residual (FP64: one rounded product).
-template <int A>
-__device__ __forceinline__ Num<A> jacobi(double d, const Num<A> &r)
-{
-    if constexpr (A == FP64) return promote<A>(d * r.w[0]);
-    else return dxmul<A>(d, r);
-}
-
-// d_i = fl(1 / a_ii) from the CSR rows (the last stored entry in column i;
-// none: 1 / 0 = inf, which ends the solve with a breakdown).
-__global__ void __launch_bounds__(NT) mw_cg_dinv_kernel(int n, const int32_t *__restrict__ row_ptr,
-                                                        const int32_t *__restrict__ col,
-                                                        const double *__restrict__ val, double *__restrict__ dinv)
-{
-    const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
-    double aii = 0.0;
-    for (int j = row_ptr[i]; j < row_ptr[i + 1]; ++j)
-        if (col[j] == i) aii = val[j];
-    dinv[i] = 1.0 / aii;
-}
-
 // r = b - q (q = A x0), p = r, partials of r^T r and b^T b.  PC (Jacobi):
 // p = z = D r, partials of r^T z (to slots_rr), b^T b and r^T r (to
 // slots_c).
@@ -644,8 +621,7 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     if (rc) return rc;
     const int gi = persistent_grid(blocks_for(n, NT));
     if (pc) {
-        hipLaunchKernelGGL(mw_cg_dinv_kernel, dim3(blocks_for(n, NT)), dim3(NT), 0, s, n, M->row_ptr, M->col_idx,
-                           M->val, dinv);
+        launch_jacobi_dinv(M, dinv, s);
         hipLaunchKernelGGL((mw_cg_init_kernel<A, true>), dim3(gi), dim3(NT), 0, s, n, b, q, r, p, sa, sb, dinv, sc);
         hipLaunchKernelGGL((mw_cg_init_final_kernel<A, true>), dim3(1), dim3(FIN_NT), 0, s, gi, sa, sb, sc, st);
     } else {

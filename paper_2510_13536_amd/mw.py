@@ -384,9 +384,10 @@ def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0
 
 
 def cg_solve_batched(arith, A, sys_row_off, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0,
-                     graph=True, workspace=None, shape=None):
+                     graph=True, workspace=None, shape=None, precond=None):
     """Solve the independent systems on the diagonal blocks of A (a DeviceCSR)
-    together; sys_row_off: host sequence of nsys + 1 row offsets.
+    together; sys_row_off: host sequence of nsys + 1 row offsets; precond:
+    None or "jacobi" (as cg_solve, per system).
 
     Returns (x (k, n) tensor, iters, status, rel_res (numpy arrays), info)."""
     import numpy as np
@@ -408,7 +409,9 @@ def cg_solve_batched(arith, A, sys_row_off, b, x=None, tol=1e-12, maxit=None, no
     status = torch.zeros(nsys, dtype=torch.int32, device=b.device)
     rel = torch.zeros(nsys, dtype=torch.float64, device=b.device)
     sh = Shape.of(shape)
-    opts = CgOpts(int(normalize), int(chunk), None, None, None, 0 if graph else 1, 0,
+    if precond not in PRECOND:
+        raise MWError("precond must be None or 'jacobi'")
+    opts = CgOpts(int(normalize), int(chunk), None, None, None, 0 if graph else 1, PRECOND[precond],
                   C.pointer(sh) if sh is not None else None)
     info = CgInfo()
     csr = A.c()
