@@ -445,6 +445,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape tuner (built-in shapes)")
     ap.add_argument("--table1", action="store_true",
                     help="also time iterations on banded stand-ins of the paper's Table I matrices")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the 512-system batched comparison (for profiling that path) and print its line")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -466,6 +468,13 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.batched_only:
+        bt = bench_batched(mw, P, torch, dev, tune=not args.no_tune)
+        print(json.dumps({"metric": "batched QTW CG time-to-1e-12 (512 systems, one lockstep solve)",
+                          "value": bt["qtw"]["batched_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+                          "dtype": "f64", "data": "synthetic", "config": {"workload": bt["workload"]},
+                          "extra": {"batched": bt}}), flush=True)
+        return
     t = time.time()
     A, b, _ = P.case_poisson3d(args.nx)
     log("problem: 3D Poisson %d^3 n=%d nnz=%d (%.1fs)" % (args.nx, A.n, A.nnz, time.time() - t))
