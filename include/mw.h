@@ -34,8 +34,8 @@
  *             convergence.
  *   Errors:   functions return MW_OK (0), a positive solver status, or a
  *             negative error: MW_EINVAL for a rejected argument (nothing is
- *             enqueued) and MW_EHIP for a HIP runtime error (text available
- *             from mw_last_error()).
+ *             enqueued) and MW_EHIP for a HIP runtime error (details from
+ *             mw_last_error()).
  *   Threads:  calls are re-entrant across streams when their workspaces
  *             and outputs are distinct.
  */
@@ -228,7 +228,11 @@ int mw_words(mw_arith_t a);
 /* Static text for a return code. */
 const char *mw_status_string(int code);
 
-/* Text of the last HIP error seen by this thread ("" if none). */
+/* Details of the last failed call on this thread: the HIP error of an
+ * MW_EHIP, or the cause of an MW_EINVAL that is more than a rejected
+ * argument (a failed CSR check, batched padding beyond the workspace, a
+ * tuner run that stopped early); "" otherwise.  Every status-returning
+ * call clears it on entry. */
 const char *mw_last_error(void);
 
 /*
@@ -281,6 +285,20 @@ int mw_dot(mw_arith_t a, int32_t n, const double *x, const double *y, double *re
  * sequential definition.  No workspace.  Asynchronous.
  */
 int mw_spmv(mw_arith_t a, const mw_csr_t *A, const double *x, double *y, void *stream);
+
+/*
+ * Checks a CSR matrix on the device (a set-up step, not part of the
+ * paper's method): row_ptr[0] = 0, row_ptr[n] = nnz, row_ptr
+ * non-decreasing, every column index in [0, n).  Reads row_ptr[0 .. n] and
+ * col_idx[0 .. nnz) only, so it is safe on arrays of those lengths
+ * whatever they hold, whereas the other entry points trust these
+ * properties and may read out of bounds without them.  Returns MW_OK or
+ * MW_EINVAL (mw_last_error names the first failed property).  With
+ * MW_CHECK_CSR=1 in the environment (read once per process) every entry
+ * point that reads a matrix runs this check first and returns its
+ * MW_EINVAL.  Synchronises `stream`.
+ */
+int mw_csr_check(const mw_csr_t *A, void *stream);
 
 
 /* Bytes of device memory mw_spmv_plan needs for an n x n matrix with nnz

@@ -765,10 +765,12 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
                         double *x, double tol, int32_t maxit, const mw_cg_opts_t *opts, void *workspace,
                         int32_t *iters, int32_t *status, double *rel_res, mw_cg_info_t *info, void *stream)
 {
+    mwh::clear_error();
     if (!batched_args_ok(a, nsys, sys_row_off, A, b, x, workspace) || !(tol >= 0.0) || maxit < 0) return MW_EINVAL;
     if (opts && (!shape_valid(opts->shape) || opts->normalize < 0 ||
                  (opts->precond != MW_PRECOND_NONE && opts->precond != MW_PRECOND_JACOBI)))
         return MW_EINVAL;
+    MW_CSR_GUARD(A, stream);
     MW_DISPATCH(a, batched_a, nsys, sys_row_off, A, b, x, tol, maxit, opts, workspace, iters, status, rel_res, info,
                 (hipStream_t)stream);
 }
@@ -776,6 +778,7 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
 int mw_cg_batched_tune(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, const mw_csr_t *A,
                        const double *b, double *x, int32_t iters, void *workspace, mw_shape_t *best, void *stream)
 {
+    mwh::clear_error();
     if (!best || iters < 2 || iters > 4096 || !batched_args_ok(a, nsys, sys_row_off, A, b, x, workspace))
         return MW_EINVAL;
     const int grids[] = {256, 512, 1024, 1536, 2048};

@@ -50,6 +50,8 @@ int hip_fail(hipError_t e, const char *what)
 
 void set_error(const char *msg) { snprintf(g_err, sizeof(g_err), "%s", msg); }
 
+void clear_error() { g_err[0] = 0; }
+
 }  // namespace mwh
 
 namespace {
@@ -357,6 +359,27 @@ __global__ void __launch_bounds__(NT) mw_csr_grad_kernel(int n, const int32_t *_
     for (int z = row_ptr[i]; z < row_ptr[i + 1]; ++z) grad[z] = -to_fp64<A>(mul<A>(li, load<A>(x, n, col[z])));
 }
 
+// ------------------------------------------------------------- CSR check
+//
+// Flags (pinned host memory, written by the device): [0] row_ptr[0] != 0 or
+// row_ptr[n] != nnz, [1] row_ptr decreases somewhere, [2] a column index
+// outside [0, n).  Reads row_ptr[0 .. n] and col[0 .. nnz) only, so it is
+// safe on any arrays of those lengths, whatever they hold.
+__global__ void __launch_bounds__(NT) mw_csr_check_kernel(int n, int nnz, const int32_t *__restrict__ row_ptr,
+                                                          const int32_t *__restrict__ col, int32_t *flags)
+{
+    const long tid = (long)blockIdx.x * NT + threadIdx.x, stride = (long)gridDim.x * NT;
+    if (tid == 0 && (row_ptr[0] != 0 || row_ptr[n] != nnz)) flags[0] = 1;
+    bool dec = false, out = false;
+    for (long i = tid; i < n; i += stride) dec = dec || row_ptr[i + 1] < row_ptr[i];
+    for (long j = tid; j < nnz; j += stride) {
+        const int c = col[j];
+        out = out || c < 0 || c >= n;
+    }
+    if (dec) flags[1] = 1;
+    if (out) flags[2] = 1;
+}
+
 // ------------------------------------------------------ Jacobi reciprocal
 //
 // d_i = fl(1 / a_ii) from the CSR rows (the last stored entry in column i;
@@ -569,6 +592,36 @@ int plan_auto(int a, const mw_csr_t *A, int lanes, void *buffer, size_t bytes, m
     return rc;
 }
 
+int csr_check(const mw_csr_t *A, hipStream_t s)
+{
+    if (!valid_csr(A)) return MW_EINVAL;
+    thread_local int32_t *flags = nullptr;
+    if (!flags && hipHostMalloc((void **)&flags, 64, hipHostMallocCoherent) != hipSuccess) flags = nullptr;
+    if (!flags) return hip_fail(hipErrorOutOfMemory, "hipHostMalloc");
+    int32_t *dflags = nullptr;
+    HIP_TRY(hipHostGetDevicePointer((void **)&dflags, flags, 0));
+    flags[0] = flags[1] = flags[2] = 0;
+    const long work = A->n > A->nnz ? A->n : A->nnz;
+    const int g = blocks_for(work, NT) < 1024 ? blocks_for(work, NT) : 1024;
+    hipLaunchKernelGGL(mw_csr_check_kernel, dim3(g > 0 ? g : 1), dim3(NT), 0, s, A->n, A->nnz, A->row_ptr, A->col_idx,
+                       dflags);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    if (flags[0]) set_error("CSR check: row_ptr[0] is not 0 or row_ptr[n] is not nnz");
+    else if (flags[1]) set_error("CSR check: row_ptr decreases");
+    else if (flags[2]) set_error("CSR check: a column index is outside [0, n)");
+    return flags[0] || flags[1] || flags[2] ? MW_EINVAL : MW_OK;
+}
+
+bool csr_check_on()
+{
+    static const bool on = [] {
+        const char *e = getenv("MW_CHECK_CSR");
+        return e && atoi(e) != 0;
+    }();
+    return on;
+}
+
 void launch_jacobi_dinv(const mw_csr_t *A, double *dinv, hipStream_t s)
 {
     hipLaunchKernelGGL(mw_jacobi_dinv_kernel, dim3(blocks_for(A->n, NT)), dim3(NT), 0, s, A->n, A->row_ptr,
@@ -779,6 +832,7 @@ const char *mw_last_error(void) { return mwh::g_err; }
 
 int mw_elementwise(mw_arith_t a, int op, int32_t n, const double *u, const double *v, double *w, void *stream)
 {
+    mwh::clear_error();
     if (!valid_arith(a) || op < MW_OP_ADD || op > MW_OP_TOFP64 || n < 0 || (n > 0 && (!u || !w)))
         return MW_EINVAL;
     const bool needs_v = (op == MW_OP_ADD || op == MW_OP_MUL || op == MW_OP_DXMUL || op == MW_OP_DIV);
@@ -790,6 +844,7 @@ int mw_elementwise(mw_arith_t a, int op, int32_t n, const double *u, const doubl
 
 int mw_axpy(mw_arith_t a, int32_t n, const double *alpha, const double *x, double *y, void *stream)
 {
+    mwh::clear_error();
     if (!valid_arith(a) || n < 0 || (n > 0 && (!alpha || !x || !y))) return MW_EINVAL;
     if (n == 0) return MW_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -806,6 +861,7 @@ size_t mw_dot_workspace_bytes(mw_arith_t a, int32_t n)
 int mw_dot(mw_arith_t a, int32_t n, const double *x, const double *y, double *result, void *workspace,
            void *stream)
 {
+    mwh::clear_error();
     if (!valid_arith(a) || n < 0 || !result || !workspace || (n > 0 && (!x || !y))) return MW_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     MW_DISPATCH(a, dot_a, n, x, y, result, workspace, s);
@@ -813,15 +869,25 @@ int mw_dot(mw_arith_t a, int32_t n, const double *x, const double *y, double *re
 
 int mw_spmv(mw_arith_t a, const mw_csr_t *A, const double *x, double *y, void *stream)
 {
+    mwh::clear_error();
     if (!valid_arith(a) || !valid_csr(A) || !x || !y || x == y) return MW_EINVAL;
+    MW_CSR_GUARD(A, stream);
     hipStream_t s = (hipStream_t)stream;
     MW_DISPATCH(a, spmv_csr_a, A, x, y, s);
+}
+
+int mw_csr_check(const mw_csr_t *A, void *stream)
+{
+    mwh::clear_error();
+    return mwh::csr_check(A, (hipStream_t)stream);
 }
 
 int mw_csr_grad(mw_arith_t a, const mw_csr_t *A, const double *lam, const double *x, double *grad_val,
                 void *stream)
 {
+    mwh::clear_error();
     if (!valid_arith(a) || !valid_csr(A) || !lam || !x || !grad_val) return MW_EINVAL;
+    MW_CSR_GUARD(A, stream);
     hipStream_t s = (hipStream_t)stream;
     MW_DISPATCH(a, grad_a, A, lam, x, grad_val, s);
 }
@@ -834,19 +900,24 @@ size_t mw_spmv_plan_bytes(int32_t n, int32_t nnz)
 
 int mw_spmv_plan(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *plan, void *stream)
 {
+    mwh::clear_error();
     if (!valid_csr(A) || !buffer || !plan) return MW_EINVAL;
+    MW_CSR_GUARD(A, stream);
     return mwh::plan_build(A, buffer, bytes, plan, (hipStream_t)stream);
 }
 
 int mw_spmv_plan_rows(const mw_csr_t *A, int32_t lanes, mw_spmv_plan_t *plan)
 {
+    mwh::clear_error();
     if (!valid_csr(A) || !plan) return MW_EINVAL;
     return mwh::plan_rows(A, lanes, plan);
 }
 
 int mw_spmv_planned(mw_arith_t a, const mw_spmv_plan_t *plan, const double *x, double *y, void *stream)
 {
+    mwh::clear_error();
     if (!valid_arith(a) || !plan_valid(plan) || !x || !y || x == y) return MW_EINVAL;
+    MW_CSR_GUARD(&plan->csr, stream);
     hipStream_t s = (hipStream_t)stream;
     MW_DISPATCH(a, spmv_planned_a, plan, x, y, s);
 }

@@ -242,6 +242,19 @@ size_t plan_bytes(int32_t n, int32_t nnz);
 // Builds a plan (SELL-64, or the CSR fallback) in `buffer`; synchronises s.
 int plan_build(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *plan, hipStream_t s);
 
+// The CSR check of mw_csr_check (synchronises s), and whether every entry
+// point that reads a matrix runs it first (MW_CHECK_CSR=1 in the
+// environment, read once).
+int csr_check(const mw_csr_t *A, hipStream_t s);
+bool csr_check_on();
+#define MW_CSR_GUARD(A, s)                                              \
+    do {                                                                \
+        if (mwh::csr_check_on()) {                                      \
+            const int rc_ = mwh::csr_check((A), (hipStream_t)(s));      \
+            if (rc_) return rc_;                                        \
+        }                                                               \
+    } while (0)
+
 // dinv[i] = fl(1 / a_ii) for every row of A (the Jacobi preconditioner;
 // see launch_jacobi_dinv in mw_blas.hip).
 void launch_jacobi_dinv(const mw_csr_t *A, double *dinv, hipStream_t s);

@@ -743,8 +743,10 @@ size_t mw_cg_workspace_bytes(mw_arith_t a, int32_t n, int32_t nnz)
 int mw_cg_plan(mw_arith_t a, const mw_csr_t *A, int32_t lanes, void *buffer, size_t bytes, mw_spmv_plan_t *plan,
                void *stream)
 {
+    mwh::clear_error();
     if (!valid_arith(a) || !valid_csr(A) || !plan) return MW_EINVAL;
     if (lanes != 0 && !(lanes >= 2 && lanes <= 64 && (lanes & (lanes - 1)) == 0)) return MW_EINVAL;
+    MW_CSR_GUARD(A, stream);
     const int l = lanes ? lanes : cg_shape(a, A->n, A->nnz, 1, nullptr, 0).lanes;
     return plan_auto(a, A, l, buffer, bytes, plan, (hipStream_t)stream);
 }
@@ -752,20 +754,24 @@ int mw_cg_plan(mw_arith_t a, const mw_csr_t *A, int32_t lanes, void *buffer, siz
 int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, double tol, int32_t maxit,
                 const mw_cg_opts_t *opts, void *workspace, mw_cg_info_t *info, void *stream)
 {
+    mwh::clear_error();
     if (!valid_arith(a) || !valid_csr(A) || !b || !x || !workspace || !(tol >= 0.0) || maxit < 0)
         return MW_EINVAL;
     if (opts && opts->plan && (!plan_valid(opts->plan) || opts->plan->n != A->n || opts->plan->csr.row_ptr != A->row_ptr))
         return MW_EINVAL;
     if (opts && (!shape_valid(opts->shape) || opts->normalize < 0)) return MW_EINVAL;
     if (opts && opts->precond != MW_PRECOND_NONE && opts->precond != MW_PRECOND_JACOBI) return MW_EINVAL;
+    MW_CSR_GUARD(A, stream);
     MW_DISPATCH(a, cg_a, A, b, x, tol, maxit, opts, workspace, info, (hipStream_t)stream);
 }
 
 int mw_cg_tune(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, int32_t iters, void *workspace,
                mw_shape_t *best, void *stream)
 {
+    mwh::clear_error();
     if (!valid_arith(a) || !valid_csr(A) || !b || !x || !workspace || !best || iters < 2 || iters > 4096)
         return MW_EINVAL;
+    MW_CSR_GUARD(A, stream);
     const int n = A->n;
     const CgLayout L = cg_layout(a, n, A->nnz);
     hipStream_t s = (hipStream_t)stream;

@@ -154,6 +154,7 @@ namespace mwh {
 
 int hip_fail(hipError_t e, const char *what);
 void set_error(const char *msg);
+void clear_error();  // at the entry of every status-returning ABI call
 
 inline int blocks_for(long n, long per) { return (int)((n + per - 1) / per); }
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }

@@ -132,6 +132,7 @@ def lib():
     L.mw_spmv_plan.argtypes = [C.POINTER(Csr), _vp, C.c_size_t, C.POINTER(SpmvPlan), _vp]
     L.mw_spmv_planned.argtypes = [C.c_int, C.POINTER(SpmvPlan), _vp, _vp, _vp]
     L.mw_spmv_plan_rows.argtypes = [C.POINTER(Csr), C.c_int32, C.POINTER(SpmvPlan)]
+    L.mw_csr_check.argtypes = [C.POINTER(Csr), _vp]
     L.mw_cg_plan.argtypes = [C.c_int, C.POINTER(Csr), C.c_int32, _vp, C.c_size_t, C.POINTER(SpmvPlan), _vp]
     L.mw_cg_workspace_bytes.argtypes = [C.c_int, C.c_int32, C.c_int32]
     L.mw_cg_workspace_bytes.restype = C.c_size_t
@@ -154,8 +155,9 @@ def lib():
 def _check(rc, what):
     if rc < 0:
         msg = lib().mw_status_string(rc).decode()
-        if rc == MW_EHIP:
-            msg += ": " + lib().mw_last_error().decode()
+        detail = lib().mw_last_error().decode()
+        if detail:
+            msg += ": " + detail
         raise MWError("%s failed (%d): %s" % (what, rc, msg))
     return rc
 
@@ -262,6 +264,13 @@ def spmv(arith, A, x, y=None):
     csr = A.c()
     _check(lib().mw_spmv(ARITH[arith], C.byref(csr), _ptr(x), _ptr(y), _stream()), "mw_spmv")
     return y
+
+
+def csr_check(A):
+    """Check A's CSR arrays on the device (mw_csr_check); raises MWError
+    naming the first failed property."""
+    csr = A.c()
+    _check(lib().mw_csr_check(C.byref(csr), _stream()), "mw_csr_check")
 
 
 class Plan:
