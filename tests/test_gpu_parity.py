@@ -411,6 +411,39 @@ def test_spmv_rows_within_bound(mw, arith, mat, lanes):
     assert np.all(y1[:, empty] == 0.0)
 
 
+@pytest.mark.parametrize("arith", ["fp64", "qtw"])
+def test_spmv_rows_tiny_and_ragged(mw, arith):
+    """Vector-row plans at n = 1, 2, 63, 65, 257 (a single tile, a ragged
+    last tile) and one row longer than 64 x L entries, every L: within the
+    row-sum bound, and the CG on a tiny SPD system with a vector plan agrees
+    with the oracle."""
+    k = O.WORDS[arith]
+    rng = np.random.default_rng(17)
+    mats = []
+    for n in (1, 2, 63, 65, 257):
+        M = sp.random(n, n, density=min(1.0, 9.0 / n), random_state=rng, format="csr") + sp.eye(n)
+        mats.append(P.CSR.from_scipy(M))
+    long_row = sp.lil_matrix((5000, 5000))
+    long_row[5, :] = rng.standard_normal(5000)               # 5000 > 64 x 64 entries in one row
+    mats.append(P.CSR.from_scipy(long_row.tocsr() + sp.eye(5000)))
+    for A in mats:
+        x = rand_mw(np.random.default_rng(A.n), k, A.n, emin=-3, emax=3)
+        Ad = mw.DeviceCSR.from_host(A)
+        for lanes in (2, 4, 8, 16, 32, 64):
+            y = host(mw.spmv_planned(arith, mw.Plan(Ad, rows=lanes), dev(x)))
+            err, sc = O.spmv_error(arith, A, x, y)
+            lens = np.diff(A.row_ptr)
+            bound = 8 * (np.ceil(lens / lanes) + np.log2(lanes) + 2) * 2.0 ** (-53 * k) * sc
+            assert np.all(err <= bound), (A.n, lanes)
+    A = P.poisson2d(3, 2)
+    b = A.matvec(np.arange(1.0, A.n + 1))
+    Ad = mw.DeviceCSR.from_host(A)
+    xo, io = O.cg_solve(arith, A, b, tol=1e-12)
+    for lanes in (2, 64):
+        xg, ig = mw.cg_solve(arith, Ad, dev(b), tol=1e-12, plan=mw.Plan(Ad, rows=lanes))
+        assert ig["status"] == io["status"] == "ok" and abs(ig["iters"] - io["iters"]) <= 1
+
+
 def _normal_matrix(seed=9, n=3000, k=6, shift=0.01):
     """B^T B + shift I, B random sparse (k entries per row on average): SPD,
     rows of 1 to ~100 entries (about 37 on average), ~400 CG iterations."""
