@@ -411,7 +411,7 @@ def test_spmv_rows_within_bound(mw, arith, mat, lanes):
     assert np.all(y1[:, empty] == 0.0)
 
 
-@pytest.mark.parametrize("arith", ["fp64", "qtw"])
+@pytest.mark.parametrize("arith", ARITHS)
 def test_spmv_rows_tiny_and_ragged(mw, arith):
     """Vector-row plans at n = 1, 2, 63, 65, 257 (a single tile, a ragged
     last tile) and one row longer than 64 x L entries, every L: within the
