@@ -486,15 +486,19 @@ int32_t *pinned_count()
     return buf;
 }
 
+// What a captured chunk depends on: the sizes that place the workspace's
+// arrays (batch_layout: n, nnz and nsys move the slice copy's offsets) and
+// every pointer its kernels take, the BatchDev fields included.
 struct BatchKey {
-    int arith, nsys, ns, n, chunk, grid, pc;
-    const void *ptrs[8];
+    int arith, nsys, ns, n, nnz, chunk, grid, pc;
+    static constexpr int NPTR = 14;
+    const void *ptrs[NPTR];
     bool operator==(const BatchKey &o) const
     {
-        if (arith != o.arith || nsys != o.nsys || ns != o.ns || n != o.n || chunk != o.chunk || grid != o.grid ||
-            pc != o.pc)
+        if (arith != o.arith || nsys != o.nsys || ns != o.ns || n != o.n || nnz != o.nnz || chunk != o.chunk ||
+            grid != o.grid || pc != o.pc)
             return false;
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < NPTR; ++i)
             if (ptrs[i] != o.ptrs[i]) return false;
         return true;
     }
@@ -580,13 +584,8 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     hipStream_t s = batch_stream();
     int32_t *hcount = pinned_count();
     if (!s || !hcount) return hip_fail(hipErrorOutOfMemory, "stream/pinned buffer");
-    hipEvent_t e_in, e0, e1;
-    HIP_TRY(hipEventCreateWithFlags(&e_in, hipEventDisableTiming));
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventRecord(e_in, user));
-    HIP_TRY(hipStreamWaitEvent(s, e_in, 0));
-    HIP_TRY(hipEventRecord(e0, s));
+    SolveEvents se;
+    if (const int erc = se.start(user, s)) return erc;
 
     BatchDev d{};
     d.sys_slice_off = (int32_t *)(base + L.sys_slice_off);
@@ -676,7 +675,8 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     int chunks = 0;
     if (*hcount > 0 && use_graph) {
         BatchGraph &G = batch_graph();
-        BatchKey key{A, nsys, ns, n, chunk, g, pc ? 1 : 0, {r, p, q, x, sa, sb, d.sp, base}};
+        BatchKey key{A, nsys, ns, n, M->nnz, chunk, g, pc ? 1 : 0,
+                     {r, p, q, x, sa, sb, sc, base, d.sp, d.sc, d.sv, d.soff, d.smask, d.dinv}};
         if (!(G.valid && G.key == key)) {
             G.release();
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -709,13 +709,10 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     if (rel_out) HIP_TRY(hipMemcpyAsync(rel_out, d.rel, sizeof(double) * nsys, hipMemcpyDeviceToDevice, s));
     std::vector<int32_t> hi(2 * (size_t)nsys);
     HIP_TRY(hipMemcpyAsync(hi.data(), d.iters, sizeof(int32_t) * 2 * nsys, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventRecord(se.t1, s));
     HIP_TRY(hipStreamSynchronize(s));
     float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e_in);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    HIP_TRY(hipEventElapsedTime(&ms, se.t0, se.t1));
     int worst = MW_OK, maxit_seen = 0;
     for (int i = 0; i < nsys; ++i) {
         if (hi[i] > maxit_seen) maxit_seen = hi[i];

@@ -408,6 +408,10 @@ hipStream_t own_stream()
 struct EventPool {
     hipEvent_t *e = nullptr;
     int n = 0;
+    EventPool() = default;
+    EventPool(const EventPool &) = delete;
+    EventPool &operator=(const EventPool &) = delete;
+    ~EventPool() { release(); }
     int init(int count)
     {
         release();
@@ -583,13 +587,8 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     if (!s || !fl) return hip_fail(hipErrorOutOfMemory, "stream/pinned buffer");
 
     EventPool ev;
-    hipEvent_t e_in, e0, e1;
-    HIP_TRY(hipEventCreateWithFlags(&e_in, hipEventDisableTiming));
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventRecord(e_in, user));
-    HIP_TRY(hipStreamWaitEvent(s, e_in, 0));
-    HIP_TRY(hipEventRecord(e0, s));
+    SolveEvents se;
+    if (const int erc = se.start(user, s)) return erc;
 
     // SpMV plan: given by the caller or chosen here (plan_auto; the lanes
     // of vector rows from the launch shape)
@@ -712,13 +711,10 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
         iters_before = now;
     }
     HIP_TRY(hipMemcpyAsync(&h, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventRecord(se.t1, s));
     HIP_TRY(hipStreamSynchronize(s));
     float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e_in);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    HIP_TRY(hipEventElapsedTime(&ms, se.t0, se.t1));
     if (info) {
         info->iters = h.iters_final;
         info->status = h.status;

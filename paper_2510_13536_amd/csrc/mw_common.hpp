@@ -172,6 +172,33 @@ inline bool valid_csr(const mw_csr_t *A)
         if (e_ != hipSuccess) return mwh::hip_fail(e_, #call);     \
     } while (0)
 
+// The events that order a solve after the caller's stream (`in`) and time
+// it (t0, t1); destroyed on every return path of the solve.
+struct SolveEvents {
+    hipEvent_t in = nullptr, t0 = nullptr, t1 = nullptr;
+    SolveEvents() = default;
+    SolveEvents(const SolveEvents &) = delete;
+    SolveEvents &operator=(const SolveEvents &) = delete;
+    ~SolveEvents()
+    {
+        if (in) (void)hipEventDestroy(in);
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+    }
+    // Creates the three events, makes `own` wait for the work enqueued on
+    // `user` so far and records t0 on `own`.
+    int start(hipStream_t user, hipStream_t own)
+    {
+        HIP_TRY(hipEventCreateWithFlags(&in, hipEventDisableTiming));
+        HIP_TRY(hipEventCreate(&t0));
+        HIP_TRY(hipEventCreate(&t1));
+        HIP_TRY(hipEventRecord(in, user));
+        HIP_TRY(hipStreamWaitEvent(own, in, 0));
+        HIP_TRY(hipEventRecord(t0, own));
+        return 0;
+    }
+};
+
 // Kernel launch; given a pair of events, they are attached to the dispatch
 // itself (hipExtLaunchKernelGGL), so their elapsed time is the kernel's
 // execution alone.
