@@ -195,6 +195,80 @@ def test_normalisation_frequency_modes(arith):
         assert hK["status"] != "ok"
 
 
+def _overlap(v):
+    """||second word|| / ||leading word|| of a multi-word vector."""
+    return np.linalg.norm(v[1]) / max(np.linalg.norm(v[0]), 1e-300)
+
+
+def _cg_overlaps(arith, A, b, K, iters, normalise_p=False):
+    """Alg. 1 replayed with the oracle's vector operations (SpMV, dot,
+    element-wise add, mul, neg, div, normalise), returning the FP64-rounded
+    relative residual and the word overlap of p after every iteration.
+    normalise_p also normalises p whenever r is (a variant, not the
+    paper's placement)."""
+    k = O.WORDS[arith]
+    n = A.n
+
+    def E(op, u, v=None):
+        return O.elementwise(arith, op, u, v)
+
+    def bcast(s):
+        return np.repeat(np.asarray(s).reshape(k, 1), n, axis=1)
+
+    def div(a, c):
+        return E("div", np.asarray(a).reshape(k, 1), np.asarray(c).reshape(k, 1))[:, 0]
+
+    bw = np.zeros((k, n))
+    bw[0] = b
+    r = bw.copy()
+    p = r.copy()
+    rho = O.dot(arith, r, r)
+    nb = np.sqrt(E("tofp64", O.dot(arith, bw, bw).reshape(k, 1))[0])
+    res, ov = [], []
+    for it in range(1, iters + 1):
+        q = O.spmv(arith, A, p)
+        sigma = O.dot(arith, p, q)
+        if not np.sum(sigma) > 0:
+            break
+        alpha = div(rho, sigma)
+        r = E("add", r, E("neg", E("mul", bcast(alpha), q)))
+        if K > 0 and it % K == 0:
+            r = E("norm", r)
+            if normalise_p:
+                p = E("norm", p)
+        rho_new = O.dot(arith, r, r)
+        res.append(np.sqrt(E("tofp64", rho_new.reshape(k, 1))[0]) / nb)
+        p = E("add", r, E("mul", bcast(div(rho_new, rho)), p))
+        ov.append(_overlap(p))
+        rho = rho_new
+    return np.array(res), np.array(ov)
+
+
+@pytest.mark.parametrize("arith", ["qdw", "qtw"])
+def test_normalise_every_second_iteration_mechanism(arith):
+    """Why K = 2 breaks down while K = 1 and K = 0 converge (measured, not
+    stated by the paper).  p is never normalised.  With K = 1, p is built
+    from a normalised r each time and its word overlap stays at the unit
+    round-off; with K = 2 the overlap of p grows geometrically (about x2.5
+    per two iterations on this matrix) until the long division's operands
+    overlap so much that alpha goes wrong and p^T q turns negative.
+    Normalising p together with r holds the overlap down.  The replay is
+    first checked against the oracle's own solver bit for bit."""
+    A, b, _ = P.case_poisson2d_64()
+    res2, ov2 = _cg_overlaps(arith, A, b, 2, 40)
+    _, h2 = O.cg_solve(arith, A, b, tol=1e-12, maxit=40, normalise=2, history=True)
+    assert np.array_equal(res2, h2["history"])
+    _, ov1 = _cg_overlaps(arith, A, b, 1, 40)
+    _, ov2p = _cg_overlaps(arith, A, b, 2, 40, normalise_p=True)
+    assert ov1.max() < 1e-15 and ov2p.max() < 1e-15
+    assert ov2[-1] > 1e4 * ov1[-1]
+    # geometric growth: every ten iterations multiply the overlap by >= 10
+    assert np.all(ov2[19::10] > 10 * ov2[9:-10:10])
+    # and the K = 2 solve itself breaks down
+    _, hb = O.cg_solve(arith, A, b, tol=1e-12, maxit=400, normalise=2)
+    assert hb["status"] == "breakdown"
+
+
 @pytest.mark.parametrize("arith", ARITHS)
 def test_initial_guess(arith):
     """Alg. 1 starts from the given x0 (r0 = b - A x0).  With x0 the exact
