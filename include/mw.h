@@ -277,6 +277,25 @@ size_t mw_dot_workspace_bytes(mw_arith_t a, int32_t n);
 int mw_dot(mw_arith_t a, int32_t n, const double *x, const double *y, double *result,
            void *workspace, void *stream);
 
+/* Largest n mw_dot_noalloc accepts (2^25 elements). */
+#define MW_DOT_NOALLOC_MAX_N 33554432
+
+/*
+ * mw_dot without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and summation
+ * order as mw_dot, so the result is bit-identical to mw_dot's.  The
+ * per-workgroup partial sums live in a static device array of the library
+ * (384 KiB per GPU, held until the process ends); the library allocates
+ * nothing.  n in [0, MW_DOT_NOALLOC_MAX_N]; a larger n returns MW_EINVAL
+ * (mw_last_error says why).  Calls that overlap on one GPU (several
+ * streams, threads or processes' graphs at once) share that array and race:
+ * serialise them.  The first call on a device looks up the array's address
+ * there (a host-side query, no allocation).  Asynchronous.
+ */
+int mw_dot_noalloc(mw_arith_t a, int32_t n, const double *x, const double *y, double *result,
+                   void *stream);
+
 /*
  * y = A x (CSR SpMV, Sec. IV-B; q = A p in Alg. 1).  A: FP64 CSR; x, y: k planes
  * of A->n (must not alias).  Each row is accumulated from zero in CSR order,

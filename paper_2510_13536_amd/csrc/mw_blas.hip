@@ -31,8 +31,8 @@
 #include "mw_blas.hpp"
 
 #include <cstdlib>
-
 #include <cstring>
+#include <mutex>
 
 using namespace mwk;
 
@@ -787,6 +787,48 @@ int dot_a(int32_t n, const double *x, const double *y, double *res, void *ws, hi
     return MW_OK;
 }
 
+// ------------------------------------------- dot without a workspace
+//
+// mw_dot_noalloc keeps the per-workgroup partial sums in `scratch`, a
+// file-scope device array that every GPU the library runs on holds until
+// the process ends.  On the host `scratch` is only a stand-in for the
+// symbol, not a device address: the address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and that pointer is what
+// the kernels receive.  Every slot the reduction reads is written by the
+// partial kernel of the same call, so nothing needs clearing between calls;
+// calls that overlap on one GPU share the array and race.
+constexpr int NOALLOC_SLOTS = MW_DOT_NOALLOC_MAX_N / (NT * DOT_EPT);
+static_assert((long)NOALLOC_SLOTS * NT * DOT_EPT == MW_DOT_NOALLOC_MAX_N, "whole workgroups");
+constexpr int MAX_DEVICES = 64;
+
+static __device__ __align__(256) double scratch[3 * NOALLOC_SLOTS];
+
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The current device's copy of `scratch`.
+int scratch_slots(double **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        set_error("mw_dot_noalloc: device ordinal beyond the 64 this library keeps scratch addresses for");
+        return MW_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("mw_dot_noalloc: hipGetSymbolAddress returned a null address for the scratch array");
+            return MW_EHIP;
+        }
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MW_OK;
+}
+
 template <int A>
 int grad_a(const mw_csr_t *M, const double *lam, const double *x, double *grad, hipStream_t s)
 {
@@ -865,6 +907,21 @@ int mw_dot(mw_arith_t a, int32_t n, const double *x, const double *y, double *re
     if (!valid_arith(a) || n < 0 || !result || !workspace || (n > 0 && (!x || !y))) return MW_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     MW_DISPATCH(a, dot_a, n, x, y, result, workspace, s);
+}
+
+int mw_dot_noalloc(mw_arith_t a, int32_t n, const double *x, const double *y, double *result, void *stream)
+{
+    mwh::clear_error();
+    if (!valid_arith(a) || n < 0 || !result || (n > 0 && (!x || !y))) return MW_EINVAL;
+    if (n > MW_DOT_NOALLOC_MAX_N) {
+        set_error("mw_dot_noalloc: n exceeds MW_DOT_NOALLOC_MAX_N (33554432); use mw_dot with a workspace");
+        return MW_EINVAL;
+    }
+    double *slots = nullptr;
+    const int rc = scratch_slots(&slots);
+    if (rc != MW_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    MW_DISPATCH(a, dot_a, n, x, y, result, slots, s);
 }
 
 int mw_spmv(mw_arith_t a, const mw_csr_t *A, const double *x, double *y, void *stream)

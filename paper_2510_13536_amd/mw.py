@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libmwcg.so")
 
 ARITH = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4, "qtwe": 5}
 WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3, "qtwe": 3}
+DOT_NOALLOC_MAX_N = 33554432  # MW_DOT_NOALLOC_MAX_N in include/mw.h
 OPS = {"add": 0, "mul": 1, "dxmul": 2, "div": 3, "norm": 4, "neg": 5, "tofp64": 6}
 STATUS = {0: "ok", 1: "not_converged", 2: "breakdown"}
 MW_EINVAL, MW_EHIP = -1, -2
@@ -126,6 +127,7 @@ def lib():
     L.mw_dot_workspace_bytes.argtypes = [C.c_int, C.c_int32]
     L.mw_dot_workspace_bytes.restype = C.c_size_t
     L.mw_dot.argtypes = [C.c_int, C.c_int32, _vp, _vp, _vp, _vp, _vp]
+    L.mw_dot_noalloc.argtypes = [C.c_int, C.c_int32, _vp, _vp, _vp, _vp]
     L.mw_spmv.argtypes = [C.c_int, C.POINTER(Csr), _vp, _vp, _vp]
     L.mw_spmv_plan_bytes.argtypes = [C.c_int32, C.c_int32]
     L.mw_spmv_plan_bytes.restype = C.c_size_t
@@ -251,6 +253,20 @@ def dot(arith, x, y, out=None, workspace=None):
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
     _check(lib().mw_dot(ARITH[arith], n, _ptr(x), _ptr(y), _ptr(out), _ptr(workspace), _stream()), "mw_dot")
+    return out
+
+
+def dot_noalloc(arith, x, y, out):
+    """x^T y into the caller's (k,) device tensor `out`, with no workspace
+    and no allocation (mw_dot_noalloc; n <= DOT_NOALLOC_MAX_N)."""
+    k = WORDS[arith]
+    x = _vec(x, k, name="x")
+    y = _vec(y, k, x.shape[1], name="y")
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
+            and out.is_contiguous() and out.numel() == k):
+        raise MWError("out must be a contiguous (k,) float64 CUDA tensor")
+    _check(lib().mw_dot_noalloc(ARITH[arith], x.shape[1], _ptr(x), _ptr(y), _ptr(out), _stream()),
+           "mw_dot_noalloc")
     return out
 
 

@@ -97,6 +97,21 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     assert lib.mw_cg_solve(1, None, bogus, bogus, 1e-12, 10, None, bogus, None, None) == -1
 
 
+def test_dot_noalloc_rejections_without_gpu(lib):
+    """The allocation-free dot checks its arguments and its size limit on
+    the host, before any device call."""
+    vp = C.c_void_p
+    lib.mw_dot_noalloc.argtypes = [C.c_int, C.c_int32, vp, vp, vp, vp]
+    lib.mw_last_error.restype = C.c_char_p
+    bogus = vp(0x1000)
+    assert lib.mw_dot_noalloc(6, 10, bogus, bogus, bogus, None) == -1          # arith
+    assert lib.mw_dot_noalloc(4, -1, bogus, bogus, bogus, None) == -1         # n
+    assert lib.mw_dot_noalloc(4, 10, bogus, bogus, None, None) == -1          # result
+    assert lib.mw_dot_noalloc(4, 10, None, bogus, bogus, None) == -1          # x
+    assert lib.mw_dot_noalloc(4, 33554433, bogus, bogus, bogus, None) == -1   # beyond the scratch array
+    assert b"MW_DOT_NOALLOC_MAX_N" in lib.mw_last_error()
+
+
 class Shape(C.Structure):
     _fields_ = [("spmv_grid", C.c_int32), ("update_grid", C.c_int32), ("update_threads", C.c_int32),
                 ("chunk", C.c_int32), ("lanes", C.c_int32), ("us_per_iteration", C.c_double)]
