@@ -2,7 +2,7 @@
  * mwo.c -- CPU oracle for Conjugate Gradient in FP64, double-word (DW),
  * quasi double-word (QDW, pair arithmetic), triple-word (TW) and quasi
  * triple-word (QTW) arithmetic, plus QTWE: QTW with VecSum3 after every
- * operation.
+ * operation, and the quadruple-word formats QW and QQW.
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
  * statement of what the GPU path computes.  Only the test-suite, the smoke
@@ -33,6 +33,9 @@
  *                         QDW the same placement is DW itself, since QDW is
  *                         DW without the closing QuickTwoSum.)
  *   Alg. 1              : the CG iteration.
+ *   Sec. I              : quadruple-word (QW, Hida, Li and Bailey) and quasi
+ *                         quadruple-word (QQW, Ozaki and Imamura) formats,
+ *                         named but not given by the paper (see below).
  *
  * Readings where the paper is silent:
  *   - multi-operand sums inside one fl(...) are evaluated left to right;
@@ -46,7 +49,22 @@
  *     digits, the remainder formed in the arithmetic itself (see mw_div);
  *   - the FP64 residual test uses sqrt(fp64(rho)) / sqrt(fp64(b.b)) where
  *     both dots are carried out in the arithmetic;
- *   - rounding a multi-word value to FP64: fl(x1 + x2), fl(x1 + fl(x2 + x3)).
+ *   - rounding a multi-word value to FP64: fl(x1 + x2), fl(x1 + fl(x2 + x3)),
+ *     fl(x1 + fl(x2 + fl(x3 + x4)));
+ *   - QW: the quad-double algorithms published by Hida, Li and Bailey
+ *     ("Algorithms for quad-double precision floating point arithmetic",
+ *     ARITH 2001): the faster ("sloppy") addition, the multiplication that
+ *     keeps every product term through the third order, and their
+ *     five-component renormalisation.  The FP64 x QW product drops, from
+ *     that multiplication, every operation on the FP64 operand's zero
+ *     lower words that is an exact identity (the rule stated with Alg. 10);
+ *   - QQW: its source is not available.  Read as the construction of QTW
+ *     (Alg. 7, 8, 10) carried one order further: every word but the last
+ *     formed by TwoSum/TwoProdFMA with the errors passed down one word,
+ *     the last word one plain FP64 sum of its order's terms, no
+ *     renormalisation; VecSum4 (three TwoSums from the top down, the
+ *     extension of Alg. 9) normalises r in CG.  Parity with the QQW
+ *     publication is unpinned.
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC.
  * Contraction must stay off: every fused multiply-add below is an explicit
@@ -63,7 +81,12 @@
 #include <omp.h>
 #endif
 
-enum { MWO_FP64 = 0, MWO_DW = 1, MWO_QDW = 2, MWO_TW = 3, MWO_QTW = 4, MWO_QTWE = 5 };
+/* Loops over fewer rows than this run on one thread: every row's result is
+ * the same on any number of threads, and below this size the threads cost
+ * more than they save. */
+#define MWO_PAR_MIN 65536
+
+enum { MWO_FP64 = 0, MWO_DW = 1, MWO_QDW = 2, MWO_TW = 3, MWO_QTW = 4, MWO_QTWE = 5, MWO_QW = 6, MWO_QQW = 7 };
 
 enum {
     MWO_OK = 0,
@@ -141,7 +164,7 @@ static inline void two_prod(double a, double b, double *x, double *y)
  * Multi-word values.  w[0] is the leading word; words beyond the format's
  * width are kept at zero and never read.
  * ---------------------------------------------------------------------- */
-typedef struct { double w[3]; } mwv;
+typedef struct { double w[4]; } mwv;
 
 static int words_of(int a)
 {
@@ -149,14 +172,17 @@ static int words_of(int a)
     case MWO_FP64: return 1;
     case MWO_DW: case MWO_QDW: return 2;
     case MWO_TW: case MWO_QTW: case MWO_QTWE: return 3;
+    case MWO_QW: case MWO_QQW: return 4;
     default: return -1;
     }
 }
 
-static inline mwv mw_make(double a, double b, double c)
+static inline mwv mw_make4(double a, double b, double c, double d)
 {
-    mwv r; r.w[0] = a; r.w[1] = b; r.w[2] = c; return r;
+    mwv r; r.w[0] = a; r.w[1] = b; r.w[2] = c; r.w[3] = d; return r;
 }
+
+static inline mwv mw_make(double a, double b, double c) { return mw_make4(a, b, c, 0.0); }
 
 /* Promotion of an FP64 value: the lower words are zero. */
 static inline mwv mw_promote(double a) { return mw_make(a, 0.0, 0.0); }
@@ -327,6 +353,193 @@ static mwv qtwe_add(mwv a, mwv b) { return vec_sum3(qtw_add(a, b)); }
 static mwv qtwe_mul(mwv a, mwv b) { return vec_sum3(qtw_mul(a, b)); }
 static mwv qtwe_dxmul(double a, mwv b) { return vec_sum3(qtw_dxmul(a, b)); }
 
+/* ---- QW (Hida, Li and Bailey, ARITH 2001) ----------------------------- */
+
+/* Three terms to three: (a, b, c) -> (s, e1, e2) with s + e1 + e2 = a + b + c
+ * exactly, by three TwoSums. */
+static void three_sum(double *a, double *b, double *c)
+{
+    double t1, t2, t3;
+    two_sum(*a, *b, &t1, &t2);
+    two_sum(*c, t1, a, &t3);
+    two_sum(t2, t3, b, c);
+}
+
+/* Three terms to two: the same first two TwoSums, the last pair added in
+ * FP64 (its error is dropped). */
+static void three_sum2(double *a, double *b, double c)
+{
+    double t1, t2, t3;
+    two_sum(*a, *b, &t1, &t2);
+    two_sum(c, t1, a, &t3);
+    *b = f_add(t2, t3);
+}
+
+/* Renormalisation of five overlapping components, largest first, into four
+ * non-overlapping words: QuickTwoSums from the bottom up, then from the top
+ * down, keeping a partial sum as an output word whenever the error it
+ * leaves is nonzero, up to four words. */
+static mwv qw_renorm(double c0, double c1, double c2, double c3, double c4)
+{
+    double t[5], s, e;
+    quick_two_sum(c3, c4, &s, &t[4]);
+    quick_two_sum(c2, s, &s, &t[3]);
+    quick_two_sum(c1, s, &s, &t[2]);
+    quick_two_sum(c0, s, &t[0], &t[1]);
+    double b[4] = { 0.0, 0.0, 0.0, 0.0 };
+    int k = 0;
+    s = t[0];
+    for (int i = 1; i < 5 && k < 4; i++) {
+        quick_two_sum(s, t[i], &s, &e);
+        if (e != 0.0) {
+            b[k++] = s;
+            s = e;
+        }
+    }
+    if (k < 4) b[k] = s;
+    return mw_make4(b[0], b[1], b[2], b[3]);
+}
+
+/* QW addition, the faster of the two published variants: word-wise
+ * TwoSums, the errors carried into the next word with TwoSum / three-term
+ * sums, the last order summed in FP64, then the renormalisation. */
+static mwv qw_add(mwv a, mwv b)
+{
+    double s0, s1, s2, s3, e0, e1, e2, e3;
+    two_sum(a.w[0], b.w[0], &s0, &e0);
+    two_sum(a.w[1], b.w[1], &s1, &e1);
+    two_sum(a.w[2], b.w[2], &s2, &e2);
+    two_sum(a.w[3], b.w[3], &s3, &e3);
+    two_sum(s1, e0, &s1, &e0);
+    three_sum(&s2, &e0, &e1);
+    three_sum2(&s3, &e0, e2);
+    e0 = f_add(f_add(e0, e1), e3);
+    return qw_renorm(s0, s1, s2, s3, e0);
+}
+
+/* QW multiplication: the products of orders 0, 1 and 2 (a_i b_j, i + j <= 2)
+ * by TwoProdFMA, their sums by TwoSums order by order, the order-3 products
+ * and the remaining order-2 errors summed in FP64, then the
+ * renormalisation. */
+static mwv qw_mul(mwv a, mwv b)
+{
+    double p0, p1, p2, p3, p4, p5, q0, q1, q2, q3, q4, q5;
+    double s0, s1, s2, t0, t1;
+    two_prod(a.w[0], b.w[0], &p0, &q0);
+    two_prod(a.w[0], b.w[1], &p1, &q1);
+    two_prod(a.w[1], b.w[0], &p2, &q2);
+    two_prod(a.w[0], b.w[2], &p3, &q3);
+    two_prod(a.w[1], b.w[1], &p4, &q4);
+    two_prod(a.w[2], b.w[0], &p5, &q5);
+    /* order 1: p1, p2 and the error q0 of order 0 */
+    three_sum(&p1, &p2, &q0);
+    /* order 2: (p2, q1, q2) + (p3, p4, p5) */
+    three_sum(&p2, &q1, &q2);
+    three_sum(&p3, &p4, &p5);
+    two_sum(p2, p3, &s0, &t0);
+    two_sum(q1, p4, &s1, &t1);
+    s2 = f_add(q2, p5);
+    two_sum(s1, t0, &s1, &t0);
+    s2 = f_add(s2, f_add(t0, t1));
+    /* order 3 */
+    double o3 = f_mul(a.w[0], b.w[3]);
+    o3 = f_add(o3, f_mul(a.w[1], b.w[2]));
+    o3 = f_add(o3, f_mul(a.w[2], b.w[1]));
+    o3 = f_add(o3, f_mul(a.w[3], b.w[0]));
+    o3 = f_add(o3, q0);
+    o3 = f_add(o3, q3);
+    o3 = f_add(o3, q4);
+    o3 = f_add(o3, q5);
+    s1 = f_add(s1, o3);
+    return qw_renorm(p0, p1, s0, s1, s2);
+}
+
+/* FP64 x QW: qw_mul with a = (a, 0, 0, 0), every operation whose operand is
+ * one of the zero words and whose result is therefore exact dropped (the
+ * rule stated with Alg. 10).  What remains: */
+static mwv qw_dxmul(double a, mwv b)
+{
+    double p0, p1, p3, q0, q1, q3, s0, s1, s2, t0, u;
+    two_prod(a, b.w[0], &p0, &q0);
+    two_prod(a, b.w[1], &p1, &q1);
+    two_prod(a, b.w[2], &p3, &q3);
+    two_sum(q0, p1, &p1, &u);    /* order 1: three_sum(p1, 0, q0) */
+    two_sum(u, q1, &u, &q1);     /* order 2: three_sum(u, q1, 0) */
+    two_sum(u, p3, &s0, &t0);    /* (u, q1, 0) + (p3, 0, 0) */
+    s1 = q1;
+    two_sum(s1, t0, &s1, &t0);
+    s2 = t0;
+    s1 = f_add(s1, f_add(f_mul(a, b.w[3]), q3));
+    return qw_renorm(p0, p1, s0, s1, s2);
+}
+
+/* ---- QQW (reading: Alg. 7, 8, 10 carried one order further) ----------- */
+
+static mwv qqw_add(mwv a, mwv b)
+{
+    double c1, c2, c3, c4, e1, e2, e3, e4, e5, e6;
+    two_sum(a.w[0], b.w[0], &c1, &e1);
+    two_sum(a.w[1], b.w[1], &c2, &e2);
+    two_sum(c2, e1, &c2, &e3);
+    two_sum(a.w[2], b.w[2], &c3, &e4);
+    two_sum(c3, e2, &c3, &e5);
+    two_sum(c3, e3, &c3, &e6);
+    c4 = f_add(f_add(f_add(f_add(a.w[3], b.w[3]), e4), e5), e6);
+    return mw_make4(c1, c2, c3, c4);
+}
+
+static mwv qqw_mul(mwv a, mwv b)
+{
+    double c1, c2, c3, c4, t2, t3, t4, t5, t6;
+    double e1, e2, e3, e4, e5, e6, e7, e8, e9, e10, e11, e12, e13, e14;
+    two_prod(a.w[0], b.w[0], &c1, &e1);
+    /* order 1 */
+    two_prod(a.w[0], b.w[1], &t2, &e2);
+    two_prod(a.w[1], b.w[0], &t3, &e3);
+    two_sum(t2, t3, &c2, &e4);
+    two_sum(c2, e1, &c2, &e5);
+    /* order 2: the products, then the order-1 errors */
+    two_prod(a.w[0], b.w[2], &t4, &e6);
+    two_prod(a.w[1], b.w[1], &t5, &e7);
+    two_prod(a.w[2], b.w[0], &t6, &e8);
+    two_sum(t4, t5, &c3, &e9);
+    two_sum(c3, t6, &c3, &e10);
+    two_sum(c3, e2, &c3, &e11);
+    two_sum(c3, e3, &c3, &e12);
+    two_sum(c3, e4, &c3, &e13);
+    two_sum(c3, e5, &c3, &e14);
+    /* order 3, in FP64: each product takes one error by FMA */
+    c4 = f_add(f_fma(a.w[3], b.w[0], e6), f_fma(a.w[2], b.w[1], e7));
+    c4 = f_add(c4, f_fma(a.w[1], b.w[2], e8));
+    c4 = f_add(c4, f_fma(a.w[0], b.w[3], e9));
+    c4 = f_add(f_add(f_add(f_add(f_add(c4, e10), e11), e12), e13), e14);
+    return mw_make4(c1, c2, c3, c4);
+}
+
+/* FP64 x QQW, the extension of Alg. 10. */
+static mwv qqw_dxmul(double a, mwv b)
+{
+    double c1, c2, c3, c4, e1, e2, e3, e4, e5, e6;
+    two_prod(a, b.w[0], &c1, &e1);
+    two_prod(a, b.w[1], &c2, &e2);
+    two_sum(c2, e1, &c2, &e5);
+    two_prod(a, b.w[2], &c3, &e3);
+    two_sum(c3, e2, &c3, &e4);
+    two_sum(c3, e5, &c3, &e6);
+    c4 = f_add(f_add(f_fma(a, b.w[3], e3), e4), e6);
+    return mw_make4(c1, c2, c3, c4);
+}
+
+/* VecSum4: the four-word extension of Alg. 9, TwoSums from the top down. */
+static mwv vec_sum4(mwv c)
+{
+    double c1 = c.w[0], c2 = c.w[1], c3 = c.w[2], c4 = c.w[3];
+    two_sum(c1, c2, &c1, &c2);
+    two_sum(c2, c3, &c2, &c3);
+    two_sum(c3, c4, &c3, &c4);
+    return mw_make4(c1, c2, c3, c4);
+}
+
 /* ---- Dispatch by arithmetic ------------------------------------------- */
 
 static mwv mw_add(int ar, mwv a, mwv b)
@@ -337,6 +550,8 @@ static mwv mw_add(int ar, mwv a, mwv b)
     case MWO_QDW: return qdw_add(a, b);
     case MWO_TW: return tw_add(a, b);
     case MWO_QTWE: return qtwe_add(a, b);
+    case MWO_QW: return qw_add(a, b);
+    case MWO_QQW: return qqw_add(a, b);
     default: return qtw_add(a, b);
     }
 }
@@ -349,6 +564,8 @@ static mwv mw_mul(int ar, mwv a, mwv b)
     case MWO_QDW: return qdw_mul(a, b);
     case MWO_TW: return tw_mul(a, b);
     case MWO_QTWE: return qtwe_mul(a, b);
+    case MWO_QW: return qw_mul(a, b);
+    case MWO_QQW: return qqw_mul(a, b);
     default: return qtw_mul(a, b);
     }
 }
@@ -361,16 +578,18 @@ static mwv mw_dxmul(int ar, double a, mwv b)
     case MWO_QDW: return qdw_dxmul(a, b);
     case MWO_TW: return tw_dxmul(a, b);
     case MWO_QTWE: return qtwe_dxmul(a, b);
+    case MWO_QW: return qw_dxmul(a, b);
+    case MWO_QQW: return qqw_dxmul(a, b);
     default: return qtw_dxmul(a, b);
     }
 }
 
 /* Negation flips the sign of every word; it is exact. */
-static mwv mw_neg(mwv a) { return mw_make(-a.w[0], -a.w[1], -a.w[2]); }
+static mwv mw_neg(mwv a) { return mw_make4(-a.w[0], -a.w[1], -a.w[2], -a.w[3]); }
 
 /* The normalisation each format uses: QuickTwoSum for the two-word types,
  * VecSum3 for QTW and QTWE (Sec. III / IV-D), the full renormalisation for
- * TW. */
+ * TW and QW, VecSum4 for QQW. */
 static mwv mw_normalise(int ar, mwv a)
 {
     double x, y;
@@ -380,6 +599,8 @@ static mwv mw_normalise(int ar, mwv a)
         quick_two_sum(a.w[0], a.w[1], &x, &y);
         return mw_make(x, y, 0.0);
     case MWO_TW: return tw_renorm(a);
+    case MWO_QW: return qw_renorm(a.w[0], a.w[1], a.w[2], a.w[3], 0.0);
+    case MWO_QQW: return vec_sum4(a);
     default: return vec_sum3(a);
     }
 }
@@ -390,15 +611,17 @@ static double mw_to_fp64(int ar, mwv a)
     switch (words_of(ar)) {
     case 1: return a.w[0];
     case 2: return f_add(a.w[0], a.w[1]);
-    default: return f_add(a.w[0], f_add(a.w[1], a.w[2]));
+    case 3: return f_add(a.w[0], f_add(a.w[1], a.w[2]));
+    default: return f_add(a.w[0], f_add(a.w[1], f_add(a.w[2], a.w[3])));
     }
 }
 
 /* Division a / b (needed by CG for alpha and beta; the paper gives no
  * algorithm).  Long division with FP64 quotient digits:
  *   q1 = fl(a1 / b1);  r = normalise(a - q1*b);  q2 = fl(r1 / b1);
- *   three words only: r = normalise(r - q2*b);  q3 = fl(r1 / b1);
- *   result = normalise(q1, q2[, q3]).
+ *   three and four words: r = normalise(r - q2*b);  q3 = fl(r1 / b1);
+ *   four words: r = normalise(r - q3*b);  q4 = fl(r1 / b1);
+ *   result = normalise(q1, q2[, q3[, q4]]).
  * The products q*b are FP64 x multi-word products and the subtractions are
  * additions of the negated product, all in the arithmetic itself. */
 static mwv mw_div(int ar, mwv a, mwv b)
@@ -411,7 +634,10 @@ static mwv mw_div(int ar, mwv a, mwv b)
     if (k == 2) return mw_normalise(ar, mw_make(q1, q2, 0.0));
     r = mw_normalise(ar, mw_add(ar, r, mw_neg(mw_dxmul(ar, q2, b))));
     double q3 = f_div(r.w[0], b.w[0]);
-    return mw_normalise(ar, mw_make(q1, q2, q3));
+    if (k == 3) return mw_normalise(ar, mw_make(q1, q2, q3));
+    r = mw_normalise(ar, mw_add(ar, r, mw_neg(mw_dxmul(ar, q3, b))));
+    double q4 = f_div(r.w[0], b.w[0]);
+    return mw_normalise(ar, mw_make4(q1, q2, q3, q4));
 }
 
 /* ------------------------------------------------------------------------
@@ -507,7 +733,7 @@ static void spmv_rows(int ar, long n, const int32_t *row_ptr, const int32_t *col
                       const double *val, const double *x, double *y)
 {
     int k = words_of(ar);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= MWO_PAR_MIN)
     for (long i = 0; i < n; i++) {
         if (ar == MWO_FP64) {
             double acc = 0.0;
@@ -561,8 +787,8 @@ int mwo_axpy(int arith, long n, const double *alpha, const double *x, double *y)
 {
     int k = words_of(arith);
     if (k < 0 || n < 0) return MWO_EINVAL;
-    mwv al = mw_make(alpha[0], k > 1 ? alpha[1] : 0.0, k > 2 ? alpha[2] : 0.0);
-#pragma omp parallel for schedule(static)
+    mwv al = mw_make4(alpha[0], k > 1 ? alpha[1] : 0.0, k > 2 ? alpha[2] : 0.0, k > 3 ? alpha[3] : 0.0);
+#pragma omp parallel for schedule(static) if (n >= MWO_PAR_MIN)
     for (long i = 0; i < n; i++) {
         if (arith == MWO_FP64) y[i] = f_fma(al.w[0], x[i], y[i]);
         else mw_store(k, y, n, i, mw_add(arith, mw_load(k, y, n, i), mw_mul(arith, al, mw_load(k, x, n, i))));
@@ -588,7 +814,7 @@ typedef struct {
  *     q = A p;  sigma = p^T q;  (sigma <= 0 or not finite: breakdown)
  *     alpha = rho / sigma
  *     x = x + alpha p;  r = r + (-(alpha q))
- *     QDW/QTW: r = normalise(r) when normalise_r = K > 0 and the iteration
+ *     QDW/QTW/QQW: r = normalise(r) when normalise_r = K > 0 and the iteration
  *       number (1, 2, ...) is a multiple of K; K = 1, every iteration, is
  *       Sec. IV-D; K = 0 never (the "-NN" variants of Sec. V-B); other K
  *       explore the frequency the paper leaves open (Sec. VI)
@@ -605,7 +831,7 @@ int mwo_cg_solve(int arith, long n, const int32_t *row_ptr, const int32_t *col,
 {
     int k = words_of(arith);
     if (k < 0 || n <= 0 || !(tol >= 0.0) || maxit < 0 || !info) return MWO_EINVAL;
-    int quasi = (arith == MWO_QDW || arith == MWO_QTW);
+    int quasi = (arith == MWO_QDW || arith == MWO_QTW || arith == MWO_QQW);
     double *r = calloc((size_t)k * n, sizeof(double));
     double *p = calloc((size_t)k * n, sizeof(double));
     double *q = calloc((size_t)k * n, sizeof(double));
@@ -620,7 +846,7 @@ int mwo_cg_solve(int arith, long n, const int32_t *row_ptr, const int32_t *col,
 
     /* r = b - A x */
     spmv_rows(arith, n, row_ptr, col, val, x, q);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= MWO_PAR_MIN)
     for (long i = 0; i < n; i++) {
         if (arith == MWO_FP64) r[i] = f_sub(b[i], q[i]);
         else mw_store(k, r, n, i, mw_add(arith, mw_promote(b[i]), mw_neg(mw_load(k, q, n, i))));
@@ -641,7 +867,7 @@ int mwo_cg_solve(int arith, long n, const int32_t *row_ptr, const int32_t *col,
         if (!(s64 > 0.0) || !isfinite(s64)) { status = MWO_BREAKDOWN; break; }
         mwv alpha = mw_div(arith, rho, sigma);
         if (!isfinite(mw_to_fp64(arith, alpha))) { status = MWO_BREAKDOWN; break; }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= MWO_PAR_MIN)
         for (long i = 0; i < n; i++) {
             if (arith == MWO_FP64) {
                 x[i] = f_fma(alpha.w[0], p[i], x[i]);
@@ -663,7 +889,7 @@ int mwo_cg_solve(int arith, long n, const int32_t *row_ptr, const int32_t *col,
         if (info->rel_res < tol) break;
         if (info->iters >= maxit) { status = MWO_NOT_CONVERGED; break; }
         mwv beta = mw_div(arith, rho_new, rho);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= MWO_PAR_MIN)
         for (long i = 0; i < n; i++) {
             if (arith == MWO_FP64) p[i] = f_fma(beta.w[0], p[i], r[i]);
             else mw_store(k, p, n, i, mw_add(arith, mw_load(k, r, n, i), mw_mul(arith, beta, mw_load(k, p, n, i))));
@@ -692,7 +918,7 @@ done:
  *   loop:
  *     q = A p;  sigma = p^T q;  (sigma <= 0 or not finite: breakdown)
  *     alpha = rho / sigma
- *     x = x + alpha p;  r = r + (-(alpha q));  QDW/QTW: r = normalise(r)
+ *     x = x + alpha p;  r = r + (-(alpha q));  QDW/QTW/QQW: r = normalise(r)
  *       as in mwo_cg_solve (normalise_r = K)
  *     z = D r;  rho' = r^T z;  rr = r^T r;  iters++
  *     sqrt(fp64(rr)) / nb < tol: converged
@@ -714,7 +940,7 @@ int mwo_pcg_jacobi_solve(int arith, long n, const int32_t *row_ptr, const int32_
 {
     int k = words_of(arith);
     if (k < 0 || n <= 0 || !(tol >= 0.0) || maxit < 0 || !info) return MWO_EINVAL;
-    int quasi = (arith == MWO_QDW || arith == MWO_QTW);
+    int quasi = (arith == MWO_QDW || arith == MWO_QTW || arith == MWO_QQW);
     double *r = calloc((size_t)k * n, sizeof(double));
     double *z = calloc((size_t)k * n, sizeof(double));
     double *p = calloc((size_t)k * n, sizeof(double));
@@ -739,7 +965,7 @@ int mwo_pcg_jacobi_solve(int arith, long n, const int32_t *row_ptr, const int32_
     info->seconds = 0.0;
 
     spmv_rows(arith, n, row_ptr, col, val, x, q);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= MWO_PAR_MIN)
     for (long i = 0; i < n; i++) {
         mwv ri;
         if (arith == MWO_FP64) ri = mw_promote(f_sub(b[i], q[i]));
@@ -764,7 +990,7 @@ int mwo_pcg_jacobi_solve(int arith, long n, const int32_t *row_ptr, const int32_
         if (!(s64 > 0.0) || !isfinite(s64)) { status = MWO_BREAKDOWN; break; }
         mwv alpha = mw_div(arith, rho, sigma);
         if (!isfinite(mw_to_fp64(arith, alpha))) { status = MWO_BREAKDOWN; break; }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= MWO_PAR_MIN)
         for (long i = 0; i < n; i++) {
             mwv ri;
             if (arith == MWO_FP64) {
@@ -788,7 +1014,7 @@ int mwo_pcg_jacobi_solve(int arith, long n, const int32_t *row_ptr, const int32_
         if (info->rel_res < tol) break;
         if (info->iters >= maxit) { status = MWO_NOT_CONVERGED; break; }
         mwv beta = mw_div(arith, rho_new, rho);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= MWO_PAR_MIN)
         for (long i = 0; i < n; i++) {
             if (arith == MWO_FP64) p[i] = f_fma(beta.w[0], p[i], z[i]);
             else mw_store(k, p, n, i, mw_add(arith, mw_load(k, z, n, i), mw_mul(arith, beta, mw_load(k, p, n, i))));
@@ -936,7 +1162,7 @@ int mwo_spmv_error(int arith, long n, const int32_t *row_ptr, const int32_t *col
 {
     int k = words_of(arith);
     if (k < 0 || n < 0 || nrows < 0) return MWO_EINVAL;
-#pragma omp parallel for schedule(dynamic, 64)
+#pragma omp parallel for schedule(dynamic, 64) if (nrows >= MWO_PAR_MIN)
     for (long t = 0; t < nrows; t++) {
         long i = rows[t];
         kacc acc;
@@ -962,7 +1188,7 @@ int mwo_true_residual(int arith, long n, const int32_t *row_ptr, const int32_t *
     int k = words_of(arith);
     if (k < 0 || n < 0) return MWO_EINVAL;
     double s = 0.0;
-#pragma omp parallel for schedule(static) reduction(+ : s)
+#pragma omp parallel for schedule(static) reduction(+ : s) if (n >= MWO_PAR_MIN)
     for (long i = 0; i < n; i++) {
         kacc acc;
         k_clear(&acc);

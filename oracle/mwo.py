@@ -14,8 +14,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-ARITH = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4, "qtwe": 5}
-WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3, "qtwe": 3}
+ARITH = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4, "qtwe": 5, "qw": 6, "qqw": 7}
+WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3, "qtwe": 3, "qw": 4, "qqw": 4}
 OPS = {"add": 0, "mul": 1, "dxmul": 2, "div": 3, "norm": 4, "neg": 5, "tofp64": 6}
 STATUS = {0: "ok", 1: "not_converged", 2: "breakdown", -1: "einval"}
 

@@ -15,7 +15,7 @@ import oracle as O
 from conftest import U, rand_mw
 from paper_2510_13536_amd import problems as P
 
-ARITHS = ["fp64", "dw", "qdw", "tw", "qtw", "qtwe"]
+ARITHS = ["fp64", "dw", "qdw", "tw", "qtw", "qtwe", "qw", "qqw"]
 
 
 def test_exact_sum_matches_fraction(rng):

@@ -18,8 +18,8 @@ import scipy.sparse as sp
 import oracle as O
 from paper_2510_13536_amd import problems as P
 
-ARITHS = ["fp64", "dw", "qdw", "tw", "qtw", "qtwe"]
-MW = ["dw", "qdw", "tw", "qtw", "qtwe"]
+ARITHS = ["fp64", "dw", "qdw", "tw", "qtw", "qtwe", "qw", "qqw"]
+MW = ["dw", "qdw", "tw", "qtw", "qtwe", "qw", "qqw"]
 
 
 def rel_error(x, xstar):
@@ -51,15 +51,17 @@ def test_manufactured_integer_solution(arith):
     A = P.poisson2d(24, 20)
     xstar = P.integer_vector(A.n, seed=3)
     b = (A.to_scipy().astype(np.int64) @ xstar.astype(np.int64)).astype(np.float64)
-    tol = {"fp64": 1e-14, "dw": 1e-28, "qdw": 1e-28, "tw": 1e-40, "qtw": 1e-40, "qtwe": 1e-40}[arith]
+    tol = {"fp64": 1e-14, "dw": 1e-28, "qdw": 1e-28, "tw": 1e-40, "qtw": 1e-40, "qtwe": 1e-40,
+           "qw": 1e-55, "qqw": 1e-55}[arith]
     x, info = O.cg_solve(arith, A, b, tol=tol)
     assert info["status"] == "ok", info
     err = rel_error(x, xstar)
-    limit = {"fp64": 1e-12, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-37, "qtwe": 1e-38}[arith]
+    limit = {"fp64": 1e-12, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-37, "qtwe": 1e-38,
+             "qw": 1e-53, "qqw": 1e-53}[arith]
     assert err < limit, err
     # the true residual, formed exactly, agrees with the recursive one's scale
     tr = O.true_residual(arith, A, b, x) / np.linalg.norm(b)
-    assert tr < 100 * max(info["rel_res"], 1e-16 if arith == "fp64" else 1e-40)
+    assert tr < 100 * max(info["rel_res"], 1e-16 if arith == "fp64" else 1e-55)
 
 
 @pytest.mark.parametrize("arith", ARITHS)
@@ -318,7 +320,8 @@ def test_pcg_jacobi_diagonal_matrix(arith):
     d = rng.uniform(0.3, 7.0, 500)
     M = P.CSR.from_scipy(sp.diags(d, 0).tocsr())
     b = rng.uniform(-1, 1, 500)
-    tol = {"fp64": 1e-12, "dw": 1e-28, "qdw": 1e-28, "tw": 1e-40, "qtw": 1e-40, "qtwe": 1e-40}[arith]
+    tol = {"fp64": 1e-12, "dw": 1e-28, "qdw": 1e-28, "tw": 1e-40, "qtw": 1e-40, "qtwe": 1e-40,
+           "qw": 1e-55, "qqw": 1e-55}[arith]
     x, info = O.cg_solve(arith, M, b, tol=tol, precond="jacobi")
     assert info["status"] == "ok" and info["iters"] <= O.WORDS[arith]
     _, plain = O.cg_solve(arith, M, b, tol=tol)

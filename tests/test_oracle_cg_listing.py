@@ -32,8 +32,8 @@ import oracle as O
 from paper_2510_13536_amd import problems as P
 from test_oracle_listing import IMPL, div as mw_div, fma
 
-ARITHS = ["fp64", "dw", "qdw", "tw", "qtw", "qtwe"]
-QUASI = ("qdw", "qtw")
+ARITHS = ["fp64", "dw", "qdw", "tw", "qtw", "qtwe", "qw", "qqw"]
+QUASI = ("qdw", "qtw", "qqw")
 
 
 class Ops:
@@ -74,7 +74,9 @@ class Ops:
             return a[0]
         if self.k == 2:
             return a[0] + a[1]
-        return a[0] + (a[1] + a[2])
+        if self.k == 3:
+            return a[0] + (a[1] + a[2])
+        return a[0] + (a[1] + (a[2] + a[3]))
 
     # y + alpha * x with the FP64 solver's single fma
     def axpy(self, alpha, x, y):

@@ -1,6 +1,6 @@
 """The oracle's C source under AddressSanitizer and UndefinedBehaviorSanitizer
 (CPU only): a small driver calls every entry point on a 2D Poisson matrix,
-a matrix with empty rows and random multi-word vectors, in all six
+a matrix with empty rows and random multi-word vectors, in all eight
 arithmetics; any out-of-bounds access, leak or undefined operation fails the
 run.  The same source, unsanitised and with OpenMP, is what the other
 oracle tests load."""
@@ -56,20 +56,20 @@ int main(void)
     double va2[9] = {1, 2, 3, 4, 5, 6, 7, 8, 9};
     unsigned seed = 7;
     int bad = 0;
-    for (int a = 0; a < 6; ++a) {
-        const int k = a == 0 ? 1 : (a < 3 ? 2 : 3);
-        double *u = malloc(sizeof(double) * 3 * n), *v = malloc(sizeof(double) * 3 * n);
-        double *w = malloc(sizeof(double) * 3 * n), *y = malloc(sizeof(double) * 3 * n);
-        double *b = malloc(sizeof(double) * n), *x = calloc(3 * n, sizeof(double)), *hist = malloc(sizeof(double) * 400);
-        for (int i = 0; i < 3 * n; ++i) { u[i] = rnd(&seed) * (i < n ? 1.0 : 1e-17); v[i] = rnd(&seed) * (i < n ? 1.0 : 1e-17) + (i < n ? 3.0 : 0.0); }
+    for (int a = 0; a < 8; ++a) {
+        const int k = a == 0 ? 1 : (a < 3 ? 2 : (a < 6 ? 3 : 4));
+        double *u = malloc(sizeof(double) * 4 * n), *v = malloc(sizeof(double) * 4 * n);
+        double *w = malloc(sizeof(double) * 4 * n), *y = malloc(sizeof(double) * 4 * n);
+        double *b = malloc(sizeof(double) * n), *x = calloc(4 * n, sizeof(double)), *hist = malloc(sizeof(double) * 400);
+        for (int i = 0; i < 4 * n; ++i) { u[i] = rnd(&seed) * (i < n ? 1.0 : 1e-17); v[i] = rnd(&seed) * (i < n ? 1.0 : 1e-17) + (i < n ? 3.0 : 0.0); }
         for (int i = 0; i < n; ++i) b[i] = rnd(&seed);
         for (int op = 0; op <= 6; ++op) bad |= mwo_elementwise(a, op, n, u, v, w) != 0;
         bad |= mwo_spmv(a, n, rp, ci, va, u, y) != 0;
         bad |= mwo_spmv(a, 10, rp2, ci2, va2, u, y) != 0;
-        double res[3], ae, sc;
+        double res[4], ae, sc;
         bad |= mwo_dot(a, n, u, v, res) != 0;
         bad |= mwo_dot_error(a, n, u, v, res, &ae, &sc) != 0;
-        double alpha[3] = {0.5, 1e-17, 1e-34};
+        double alpha[4] = {0.5, 1e-17, 1e-34, 1e-51};
         bad |= mwo_axpy(a, n, alpha, u, w) != 0;
         int64_t rows[4] = {0, 5, 40, n - 1};
         double errs[4], scs[4];
@@ -80,9 +80,9 @@ int main(void)
         bad |= mwo_cg_solve(a, n, rp, ci, va, b, x, 1e-12, 400, 1, &info, hist) != 0;
         double tr;
         bad |= mwo_true_residual(a, n, rp, ci, va, b, x, &tr) != 0 || !(tr < 1e-9);
-        for (int i = 0; i < 3 * n; ++i) x[i] = 0.0;
+        for (int i = 0; i < 4 * n; ++i) x[i] = 0.0;
         bad |= mwo_pcg_jacobi_solve(a, n, rp, ci, va, b, x, 1e-12, 400, 1, &info, hist) != 0;
-        for (int i = 0; i < 3 * n; ++i) x[i] = 0.0;
+        for (int i = 0; i < 4 * n; ++i) x[i] = 0.0;
         bad |= mwo_cg_solve(a, n, rp, ci, va, b, x, 0.0, 3, 0, &info, NULL) != 1;   /* maxit, no normalisation */
         free(u); free(v); free(w); free(y); free(b); free(x); free(hist);
         (void)k;
@@ -106,7 +106,9 @@ def test_oracle_runs_clean_under_asan_and_ubsan(tmp_path):
            os.path.join(ROOT, "oracle", "mwo.c"), str(drv), "-lm"]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-3000:]
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
-    env.pop("LD_PRELOAD", None)
+    # verify_asan_link_order=0: the sanitiser runtime need not be the first
+    # library loaded (an environment may preload another one)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300, env=env)
     assert r.returncode == 0 and r.stdout.strip() == "OK", (r.stdout[-2000:], r.stderr[-3000:])
