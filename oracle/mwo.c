@@ -33,6 +33,9 @@
  *                         QDW the same placement is DW itself, since QDW is
  *                         DW without the closing QuickTwoSum.)
  *   Alg. 1              : the CG iteration.
+ *   Sec. VI             : mixed precision (future work): FP64 vectors with
+ *                         the SpMV rows and the dots accumulated in a
+ *                         multi-word arithmetic (mwo_cg_mixed_solve).
  *   Sec. I              : quadruple-word (QW, Hida, Li and Bailey) and quasi
  *                         quadruple-word (QQW, Ozaki and Imamura) formats,
  *                         named but not given by the paper (see below).
@@ -1024,6 +1027,100 @@ int mwo_pcg_jacobi_solve(int arith, long n, const int32_t *row_ptr, const int32_
 done:
     info->status = status;
     free(r); free(z); free(p); free(q); free(bw); free(d);
+    return status;
+}
+
+/* ------------------------------------------------------------------------
+ * Exported: mixed-precision CG (Sec. VI names mixed precision as future
+ * work; its algorithm is not in the paper)
+ * ---------------------------------------------------------------------- */
+/*
+ * Reading: multi-word arithmetic only where values are accumulated.  x, r,
+ * p and q are FP64 vectors.  Each SpMV row is accumulated from zero in CSR
+ * order in the arithmetic, acc = acc + a_ij * x_j with x_j promoted (so each
+ * product is exact), and rounded once to FP64.  Each dot accumulates the
+ * exact products of its FP64 entries in the arithmetic and stays
+ * multi-word; alpha and beta are the arithmetic's quotients of those dots,
+ * rounded to FP64 for the vector updates, which are FP64 fmas.
+ *   q = A x;  r = fl(b - q);  p = r;  rho = r^T r;  nb = sqrt(fp64(b^T b))
+ *   rho == 0: return, 0 iterations.
+ *   loop:
+ *     q = A p;  sigma = p^T q;  (sigma <= 0 or not finite: breakdown)
+ *     alpha = rho / sigma;  a = fp64(alpha)
+ *     x = fma(a, p, x);  r = fma(-a, q, r);  rho' = r^T r;  iters++
+ *     sqrt(fp64(rho')) / nb < tol: converged;  iters == maxit: not converged
+ *     beta = rho' / rho;  p = fma(fp64(beta), p, r);  rho = rho'
+ * x: one FP64 plane.  The arithmetic must have two or more words.
+ */
+static void spmv_mixed(int ar, long n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                       const double *x, double *y)
+{
+#pragma omp parallel for schedule(static) if (n >= MWO_PAR_MIN)
+    for (long i = 0; i < n; i++) {
+        mwv acc = mw_make(0.0, 0.0, 0.0);
+        for (long p = row_ptr[i]; p < row_ptr[i + 1]; p++)
+            acc = mw_add(ar, acc, mw_dxmul(ar, val[p], mw_promote(x[col[p]])));
+        y[i] = mw_to_fp64(ar, acc);
+    }
+}
+
+static mwv dot_mixed(int ar, long n, const double *x, const double *y)
+{
+    mwv acc = mw_make(0.0, 0.0, 0.0);
+    for (long i = 0; i < n; i++) acc = mw_add(ar, acc, mw_mul(ar, mw_promote(x[i]), mw_promote(y[i])));
+    return acc;
+}
+
+int mwo_cg_mixed_solve(int arith, long n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                       const double *b, double *x, double tol, int32_t maxit, mwo_cg_info *info, double *hist)
+{
+    if (words_of(arith) < 2 || n <= 0 || !(tol >= 0.0) || maxit < 0 || !info) return MWO_EINVAL;
+    double *r = calloc((size_t)n, sizeof(double));
+    double *p = calloc((size_t)n, sizeof(double));
+    double *q = calloc((size_t)n, sizeof(double));
+    if (!r || !p || !q) { free(r); free(p); free(q); return MWO_EINVAL; }
+    info->iters = 0;
+    info->status = MWO_OK;
+    info->rel_res = 0.0;
+    info->seconds = 0.0;
+
+    spmv_mixed(arith, n, row_ptr, col, val, x, q);
+    for (long i = 0; i < n; i++) r[i] = f_sub(b[i], q[i]);
+    memcpy(p, r, sizeof(double) * n);
+    mwv rho = dot_mixed(arith, n, r, r);
+    double nb = sqrt(mw_to_fp64(arith, dot_mixed(arith, n, b, b)));
+    int status = MWO_OK;
+
+    if (mw_to_fp64(arith, rho) == 0.0) goto done;
+    info->rel_res = sqrt(mw_to_fp64(arith, rho)) / nb;
+    if (maxit == 0) { status = MWO_NOT_CONVERGED; goto done; }
+
+    for (;;) {
+        spmv_mixed(arith, n, row_ptr, col, val, p, q);
+        mwv sigma = dot_mixed(arith, n, p, q);
+        double s64 = mw_to_fp64(arith, sigma);
+        if (!(s64 > 0.0) || !isfinite(s64)) { status = MWO_BREAKDOWN; break; }
+        double a = mw_to_fp64(arith, mw_div(arith, rho, sigma));
+        if (!isfinite(a)) { status = MWO_BREAKDOWN; break; }
+        for (long i = 0; i < n; i++) {
+            x[i] = f_fma(a, p[i], x[i]);
+            r[i] = f_fma(-a, q[i], r[i]);
+        }
+        mwv rho_new = dot_mixed(arith, n, r, r);
+        info->iters++;
+        double rr = mw_to_fp64(arith, rho_new);
+        if (!isfinite(rr)) { status = MWO_BREAKDOWN; break; }
+        info->rel_res = sqrt(rr) / nb;
+        if (hist && info->iters <= maxit) hist[info->iters - 1] = info->rel_res;
+        if (info->rel_res < tol) break;
+        if (info->iters >= maxit) { status = MWO_NOT_CONVERGED; break; }
+        double be = mw_to_fp64(arith, mw_div(arith, rho_new, rho));
+        for (long i = 0; i < n; i++) p[i] = f_fma(be, p[i], r[i]);
+        rho = rho_new;
+    }
+done:
+    info->status = status;
+    free(r); free(p); free(q);
     return status;
 }
 
