@@ -22,7 +22,9 @@
  *   Vectors:  a k-word vector of length n is stored as k "word planes":
  *             k consecutive arrays of n doubles, plane 0 the leading word
  *             (element i of plane w at offset w*n + i).  k = mw_words(a).
- *   Scalars:  a k-word scalar is k consecutive doubles in device memory.
+ *   Scalars:  a scalar is mw_scalar_words(a) consecutive doubles in device
+ *             memory (= k, except for the mixed types, whose scalars are
+ *             multi-word while their vectors are FP64).
  *   CSR:      row_ptr[n+1] (row_ptr[0] = 0, nondecreasing, row_ptr[n] =
  *             nnz), col_idx[nnz] in [0, n) and ascending within each row,
  *             val[nnz] FP64; all int32.  Symmetric matrices are stored in
@@ -53,14 +55,28 @@ extern "C" {
  * and QTWE: QTW with VecSum3 (Alg. 9) after every operation, the
  * every-operation end of the normalisation placement Sec. IV-D and VI leave
  * open (3 words; r gets no extra normalisation; the QDW counterpart of this
- * placement is DW itself). */
+ * placement is DW itself).  The quadruple-word formats the paper names in
+ * Sec. I without giving their algorithms: QW (4 words; the quad-double
+ * algorithms of Hida, Li and Bailey) and QQW (4 words; read as Alg. 7, 8,
+ * 10 carried one order further, with VecSum4 normalising r in CG like the
+ * other quasi types).  Mixed precision (future work in Sec. VI): MW_MXDW and
+ * MW_MXQTW keep every vector in FP64 (one plane) and accumulate SpMV rows
+ * (each rounded once to FP64) and dots (kept multi-word) in DW / QTW;
+ * alpha and beta are DW / QTW quotients rounded to FP64 for FP64 fma
+ * updates.  Their scalars (dot results, alpha arguments) have
+ * mw_scalar_words() words; mw_elementwise, mw_csr_grad and the batched
+ * solver reject them, and mw_cg_solve takes no preconditioner with them. */
 typedef enum {
     MW_FP64 = 0,
     MW_DW = 1,
     MW_QDW = 2,
     MW_TW = 3,
     MW_QTW = 4,
-    MW_QTWE = 5
+    MW_QTWE = 5,
+    MW_QW = 6,
+    MW_QQW = 7,
+    MW_MXDW = 8,
+    MW_MXQTW = 9
 } mw_arith_t;
 
 /* Return codes. */
@@ -222,8 +238,13 @@ typedef struct {
                            shape->chunk.  Invalid values: MW_EINVAL.       */
 } mw_cg_opts_t;
 
-/* Number of FP64 words of an arithmetic: 1, 2, 2, 3, 3; -1 if unknown. */
+/* Number of FP64 words (planes) of a vector element of an arithmetic:
+ * 1, 2, 2, 3, 3, 3, 4, 4 and 1 for the mixed types; -1 if unknown. */
 int mw_words(mw_arith_t a);
+
+/* Words of a scalar of arithmetic a (a dot result, an axpy alpha): mw_words
+ * for all but the mixed types (MW_MXDW: 2, MW_MXQTW: 3); < 0 if invalid. */
+int mw_scalar_words(mw_arith_t a);
 
 /* Static text for a return code. */
 const char *mw_status_string(int code);
@@ -252,8 +273,9 @@ int mw_elementwise(mw_arith_t a, int op, int32_t n, const double *u, const doubl
                    double *w, void *stream);
 
 /*
- * y = y + alpha * x (AXPY, Sec. IV-B; the x and r updates of Alg. 1).  alpha: one k-word
- * scalar in device memory; x, y: k planes of n.  FP64: y = fma(alpha, x, y);
+ * y = y + alpha * x (AXPY, Sec. IV-B; the x and r updates of Alg. 1).  alpha: one
+ * scalar (mw_scalar_words(a) words) in device memory; x, y: k planes of n.
+ * FP64: y = fma(alpha, x, y); mixed types: y = fma(fp64(alpha), x, y);
  * otherwise y = add(y, mul(alpha, x)).  Bit-identical to the definition.
  * Asynchronous.
  */
@@ -265,7 +287,9 @@ size_t mw_dot_workspace_bytes(mw_arith_t a, int32_t n);
 
 /*
  * result = x^T y (DOT, Sec. IV-B; p^T q and r^T r in Alg. 1).  x, y: k planes of
- * n; result: one k-word scalar in device memory.  Products mul(x_i, y_i)
+ * n; result: one scalar (mw_scalar_words(a) words) in device memory; the
+ * mixed types sum the exact products of their FP64 entries in DW / QTW.
+ * Products mul(x_i, y_i)
  * are summed with the arithmetic's add in a fixed, run-to-run reproducible
  * order: sequentially over a few elements per thread, then pairwise trees
  * across the wavefront, the workgroup and the workgroup partials.  This
@@ -286,7 +310,7 @@ int mw_dot(mw_arith_t a, int32_t n, const double *x, const double *y, double *re
  * harnesses that forbid hipMalloc).  Same arguments, kernels and summation
  * order as mw_dot, so the result is bit-identical to mw_dot's.  The
  * per-workgroup partial sums live in a static device array of the library
- * (384 KiB per GPU, held until the process ends); the library allocates
+ * (512 KiB per GPU, held until the process ends); the library allocates
  * nothing.  n in [0, MW_DOT_NOALLOC_MAX_N]; a larger n returns MW_EINVAL
  * (mw_last_error says why).  Calls that overlap on one GPU (several
  * streams, threads or processes' graphs at once) share that array and race:
@@ -301,7 +325,8 @@ int mw_dot_noalloc(mw_arith_t a, int32_t n, const double *x, const double *y, do
  * of A->n (must not alias).  Each row is accumulated from zero in CSR order,
  * acc = add(acc, a_ij * x_j) with an FP64 x multi-word product (FP64:
  * acc = fma(a_ij, x_j, acc)), so every row is bit-identical to that
- * sequential definition.  No workspace.  Asynchronous.
+ * sequential definition; the mixed types accumulate in DW / QTW and round
+ * each row once to FP64.  No workspace.  Asynchronous.
  */
 int mw_spmv(mw_arith_t a, const mw_csr_t *A, const double *x, double *y, void *stream);
 

@@ -1,6 +1,6 @@
 // mw_arith.hpp -- device-side multi-word arithmetic for gfx950.
 //
-// Values of the six arithmetics (the paper's five and QTWE) are register
+// Values of the eight arithmetics (the paper's five, QTWE, QW, QQW) are register
 // tuples Num<A> of K = words(A) FP64 words, w[0] the leading one.  Every
 // operation below is one IEEE binary64 instruction with round-to-nearest-
 // even (v_add_f64, v_mul_f64, v_fma_f64); contraction is disabled for this
@@ -19,8 +19,16 @@
 // operation, the other end of the placement question Sec. IV-D and VI leave
 // open (the QDW counterpart is DW itself).  QTWE is not a "quasi" type for
 // the solver: r gets no extra normalisation.
-// On the GPU the branch of VecSumErrBranch is resolved with selects, so a
-// wavefront never diverges on it.
+// QW (quadruple-word, named in Sec. I) follows the quad-double algorithms
+// of Hida, Li and Bailey (ARITH 2001): the faster addition, the
+// multiplication through third-order terms, their five-component
+// renormalisation; FP64 x QW is that multiplication with the FP64
+// operand's zero words, the exact identities dropped.  QQW (quasi
+// quadruple-word, also named in Sec. I; its source is not available here)
+// is read as the construction of QTW (Alg. 7, 8, 10) carried one order
+// further, normalised by VecSum4 (Alg. 9 extended to four words).
+// On the GPU the branches of VecSumErrBranch and of the QW renormalisation
+// are resolved with selects, so a wavefront never diverges on them.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,14 +37,28 @@
 
 namespace mwk {
 
-enum Arith : int { FP64 = 0, DW = 1, QDW = 2, TW = 3, QTW = 4, QTWE = 5 };
+enum Arith : int { FP64 = 0, DW = 1, QDW = 2, TW = 3, QTW = 4, QTWE = 5, QW = 6, QQW = 7, MXDW = 8, MXQTW = 9 };
 
+// Mixed precision (future work in Sec. VI): MXDW / MXQTW keep vectors in
+// FP64 and accumulate SpMV rows and dots in DW / QTW.  base() is the
+// multi-word arithmetic an arithmetic computes in (the accumulator's, for
+// the mixed ones).
+__host__ __device__ constexpr bool is_mixed(int a) { return a == MXDW || a == MXQTW; }
+__host__ __device__ constexpr int base(int a) { return a == MXDW ? DW : (a == MXQTW ? QTW : a); }
+
+// Words of a value (a register tuple, a scalar such as alpha or a dot).
 __host__ __device__ constexpr int words(int a)
 {
-    return a == FP64 ? 1 : ((a == DW || a == QDW) ? 2 : 3);
+    return base(a) == FP64 ? 1
+                           : ((base(a) == DW || base(a) == QDW) ? 2 : ((base(a) == QW || base(a) == QQW) ? 4 : 3));
 }
 
-__host__ __device__ constexpr bool is_quasi(int a) { return a == QDW || a == QTW; }
+// Words of a stored vector element (one FP64 word for the mixed types).
+__host__ __device__ constexpr int vwords(int a) { return is_mixed(a) ? 1 : words(a); }
+
+// Quasi types: r is normalised after its update in CG (Sec. IV-D).  The
+// mixed types' r is FP64.
+__host__ __device__ constexpr bool is_quasi(int a) { return a == QDW || a == QTW || a == QQW; }
 
 template <int A>
 struct Num {
@@ -121,17 +143,195 @@ __device__ __forceinline__ void tw_renorm(double &c1, double &c2, double &c3)
     c3 = carry ? f2 : 0.0;
 }
 
+// ---------------------------------------------- quadruple-word helpers
+
+// (a, b, c) -> three words carrying the same exact sum (three TwoSums).
+__device__ __forceinline__ void three_sum(double &a, double &b, double &c)
+{
+    double t1, t2, t3;
+    two_sum(a, b, t1, t2);
+    two_sum(c, t1, a, t3);
+    two_sum(t2, t3, b, c);
+}
+
+// (a, b, c) -> two words; the error of the last FP64 sum is dropped.
+__device__ __forceinline__ void three_sum2(double &a, double &b, double c)
+{
+    double t1, t2, t3;
+    two_sum(a, b, t1, t2);
+    two_sum(c, t1, a, t3);
+    b = t2 + t3;
+}
+
+// QW renormalisation of five components (largest first) into four
+// non-overlapping words: QuickTwoSums from the bottom word up, then from
+// the top down, where a partial sum becomes the next output word whenever
+// the error it leaves is nonzero (and the error carries on); the last
+// partial sum fills the next free word.  The output index is per lane, so
+// each word is chosen with selects.
+__device__ __forceinline__ void qw_renorm(double c0, double c1, double c2, double c3, double c4, double &r0,
+                                          double &r1, double &r2, double &r3)
+{
+    double s, t[5];
+    quick_two_sum(c3, c4, s, t[4]);
+    quick_two_sum(c2, s, s, t[3]);
+    quick_two_sum(c1, s, s, t[2]);
+    quick_two_sum(c0, s, t[0], t[1]);
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    int k = 0;
+    s = t[0];
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+        double u, e;
+        quick_two_sum(s, t[i], u, e);
+        const bool emit = (e != 0.0);
+        b0 = (emit && k == 0) ? u : b0;
+        b1 = (emit && k == 1) ? u : b1;
+        b2 = (emit && k == 2) ? u : b2;
+        b3 = (emit && k == 3) ? u : b3;
+        s = emit ? e : u;
+        k += emit ? 1 : 0;
+    }
+    r0 = k == 0 ? s : b0;
+    r1 = k == 1 ? s : b1;
+    r2 = k == 2 ? s : b2;
+    r3 = k == 3 ? s : b3;
+}
+
+// VecSum4: TwoSums from the top word down (Alg. 9 extended to four words).
+__device__ __forceinline__ void vec_sum4(double &c1, double &c2, double &c3, double &c4)
+{
+    two_sum(c1, c2, c1, c2);
+    two_sum(c2, c3, c2, c3);
+    two_sum(c3, c4, c3, c4);
+}
+
 template <int A>
 __device__ __forceinline__ Num<A> normalise(Num<A> a)
 {
-    if constexpr (A == DW || A == QDW) {
+    constexpr int B = base(A);
+    if constexpr (B == DW || B == QDW) {
         quick_two_sum(a.w[0], a.w[1], a.w[0], a.w[1]);
-    } else if constexpr (A == QTW || A == QTWE) {
+    } else if constexpr (B == QTW || B == QTWE) {
         vec_sum3(a.w[0], a.w[1], a.w[2]);
-    } else if constexpr (A == TW) {
+    } else if constexpr (B == TW) {
         tw_renorm(a.w[0], a.w[1], a.w[2]);
+    } else if constexpr (B == QW) {
+        qw_renorm(a.w[0], a.w[1], a.w[2], a.w[3], 0.0, a.w[0], a.w[1], a.w[2], a.w[3]);
+    } else if constexpr (B == QQW) {
+        vec_sum4(a.w[0], a.w[1], a.w[2], a.w[3]);
     }
     return a;
+}
+
+// QW sum (the faster variant): word-wise TwoSums, each error carried into
+// the next word by TwoSum or a three-term sum, the last order in FP64.
+__device__ __forceinline__ void qw_add(const double *a, const double *b, double *c)
+{
+    double s0, s1, s2, s3, e0, e1, e2, e3;
+    two_sum(a[0], b[0], s0, e0);
+    two_sum(a[1], b[1], s1, e1);
+    two_sum(a[2], b[2], s2, e2);
+    two_sum(a[3], b[3], s3, e3);
+    two_sum(s1, e0, s1, e0);
+    three_sum(s2, e0, e1);
+    three_sum2(s3, e0, e2);
+    e0 = (e0 + e1) + e3;
+    qw_renorm(s0, s1, s2, s3, e0, c[0], c[1], c[2], c[3]);
+}
+
+// QW product: products of order 0, 1, 2 exactly (TwoProdFMA), summed order
+// by order with TwoSums; order-3 products and leftover errors in FP64.
+__device__ __forceinline__ void qw_mul(const double *a, const double *b, double *c)
+{
+    double p0, p1, p2, p3, p4, p5, q0, q1, q2, q3, q4, q5, s0, s1, s2, t0, t1;
+    two_prod(a[0], b[0], p0, q0);
+    two_prod(a[0], b[1], p1, q1);
+    two_prod(a[1], b[0], p2, q2);
+    two_prod(a[0], b[2], p3, q3);
+    two_prod(a[1], b[1], p4, q4);
+    two_prod(a[2], b[0], p5, q5);
+    three_sum(p1, p2, q0);
+    three_sum(p2, q1, q2);
+    three_sum(p3, p4, p5);
+    two_sum(p2, p3, s0, t0);
+    two_sum(q1, p4, s1, t1);
+    s2 = q2 + p5;
+    two_sum(s1, t0, s1, t0);
+    s2 = s2 + (t0 + t1);
+    double o3 = a[0] * b[3];
+    o3 = o3 + a[1] * b[2];
+    o3 = o3 + a[2] * b[1];
+    o3 = o3 + a[3] * b[0];
+    o3 = ((((o3 + q0) + q3) + q4) + q5);
+    s1 = s1 + o3;
+    qw_renorm(p0, p1, s0, s1, s2, c[0], c[1], c[2], c[3]);
+}
+
+// FP64 x QW: qw_mul with (a, 0, 0, 0), the operations on the zero words
+// (exact identities) left out.
+__device__ __forceinline__ void qw_dxmul(double a, const double *b, double *c)
+{
+    double p0, p1, p3, q0, q1, q3, u, s0, s1, t0;
+    two_prod(a, b[0], p0, q0);
+    two_prod(a, b[1], p1, q1);
+    two_prod(a, b[2], p3, q3);
+    two_sum(q0, p1, p1, u);
+    two_sum(u, q1, u, q1);
+    two_sum(u, p3, s0, t0);
+    two_sum(q1, t0, s1, t0);
+    s1 = s1 + (a * b[3] + q3);
+    qw_renorm(p0, p1, s0, s1, t0, c[0], c[1], c[2], c[3]);
+}
+
+// QQW sum: Alg. 7 one order further.
+__device__ __forceinline__ void qqw_add(const double *a, const double *b, double *c)
+{
+    double e1, e2, e3, e4, e5, e6, t;
+    two_sum(a[0], b[0], c[0], e1);
+    two_sum(a[1], b[1], t, e2);
+    two_sum(t, e1, c[1], e3);
+    two_sum(a[2], b[2], t, e4);
+    two_sum(t, e2, t, e5);
+    two_sum(t, e3, c[2], e6);
+    c[3] = (((a[3] + b[3]) + e4) + e5) + e6;
+}
+
+// QQW product: Alg. 8 one order further (order 2 exact, order 3 in FP64).
+__device__ __forceinline__ void qqw_mul(const double *a, const double *b, double *c)
+{
+    double e[15], t2, t3, t4, t5, t6, u;
+    two_prod(a[0], b[0], c[0], e[1]);
+    two_prod(a[0], b[1], t2, e[2]);
+    two_prod(a[1], b[0], t3, e[3]);
+    two_sum(t2, t3, u, e[4]);
+    two_sum(u, e[1], c[1], e[5]);
+    two_prod(a[0], b[2], t4, e[6]);
+    two_prod(a[1], b[1], t5, e[7]);
+    two_prod(a[2], b[0], t6, e[8]);
+    two_sum(t4, t5, u, e[9]);
+    two_sum(u, t6, u, e[10]);
+    two_sum(u, e[2], u, e[11]);
+    two_sum(u, e[3], u, e[12]);
+    two_sum(u, e[4], u, e[13]);
+    two_sum(u, e[5], c[2], e[14]);
+    double d = __builtin_fma(a[3], b[0], e[6]) + __builtin_fma(a[2], b[1], e[7]);
+    d = d + __builtin_fma(a[1], b[2], e[8]);
+    d = d + __builtin_fma(a[0], b[3], e[9]);
+    c[3] = ((((d + e[10]) + e[11]) + e[12]) + e[13]) + e[14];
+}
+
+// FP64 x QQW: Alg. 10 one order further.
+__device__ __forceinline__ void qqw_dxmul(double a, const double *b, double *c)
+{
+    double e1, e2, e3, e4, e5, e6, t;
+    two_prod(a, b[0], c[0], e1);
+    two_prod(a, b[1], t, e2);
+    two_sum(t, e1, c[1], e5);
+    two_prod(a, b[2], t, e3);
+    two_sum(t, e2, t, e4);
+    two_sum(t, e5, c[2], e6);
+    c[3] = (__builtin_fma(a, b[3], e3) + e4) + e6;
 }
 
 // ------------------------------------------------------ add / mul
@@ -139,27 +339,32 @@ __device__ __forceinline__ Num<A> normalise(Num<A> a)
 template <int A>
 __device__ __forceinline__ Num<A> add(const Num<A> &a, const Num<A> &b)
 {
+    constexpr int B = base(A);
     Num<A> c;
-    if constexpr (A == FP64) {
+    if constexpr (B == FP64) {
         c.w[0] = a.w[0] + b.w[0];
-    } else if constexpr (A == DW || A == QDW) {
+    } else if constexpr (B == DW || B == QDW) {
         double s, e;
         two_sum(a.w[0], b.w[0], s, e);
         e = (e + a.w[1]) + b.w[1];
-        if constexpr (A == DW) {
+        if constexpr (B == DW) {
             quick_two_sum(s, e, c.w[0], c.w[1]);
         } else {
             c.w[0] = s;
             c.w[1] = e;
         }
+    } else if constexpr (B == QW) {
+        qw_add(a.w, b.w, c.w);
+    } else if constexpr (B == QQW) {
+        qqw_add(a.w, b.w, c.w);
     } else {
         double e1, e2, e3, t;
         two_sum(a.w[0], b.w[0], c.w[0], e1);
         two_sum(a.w[1], b.w[1], t, e2);
         two_sum(t, e1, c.w[1], e3);
         c.w[2] = ((a.w[2] + b.w[2]) + e2) + e3;
-        if constexpr (A == TW) tw_renorm(c.w[0], c.w[1], c.w[2]);
-        if constexpr (A == QTWE) vec_sum3(c.w[0], c.w[1], c.w[2]);
+        if constexpr (B == TW) tw_renorm(c.w[0], c.w[1], c.w[2]);
+        if constexpr (B == QTWE) vec_sum3(c.w[0], c.w[1], c.w[2]);
     }
     return c;
 }
@@ -167,20 +372,25 @@ __device__ __forceinline__ Num<A> add(const Num<A> &a, const Num<A> &b)
 template <int A>
 __device__ __forceinline__ Num<A> mul(const Num<A> &a, const Num<A> &b)
 {
+    constexpr int B = base(A);
     Num<A> c;
-    if constexpr (A == FP64) {
+    if constexpr (B == FP64) {
         c.w[0] = a.w[0] * b.w[0];
-    } else if constexpr (A == DW || A == QDW) {
+    } else if constexpr (B == DW || B == QDW) {
         double p, e;
         two_prod(a.w[0], b.w[0], p, e);
         e = __builtin_fma(a.w[0], b.w[1], e);
         e = __builtin_fma(a.w[1], b.w[0], e);
-        if constexpr (A == DW) {
+        if constexpr (B == DW) {
             quick_two_sum(p, e, c.w[0], c.w[1]);
         } else {
             c.w[0] = p;
             c.w[1] = e;
         }
+    } else if constexpr (B == QW) {
+        qw_mul(a.w, b.w, c.w);
+    } else if constexpr (B == QQW) {
+        qqw_mul(a.w, b.w, c.w);
     } else {
         double e1, e2, e3, e4, e5, t2, t3, u;
         two_prod(a.w[0], b.w[0], c.w[0], e1);
@@ -192,8 +402,8 @@ __device__ __forceinline__ Num<A> mul(const Num<A> &a, const Num<A> &b)
         const double f2 = __builtin_fma(a.w[1], b.w[1], e3);
         const double f3 = __builtin_fma(a.w[0], b.w[2], e4);
         c.w[2] = ((f1 + f2) + f3) + e5;
-        if constexpr (A == TW) tw_renorm(c.w[0], c.w[1], c.w[2]);
-        if constexpr (A == QTWE) vec_sum3(c.w[0], c.w[1], c.w[2]);
+        if constexpr (B == TW) tw_renorm(c.w[0], c.w[1], c.w[2]);
+        if constexpr (B == QTWE) vec_sum3(c.w[0], c.w[1], c.w[2]);
     }
     return c;
 }
@@ -202,27 +412,32 @@ __device__ __forceinline__ Num<A> mul(const Num<A> &a, const Num<A> &b)
 template <int A>
 __device__ __forceinline__ Num<A> dxmul(double a, const Num<A> &b)
 {
+    constexpr int B = base(A);
     Num<A> c;
-    if constexpr (A == FP64) {
+    if constexpr (B == FP64) {
         c.w[0] = a * b.w[0];
-    } else if constexpr (A == DW || A == QDW) {
+    } else if constexpr (B == DW || B == QDW) {
         double p, e;
         two_prod(a, b.w[0], p, e);
         e = __builtin_fma(a, b.w[1], e);
-        if constexpr (A == DW) {
+        if constexpr (B == DW) {
             quick_two_sum(p, e, c.w[0], c.w[1]);
         } else {
             c.w[0] = p;
             c.w[1] = e;
         }
+    } else if constexpr (B == QW) {
+        qw_dxmul(a, b.w, c.w);
+    } else if constexpr (B == QQW) {
+        qqw_dxmul(a, b.w, c.w);
     } else {
         double e1, e2, e5, t;
         two_prod(a, b.w[0], c.w[0], e1);
         two_prod(a, b.w[1], t, e2);
         two_sum(t, e1, c.w[1], e5);
         c.w[2] = __builtin_fma(a, b.w[2], e2) + e5;
-        if constexpr (A == TW) tw_renorm(c.w[0], c.w[1], c.w[2]);
-        if constexpr (A == QTWE) vec_sum3(c.w[0], c.w[1], c.w[2]);
+        if constexpr (B == TW) tw_renorm(c.w[0], c.w[1], c.w[2]);
+        if constexpr (B == QTWE) vec_sum3(c.w[0], c.w[1], c.w[2]);
     }
     return c;
 }
@@ -235,13 +450,15 @@ __device__ __forceinline__ Num<A> neg(Num<A> a)
     return a;
 }
 
-// Multi-word value rounded to FP64: fl(x1 + x2), fl(x1 + fl(x2 + x3)).
+// Multi-word value rounded to FP64: fl(x1 + x2), fl(x1 + fl(x2 + x3)),
+// fl(x1 + fl(x2 + fl(x3 + x4))).
 template <int A>
 __device__ __forceinline__ double to_fp64(const Num<A> &a)
 {
     if constexpr (words(A) == 1) return a.w[0];
     else if constexpr (words(A) == 2) return a.w[0] + a.w[1];
-    else return a.w[0] + (a.w[1] + a.w[2]);
+    else if constexpr (words(A) == 3) return a.w[0] + (a.w[1] + a.w[2]);
+    else return a.w[0] + (a.w[1] + (a.w[2] + a.w[3]));
 }
 
 // a / b by long division with FP64 quotient digits.  Each remainder is
@@ -250,7 +467,8 @@ __device__ __forceinline__ double to_fp64(const Num<A> &a)
 template <int A>
 __device__ __forceinline__ Num<A> div(const Num<A> &a, const Num<A> &b)
 {
-    if constexpr (A == FP64) {
+    constexpr int B = base(A);
+    if constexpr (B == FP64) {
         return promote<A>(a.w[0] / b.w[0]);
     } else {
         const double q1 = a.w[0] / b.w[0];
@@ -259,9 +477,13 @@ __device__ __forceinline__ Num<A> div(const Num<A> &a, const Num<A> &b)
         Num<A> q;
         q.w[0] = q1;
         q.w[1] = q2;
-        if constexpr (words(A) == 3) {
+        if constexpr (words(A) >= 3) {
             r = normalise<A>(add<A>(r, neg<A>(dxmul<A>(q2, b))));
             q.w[2] = r.w[0] / b.w[0];
+        }
+        if constexpr (words(A) == 4) {
+            r = normalise<A>(add<A>(r, neg<A>(dxmul<A>(q.w[2], b))));
+            q.w[3] = r.w[0] / b.w[0];
         }
         return normalise<A>(q);
     }
@@ -271,11 +493,14 @@ __device__ __forceinline__ Num<A> div(const Num<A> &a, const Num<A> &b)
 // The FP64 solver writes every a*x + y as one fma (same as the plain
 // FP64 CG it is the reference for).
 
+// The mixed types update their FP64 vectors the same way, with the
+// multi-word alpha (beta) rounded to FP64.
 template <int A>
 __device__ __forceinline__ Num<A> axpy_term(const Num<A> &alpha, const Num<A> &x, const Num<A> &y)
 {
     // y + alpha * x
     if constexpr (A == FP64) return promote<A>(__builtin_fma(alpha.w[0], x.w[0], y.w[0]));
+    else if constexpr (is_mixed(A)) return promote<A>(__builtin_fma(to_fp64<A>(alpha), x.w[0], y.w[0]));
     else return add<A>(y, mul<A>(alpha, x));
 }
 
@@ -284,25 +509,36 @@ __device__ __forceinline__ Num<A> axmy_term(const Num<A> &alpha, const Num<A> &x
 {
     // y - alpha * x
     if constexpr (A == FP64) return promote<A>(__builtin_fma(-alpha.w[0], x.w[0], y.w[0]));
+    else if constexpr (is_mixed(A)) return promote<A>(__builtin_fma(-to_fp64<A>(alpha), x.w[0], y.w[0]));
     else return add<A>(y, neg<A>(mul<A>(alpha, x)));
 }
 
 // ------------------------------------------------------ word planes
 
+// A mixed type's vector element is one FP64 word: loaded promoted, stored
+// rounded to FP64.
 template <int A>
 __device__ __forceinline__ Num<A> load(const double *__restrict__ v, long n, long i)
 {
     Num<A> r;
+    if constexpr (is_mixed(A)) {
+        r = promote<A>(v[i]);
+    } else {
 #pragma unroll
-    for (int w = 0; w < words(A); ++w) r.w[w] = v[w * n + i];
+        for (int w = 0; w < words(A); ++w) r.w[w] = v[w * n + i];
+    }
     return r;
 }
 
 template <int A>
 __device__ __forceinline__ void store(double *__restrict__ v, long n, long i, const Num<A> &x)
 {
+    if constexpr (is_mixed(A)) {
+        v[i] = to_fp64<A>(x);
+    } else {
 #pragma unroll
-    for (int w = 0; w < words(A); ++w) v[w * n + i] = x.w[w];
+        for (int w = 0; w < words(A); ++w) v[w * n + i] = x.w[w];
+    }
 }
 
 template <int A>
@@ -324,7 +560,8 @@ __device__ __forceinline__ void store_scalar(double *__restrict__ s, const Num<A
 // Gather layout of the vector the SpMV reads (the solvers keep p in it):
 // 2-word values interleaved (element i's words at v[2 i], v[2 i + 1]); 3-word
 // values as interleaved leading pairs (v[2 i], v[2 i + 1]) followed by a
-// plane of third words (v[2 n + i]).  A gathered element is then one wide
+// plane of third words (v[2 n + i]); 4-word values as two interleaved pair
+// planes (v[2 i], v[2 i + 1]; v[2 n + 2 i], v[2 n + 2 i + 1]).  A gathered element is then one wide
 // load (plus one narrow one for 3 words) touching the fewest cache lines
 // per wavefront: 16 + 8 bytes per lane instead of 24 at a 24-byte stride.
 typedef double dvec2 __attribute__((ext_vector_type(2)));
@@ -333,13 +570,20 @@ template <int A>
 __device__ __forceinline__ Num<A> load_il(const double *__restrict__ v, long n, long i)
 {
     Num<A> r;
-    if constexpr (words(A) == 1) {
+    if constexpr (is_mixed(A)) {
+        r = promote<A>(v[i]);
+    } else if constexpr (words(A) == 1) {
         r.w[0] = v[i];
     } else {
         const dvec2 t = *(const dvec2 *)(v + 2 * i);
         r.w[0] = t.x;
         r.w[1] = t.y;
         if constexpr (words(A) == 3) r.w[2] = v[2 * n + i];
+        if constexpr (words(A) == 4) {
+            const dvec2 u = *(const dvec2 *)(v + 2 * n + 2 * i);
+            r.w[2] = u.x;
+            r.w[3] = u.y;
+        }
     }
     return r;
 }
@@ -347,7 +591,9 @@ __device__ __forceinline__ Num<A> load_il(const double *__restrict__ v, long n, 
 template <int A>
 __device__ __forceinline__ void store_il(double *__restrict__ v, long n, long i, const Num<A> &x)
 {
-    if constexpr (words(A) == 1) {
+    if constexpr (is_mixed(A)) {
+        v[i] = to_fp64<A>(x);
+    } else if constexpr (words(A) == 1) {
         v[i] = x.w[0];
     } else {
         dvec2 t;
@@ -355,6 +601,12 @@ __device__ __forceinline__ void store_il(double *__restrict__ v, long n, long i,
         t.y = x.w[1];
         *(dvec2 *)(v + 2 * i) = t;
         if constexpr (words(A) == 3) v[2 * n + i] = x.w[2];
+        if constexpr (words(A) == 4) {
+            dvec2 u;
+            u.x = x.w[2];
+            u.y = x.w[3];
+            *(dvec2 *)(v + 2 * n + 2 * i) = u;
+        }
     }
 }
 

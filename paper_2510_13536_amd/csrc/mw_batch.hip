@@ -140,7 +140,8 @@ __global__ void __launch_bounds__(BNT) mw_batch_spmv_kernel(BatchDev d, const do
                 const long re = lane == 0 ? row - 1 : row + 1;
                 if ((lane == 0 || lane == 63) && re >= 0 && re < d.n) xe = load_v<A, MODE>(x, d.n, re);
             }
-            acc = dia_row_sum<A, MODE>(b, w, lane, row, d.soff + (b >> 6), d.smask + (b >> 6), d.sv, x, d.n, xc, xe);
+            acc = dia_row_sum<A, MODE, false>(b, w, lane, row, d.soff + (b >> 6), d.smask + (b >> 6), d.sv, x, d.n, xc,
+                                              xe, nullptr);
         } else {
             acc = sell_row_sum<A, MODE>(b, w, lane, d.sc, d.sv, x, d.n);
             if (MODE == 1 && valid) xc = load_il<A>(x, d.n, row);
@@ -736,7 +737,7 @@ extern "C" {
 
 size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int32_t nnz)
 {
-    if (!valid_arith(a) || nsys <= 0 || n <= 0 || nnz < 0) return 0;
+    if (!valid_arith(a) || mixed_arith(a) || nsys <= 0 || n <= 0 || nnz < 0) return 0;
     return batch_layout(a, nsys, n, nnz).bytes;
 }
 
@@ -747,7 +748,8 @@ namespace {
 bool batched_args_ok(int a, int32_t nsys, const int32_t *sys_row_off, const mw_csr_t *A, const double *b,
                      const double *x, const void *workspace)
 {
-    if (!valid_arith(a) || nsys <= 0 || !sys_row_off || !valid_csr(A) || !b || !x || !workspace) return false;
+    if (!valid_arith(a) || mixed_arith(a) || nsys <= 0 || !sys_row_off || !valid_csr(A) || !b || !x || !workspace)
+        return false;
     if (sys_row_off[0] != 0 || sys_row_off[nsys] != A->n) return false;
     for (int s = 0; s < nsys; ++s)
         if (sys_row_off[s + 1] < sys_row_off[s]) return false;
@@ -768,7 +770,7 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
                  (opts->precond != MW_PRECOND_NONE && opts->precond != MW_PRECOND_JACOBI)))
         return MW_EINVAL;
     MW_CSR_GUARD(A, stream);
-    MW_DISPATCH(a, batched_a, nsys, sys_row_off, A, b, x, tol, maxit, opts, workspace, iters, status, rel_res, info,
+    MW_DISPATCH_WORDS(a, batched_a, nsys, sys_row_off, A, b, x, tol, maxit, opts, workspace, iters, status, rel_res, info,
                 (hipStream_t)stream);
 }
 

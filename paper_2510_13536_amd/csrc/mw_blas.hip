@@ -235,6 +235,8 @@ __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const i
     }
     const int lane = threadIdx.x & 63, wave = wave_id();
     const TileWalk tw = xcd_walk((ns + NWAVE - 1) / NWAVE, rev);
+    __shared__ double xwin[dia_window<A>() ? NWAVE * K * WIN_ROWS : 1];
+    double *wv = xwin + (dia_window<A>() ? wave * K * WIN_ROWS : 0);
     Num<A> part = zero<A>();
     for (int m = 0; m < tw.count; ++m) {
         const int s = tw[m] * NWAVE + wave;
@@ -247,12 +249,18 @@ __global__ void __launch_bounds__(NT) mw_sell_spmv_kernel(int n, int ns, const i
             // x[row]: the offset-0 slot, the source of the +-1 slots and,
             // in CG mode, p_i of p^T q
             const Num<A> xc = row < n ? load_v<A, MODE>(x, n, row) : zero<A>();
-            Num<A> xe = zero<A>();
-            if constexpr (neighbour_moves<A>()) {
-                const long re = lane == 0 ? (long)row - 1 : (long)row + 1;
-                if ((lane == 0 || lane == 63) && re >= 0 && re < n) xe = load_v<A, MODE>(x, n, re);
+            const int32_t *so = soff + (b >> 6);
+            if (dia_window<A>() && w >= WIN_MIN_W && offsets_in_window(so, w)) {
+                stage_window<A, MODE>(wv, lane, row, xc, x, n);
+                acc = dia_row_sum<A, MODE, true>(b, w, lane, row, so, smask + (b >> 6), sv, x, n, xc, xc, wv);
+            } else {
+                Num<A> xe = zero<A>();
+                if constexpr (neighbour_moves<A>()) {
+                    const long re = lane == 0 ? (long)row - 1 : (long)row + 1;
+                    if ((lane == 0 || lane == 63) && re >= 0 && re < n) xe = load_v<A, MODE>(x, n, re);
+                }
+                acc = dia_row_sum<A, MODE, false>(b, w, lane, row, so, smask + (b >> 6), sv, x, n, xc, xe, wv);
             }
-            acc = dia_row_sum<A, MODE>(b, w, lane, row, soff + (b >> 6), smask + (b >> 6), sv, x, n, xc, xe);
             if (row < n) {
                 store<A>(y, n, row, acc);
                 if constexpr (MODE == 1) part = dot_step<A>(part, xc, acc);
@@ -305,8 +313,8 @@ __global__ void __launch_bounds__(NT) mw_vec_spmv_kernel(int n, const int32_t *_
             // U entries' loads in flight per lane before their products are
             // added in order (the same association as one at a time): on
             // MI355X 5-16 % faster CG iterations on long rows; four cost the
-            // 3-word types more in registers than they gain
-            constexpr int U = words(A) == 3 ? 2 : 4;
+            // 3- and 4-word types more in registers than they gain
+            constexpr int U = words(A) >= 3 ? 2 : 4;
             for (; j + (U - 1) * L < re; j += U * L) {
                 double a[U];
                 int c[U];
@@ -686,6 +694,14 @@ template int spmv_launch<QTW>(const mw_csr_t *, const mw_spmv_plan_t *, const do
                               const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
 template int spmv_launch<QTWE>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
                                const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
+template int spmv_launch<QW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
+                             const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
+template int spmv_launch<QQW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
+                              const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
+template int spmv_launch<MXDW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
+                               const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
+template int spmv_launch<MXQTW>(const mw_csr_t *, const mw_spmv_plan_t *, const double *, double *, double *,
+                                const int32_t *, int32_t *, int, hipStream_t, int *, int, hipEvent_t, hipEvent_t, int);
 
 size_t plan_bytes(int32_t n, int32_t nnz) { return plan_layout(n, nnz).bytes; }
 
@@ -801,7 +817,7 @@ constexpr int NOALLOC_SLOTS = MW_DOT_NOALLOC_MAX_N / (NT * DOT_EPT);
 static_assert((long)NOALLOC_SLOTS * NT * DOT_EPT == MW_DOT_NOALLOC_MAX_N, "whole workgroups");
 constexpr int MAX_DEVICES = 64;
 
-static __device__ __align__(256) double scratch[3 * NOALLOC_SLOTS];
+static __device__ __align__(256) double scratch[4 * NOALLOC_SLOTS];
 
 std::mutex g_scratch_mu;
 double *g_scratch_ptr[MAX_DEVICES] = {};
@@ -856,7 +872,9 @@ int spmv_planned_a(const mw_spmv_plan_t *P, const double *x, double *y, hipStrea
 
 extern "C" {
 
-int mw_words(mw_arith_t a) { return mwh::valid_arith(a) ? words(a) : -1; }
+int mw_words(mw_arith_t a) { return mwh::valid_arith(a) ? vwords(a) : -1; }
+
+int mw_scalar_words(mw_arith_t a) { return mwh::valid_arith(a) ? words(a) : -1; }
 
 const char *mw_status_string(int code)
 {
@@ -875,13 +893,13 @@ const char *mw_last_error(void) { return mwh::g_err; }
 int mw_elementwise(mw_arith_t a, int op, int32_t n, const double *u, const double *v, double *w, void *stream)
 {
     mwh::clear_error();
-    if (!valid_arith(a) || op < MW_OP_ADD || op > MW_OP_TOFP64 || n < 0 || (n > 0 && (!u || !w)))
+    if (!valid_arith(a) || mixed_arith(a) || op < MW_OP_ADD || op > MW_OP_TOFP64 || n < 0 || (n > 0 && (!u || !w)))
         return MW_EINVAL;
     const bool needs_v = (op == MW_OP_ADD || op == MW_OP_MUL || op == MW_OP_DXMUL || op == MW_OP_DIV);
     if (needs_v && n > 0 && !v) return MW_EINVAL;
     if (n == 0) return MW_OK;
     hipStream_t s = (hipStream_t)stream;
-    MW_DISPATCH(a, elementwise_a, op, n, u, v, w, s);
+    MW_DISPATCH_WORDS(a, elementwise_a, op, n, u, v, w, s);
 }
 
 int mw_axpy(mw_arith_t a, int32_t n, const double *alpha, const double *x, double *y, void *stream)
@@ -943,10 +961,10 @@ int mw_csr_grad(mw_arith_t a, const mw_csr_t *A, const double *lam, const double
                 void *stream)
 {
     mwh::clear_error();
-    if (!valid_arith(a) || !valid_csr(A) || !lam || !x || !grad_val) return MW_EINVAL;
+    if (!valid_arith(a) || mixed_arith(a) || !valid_csr(A) || !lam || !x || !grad_val) return MW_EINVAL;
     MW_CSR_GUARD(A, stream);
     hipStream_t s = (hipStream_t)stream;
-    MW_DISPATCH(a, grad_a, A, lam, x, grad_val, s);
+    MW_DISPATCH_WORDS(a, grad_a, A, lam, x, grad_val, s);
 }
 
 size_t mw_spmv_plan_bytes(int32_t n, int32_t nnz)

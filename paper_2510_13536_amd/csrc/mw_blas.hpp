@@ -15,16 +15,17 @@ namespace mwk {
 // Search-direction buffers of the CG solver: x takes the updates
 // alpha_j p_j of xr(a) consecutive iterations in one pass, so one read and
 // write of x serves xr(a) iterations at the cost of a second p buffer.
-// For 3-word types that pays (measured on MI355X, 3D Poisson 128^3: QTW
-// solve -2 %); for 1- and 2-word types the solver's working set (matrix
+// For 3- and 4-word types that pays (measured on MI355X, 3D Poisson 128^3:
+// QTW solve -2 %); for 1- and 2-word types the solver's working set (matrix
 // and four vectors) just fits the 256 MB Infinity Cache and a second p
 // buffer costs more than x's traffic (DW +11 %), so they keep one.
-__host__ __device__ constexpr int xr(int a) { return words(a) == 3 ? 2 : 1; }
+__host__ __device__ constexpr int xr(int a) { return vwords(a) >= 3 ? 2 : 1; }
 constexpr int XR_MAX = 2;
+constexpr int KMAX = 4;  // words of the widest arithmetic
 
 struct CgState {
-    double rho[2][3];         // r^T r after the iteration of each parity
-    double alpha[XR_MAX][3];  // alpha of iteration k (0-based) in slot k % xr
+    double rho[2][KMAX];         // r^T r after the iteration of each parity
+    double alpha[XR_MAX][KMAX];  // alpha of iteration k (0-based) in slot k % xr
     double nb;           // ||b||_2
     double tol;
     double rel_res;      // relative residual at the stop (or the last test)
@@ -39,15 +40,15 @@ struct CgState {
     int32_t iters_final; // final iteration count (valid once stopped)
     int32_t pad;
 };
-// Loads of the matrix stream in the planned SpMV.  For 3-word vectors the
-// CG working set (four vectors of 24 bytes per row) competes with the
+// Loads of the matrix stream in the planned SpMV.  For 3- and 4-word vectors
+// the CG working set (four vectors of 24 or 32 bytes per row) competes with the
 // matrix stream for the 256 MB Infinity Cache; the matrix entries are used
 // once per SpMV, so they are loaded non-temporally there.  For 1- and
 // 2-word vectors plain loads measured faster.
 template <int A, typename T>
 __device__ __forceinline__ T load_matrix(const T *p)
 {
-    if constexpr (words(A) == 3) return __builtin_nontemporal_load(p);
+    if constexpr (vwords(A) >= 3) return __builtin_nontemporal_load(p);
     else return *p;
 }
 
@@ -93,25 +94,88 @@ __device__ __forceinline__ Num<A> sell_row_sum(int b, int w, int lane, const int
 template <int A>
 constexpr bool neighbour_moves() { return A == QTW; }
 
+// The x window of a diagonal-slot slice: when every slot offset of a slice
+// lies in [-WIN, WIN], the wavefront stages rows 64 s - WIN .. 64 s + 63 + WIN
+// of x in its own LDS region (two coalesced loads per lane: its row, which
+// the slice needs anyway, and one halo row), and every slot reads its
+// operand from there instead of gathering it through the vector memory
+// path.  Same values, same order: the row sums are bit-identical either
+// way.  Slices with fewer than WIN_MIN_W slots (the 7-point stencils) keep
+// the gathers: their two +-1 slots do not repay the halo load.  FP64 vectors
+// (FP64 and the mixed types) keep them too: its 8-byte gathers are cheap, and with the window its SpMV on
+// the 27-slot banded matrix measured 7 % slower (multi-word: DW 14 %, QTW
+// 30 % faster).
+constexpr int WIN = 32;
+constexpr int WIN_ROWS = 64 + 2 * WIN;
+constexpr int WIN_MIN_W = 5;
+
+template <int A>
+constexpr bool dia_window() { return vwords(A) > 1; }
+
+// Whether all w slot offsets of a diagonal slice lie in [-WIN, WIN]
+// (wave-uniform: scalar loads).  The slots follow the rows' CSR order, so
+// their offsets need not be sorted; the loop stops at the first one
+// outside.
+__device__ __forceinline__ bool offsets_in_window(const int32_t *__restrict__ so, int w)
+{
+    for (int j = 0; j < w; ++j) {
+        const int o = so[j];
+        if (o < -WIN || o > WIN) return false;
+    }
+    return true;
+}
+
+// Orders a wavefront's own LDS accesses: LDS instructions of one wavefront
+// execute in issue order, so only the compiler must not move the window's
+// stores and loads across this point.
+__device__ __forceinline__ void wave_lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Stages the window of the slice whose first row is row - lane: lane l
+// stores its x[row] (xc) at window index WIN + l and one halo row, lanes
+// below WIN the row WIN above (index l), the others the row WIN below
+// (index l + 2 WIN); rows outside [0, n) are stored as zero (no entry ever
+// reads them).  wv: the wavefront's K * WIN_ROWS doubles of LDS, in the
+// gather layout of WIN_ROWS elements.
+template <int A, int XL>
+__device__ __forceinline__ void stage_window(double *wv, int lane, long row, Num<A> xc,
+                                             const double *__restrict__ x, long n)
+{
+    const long hr = lane < WIN ? row - WIN : row + WIN;
+    const Num<A> xh = (hr >= 0 && hr < n) ? load_v<A, XL>(x, n, hr) : zero<A>();
+    wave_lds_order();  // the previous slice's window reads come first
+    store_il<A>(wv, WIN_ROWS, WIN + lane, xc);
+    store_il<A>(wv, WIN_ROWS, lane < WIN ? lane : lane + 2 * WIN, xh);
+    wave_lds_order();
+}
+
 // x[row + o] for a lane of a diagonal-slot slice whose slot has column
 // offset o (wave-uniform); need: the lane has an entry in the slot.  xc is
-// x[row] (0 for rows past n).  Offset 0 is xc itself.  With
+// x[row] (0 for rows past n).  Offset 0 is xc itself.  With the window
+// (W, wv staged by stage_window) every offset is read from LDS.  Else, with
 // neighbour_moves, offsets +-1 are xc moved from the neighbouring lane and
 // xe is the value one row beyond the slice's edge lane (lane 0:
-// x[row - 1], lane 63: x[row + 1]).  Any other offset is a gather.  Called
-// by the whole wavefront (the moves need every lane).
-template <int A, int XL>
+// x[row - 1], lane 63: x[row + 1]), and any other offset is a gather.
+// Called by the whole wavefront (the moves need every lane).
+template <int A, int XL, bool W>
 __device__ __forceinline__ Num<A> dia_x(int o, bool need, long row, Num<A> xc, Num<A> xe,
-                                        const double *__restrict__ x, long n)
+                                        const double *__restrict__ x, long n, const double *wv, int lane)
 {
     if (o == 0) return xc;
-    if constexpr (neighbour_moves<A>()) {
-        if (o == 1) return wave_shift1<1, A>(xc, xe);
-        if (o == -1) return wave_shift1<-1, A>(xc, xe);
+    if constexpr (W) {
+        return load_il<A>(wv, WIN_ROWS, WIN + lane + o);
+    } else {
+        if constexpr (neighbour_moves<A>()) {
+            if (o == 1) return wave_shift1<1, A>(xc, xe);
+            if (o == -1) return wave_shift1<-1, A>(xc, xe);
+        }
+        Num<A> v = zero<A>();
+        if (need) v = load_v<A, XL>(x, n, row + o);
+        return v;
     }
-    Num<A> v = zero<A>();
-    if (need) v = load_v<A, XL>(x, n, row + o);
-    return v;
 }
 
 // Sum of one row of a diagonal-slot slice (same value positions as
@@ -121,11 +185,11 @@ __device__ __forceinline__ Num<A> dia_x(int o, bool need, long row, Num<A> xc, N
 // so the row is summed in CSR order from zero, as in sell_row_sum.
 // soff / smask point at the slice's first slot (wave-uniform: scalar
 // loads); the gathers need no column loads.  xc, xe: see dia_x.
-template <int A, int XL>
+template <int A, int XL, bool W>
 __device__ __forceinline__ Num<A> dia_row_sum(int b, int w, int lane, long row, const int32_t *__restrict__ soff,
                                               const uint64_t *__restrict__ smask, const double *__restrict__ sv,
                                               const double *__restrict__ x, long n, Num<A> xc,
-                                              Num<A> xe)
+                                              Num<A> xe, const double *wv)
 {
     Num<A> acc = zero<A>();
     const int wp = w >> 1;
@@ -133,8 +197,8 @@ __device__ __forceinline__ Num<A> dia_row_sum(int b, int w, int lane, long row, 
         const int z = b + 128 * m + 2 * lane;
         const dvec2 a = load_matrix<A>((const dvec2 *)(sv + z));
         const bool p0 = (smask[2 * m] >> lane) & 1, p1 = (smask[2 * m + 1] >> lane) & 1;
-        const Num<A> x0 = dia_x<A, XL>(soff[2 * m], p0, row, xc, xe, x, n);
-        const Num<A> x1 = dia_x<A, XL>(soff[2 * m + 1], p1, row, xc, xe, x, n);
+        const Num<A> x0 = dia_x<A, XL, W>(soff[2 * m], p0, row, xc, xe, x, n, wv, lane);
+        const Num<A> x1 = dia_x<A, XL, W>(soff[2 * m + 1], p1, row, xc, xe, x, n, wv, lane);
         if (p0) acc = row_step<A>(acc, a.x, x0);
         if (p1) acc = row_step<A>(acc, a.y, x1);
     }
@@ -142,7 +206,7 @@ __device__ __forceinline__ Num<A> dia_row_sum(int b, int w, int lane, long row, 
         const int z = b + 128 * wp + lane;
         const double a0 = load_matrix<A>(sv + z);
         const bool p0 = (smask[w - 1] >> lane) & 1;
-        const Num<A> x0 = dia_x<A, XL>(soff[w - 1], p0, row, xc, xe, x, n);
+        const Num<A> x0 = dia_x<A, XL, W>(soff[w - 1], p0, row, xc, xe, x, n, wv, lane);
         if (p0) acc = row_step<A>(acc, a0, x0);
     }
     return acc;

@@ -131,8 +131,8 @@ __global__ void __launch_bounds__(FIN_NT) mw_cg_init_final_kernel(int nslots, co
 // the previous kernel's partials, so that those loads overlap it.  Measured
 // on MI355X (3D Poisson 128^3): four against two, FP64 and DW solves -2.5 %,
 // QTW -1 %; TW +0.6 % (its heavier arithmetic needs the registers), so TW
-// and QTWE, the two with the most arithmetic per element, keep two.
-__host__ __device__ constexpr int prefetch_tiles(int a) { return a == TW || a == QTWE ? 2 : 4; }
+// and QTWE, and the 4-word QW and QQW, keep two.
+__host__ __device__ constexpr int prefetch_tiles(int a) { return a == TW || a == QTWE || words(a) == 4 ? 2 : 4; }
 
 // Iteration step 2 (parity par; iteration k, 0-based, with k % xr(A) = kpos):
 // every workgroup reduces the p^T q partials in the same fixed order, so all
@@ -366,7 +366,7 @@ struct CgLayout {
 CgLayout cg_layout(int a, int32_t n, int32_t nnz)
 {
     const size_t K = (size_t)words(a);
-    const size_t plane = align256(sizeof(double) * (size_t)n * K);
+    const size_t plane = align256(sizeof(double) * (size_t)n * (size_t)vwords(a));
     const size_t nsl = (size_t)(spmv_max_slots(n) > UGRID_MAX ? spmv_max_slots(n) : UGRID_MAX);
     const size_t slots = align256(sizeof(double) * nsl * K);
     CgLayout L;
@@ -757,6 +757,10 @@ int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, dou
         return MW_EINVAL;
     if (opts && (!shape_valid(opts->shape) || opts->normalize < 0)) return MW_EINVAL;
     if (opts && opts->precond != MW_PRECOND_NONE && opts->precond != MW_PRECOND_JACOBI) return MW_EINVAL;
+    if (opts && opts->precond != MW_PRECOND_NONE && mixed_arith(a)) {
+        set_error("mw_cg_solve: the mixed-precision arithmetics take no preconditioner");
+        return MW_EINVAL;
+    }
     MW_CSR_GUARD(A, stream);
     MW_DISPATCH(a, cg_a, A, b, x, tol, maxit, opts, workspace, info, (hipStream_t)stream);
 }

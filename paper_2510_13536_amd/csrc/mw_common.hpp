@@ -158,7 +158,8 @@ void clear_error();  // at the entry of every status-returning ABI call
 
 inline int blocks_for(long n, long per) { return (int)((n + per - 1) / per); }
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
-inline bool valid_arith(int a) { return a >= MW_FP64 && a <= MW_QTWE; }
+inline bool valid_arith(int a) { return a >= MW_FP64 && a <= MW_MXQTW; }
+inline bool mixed_arith(int a) { return a == MW_MXDW || a == MW_MXQTW; }
 inline bool valid_csr(const mw_csr_t *A)
 {
     return A && A->n > 0 && A->nnz >= 0 && A->row_ptr && A->col_idx && A->val;
@@ -208,12 +209,23 @@ struct SolveEvents {
         else hipLaunchKernelGGL(kern, grid, block, 0, stream, __VA_ARGS__);                     \
     } while (0)
 
-#define MW_DISPATCH(a, fn, ...)                          \
+// Every arithmetic but the mixed ones (callers reject those first).
+#define MW_DISPATCH_WORDS(a, fn, ...)                    \
     switch (a) {                                         \
     case MW_FP64: return fn<mwk::FP64>(__VA_ARGS__);     \
     case MW_DW: return fn<mwk::DW>(__VA_ARGS__);         \
     case MW_QDW: return fn<mwk::QDW>(__VA_ARGS__);       \
     case MW_TW: return fn<mwk::TW>(__VA_ARGS__);         \
     case MW_QTW: return fn<mwk::QTW>(__VA_ARGS__);       \
-    default: return fn<mwk::QTWE>(__VA_ARGS__);          \
+    case MW_QTWE: return fn<mwk::QTWE>(__VA_ARGS__);     \
+    case MW_QW: return fn<mwk::QW>(__VA_ARGS__);         \
+    default: return fn<mwk::QQW>(__VA_ARGS__);           \
+    }
+
+// Every arithmetic.
+#define MW_DISPATCH(a, fn, ...)                          \
+    switch (a) {                                         \
+    case MW_MXDW: return fn<mwk::MXDW>(__VA_ARGS__);     \
+    case MW_MXQTW: return fn<mwk::MXQTW>(__VA_ARGS__);   \
+    default: MW_DISPATCH_WORDS(a, fn, __VA_ARGS__)       \
     }

@@ -16,8 +16,11 @@ import torch
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmwcg.so")
 
-ARITH = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4, "qtwe": 5}
-WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3, "qtwe": 3}
+ARITH = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4, "qtwe": 5, "qw": 6, "qqw": 7, "mxdw": 8, "mxqtw": 9}
+# planes of a vector element
+WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3, "qtwe": 3, "qw": 4, "qqw": 4, "mxdw": 1, "mxqtw": 1}
+# words of a scalar (a dot result, an axpy alpha): multi-word for the mixed types
+SWORDS = dict(WORDS, mxdw=2, mxqtw=3)
 DOT_NOALLOC_MAX_N = 33554432  # MW_DOT_NOALLOC_MAX_N in include/mw.h
 OPS = {"add": 0, "mul": 1, "dxmul": 2, "div": 3, "norm": 4, "neg": 5, "tofp64": 6}
 STATUS = {0: "ok", 1: "not_converged", 2: "breakdown"}
@@ -120,6 +123,7 @@ def lib():
     if len(rt) > 1:
         raise MWError("two HIP runtimes are mapped in this process: %s" % sorted(rt))
     L.mw_words.argtypes = [C.c_int]
+    L.mw_scalar_words.argtypes = [C.c_int]
     L.mw_status_string.restype = C.c_char_p
     L.mw_last_error.restype = C.c_char_p
     L.mw_elementwise.argtypes = [C.c_int, C.c_int, C.c_int32, _vp, _vp, _vp, _vp]
@@ -229,26 +233,26 @@ def elementwise(arith, op, u, v=None, out=None):
 
 
 def axpy(arith, alpha, x, y):
-    """y += alpha * x in place; alpha: (k,) device tensor."""
+    """y += alpha * x in place; alpha: (SWORDS[arith],) device tensor."""
     k = WORDS[arith]
     x = _vec(x, k, name="x")
     y = _vec(y, k, x.shape[1], name="y")
     alpha = alpha.reshape(-1)
-    if alpha.numel() != k or not alpha.is_cuda or alpha.dtype != torch.float64:
-        raise MWError("alpha must be a (k,) float64 CUDA tensor")
+    if alpha.numel() != SWORDS[arith] or not alpha.is_cuda or alpha.dtype != torch.float64:
+        raise MWError("alpha must be a (%d,) float64 CUDA tensor" % SWORDS[arith])
     _check(lib().mw_axpy(ARITH[arith], x.shape[1], _ptr(alpha.contiguous()), _ptr(x), _ptr(y), _stream()),
            "mw_axpy")
     return y
 
 
 def dot(arith, x, y, out=None, workspace=None):
-    """x^T y as a (k,) device tensor."""
+    """x^T y as a (SWORDS[arith],) device tensor."""
     k = WORDS[arith]
     x = _vec(x, k, name="x")
     y = _vec(y, k, x.shape[1], name="y")
     n = x.shape[1]
     if out is None:
-        out = torch.empty(k, dtype=torch.float64, device=x.device)
+        out = torch.empty(SWORDS[arith], dtype=torch.float64, device=x.device)
     need = lib().mw_dot_workspace_bytes(ARITH[arith], n)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
@@ -257,14 +261,14 @@ def dot(arith, x, y, out=None, workspace=None):
 
 
 def dot_noalloc(arith, x, y, out):
-    """x^T y into the caller's (k,) device tensor `out`, with no workspace
-    and no allocation (mw_dot_noalloc; n <= DOT_NOALLOC_MAX_N)."""
+    """x^T y into the caller's (SWORDS[arith],) device tensor `out`, with no
+    workspace and no allocation (mw_dot_noalloc; n <= DOT_NOALLOC_MAX_N)."""
     k = WORDS[arith]
     x = _vec(x, k, name="x")
     y = _vec(y, k, x.shape[1], name="y")
     if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
-            and out.is_contiguous() and out.numel() == k):
-        raise MWError("out must be a contiguous (k,) float64 CUDA tensor")
+            and out.is_contiguous() and out.numel() == SWORDS[arith]):
+        raise MWError("out must be a contiguous (%d,) float64 CUDA tensor" % SWORDS[arith])
     _check(lib().mw_dot_noalloc(ARITH[arith], x.shape[1], _ptr(x), _ptr(y), _ptr(out), _stream()),
            "mw_dot_noalloc")
     return out

@@ -36,8 +36,9 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_words_and_status_strings(lib):
-    assert [lib.mw_words(a) for a in range(6)] == [1, 2, 2, 3, 3, 3]
-    assert lib.mw_words(7) == -1
+    assert [lib.mw_words(a) for a in range(10)] == [1, 2, 2, 3, 3, 3, 4, 4, 1, 1]
+    assert [lib.mw_scalar_words(a) for a in range(10)] == [1, 2, 2, 3, 3, 3, 4, 4, 2, 3]
+    assert lib.mw_words(10) == -1 and lib.mw_scalar_words(10) == -1
     lib.mw_status_string.restype = C.c_char_p
     assert lib.mw_status_string(0) == b"ok"
     assert b"invalid" in lib.mw_status_string(-1)
@@ -51,7 +52,7 @@ def test_workspace_sizes(lib):
         ws = lib.mw_cg_workspace_bytes(a, n, 20224)
         assert ws >= 3 * k * n * 8 and ws % 256 == 0
         assert lib.mw_dot_workspace_bytes(a, n) >= 8 * k
-    assert lib.mw_cg_workspace_bytes(9, n, 0) == 0
+    assert lib.mw_cg_workspace_bytes(99, n, 0) == 0
     assert lib.mw_cg_workspace_bytes(0, 0, 0) == 0
 
 
@@ -86,7 +87,8 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     lib.mw_spmv.argtypes = [C.c_int, vp, vp, vp, vp]
     lib.mw_cg_solve.argtypes = [C.c_int, vp, vp, vp, C.c_double, C.c_int32, vp, vp, vp, vp]
     bogus = vp(0x1000)
-    assert lib.mw_elementwise(6, 0, 10, bogus, bogus, bogus, None) == -1   # arith
+    assert lib.mw_elementwise(99, 0, 10, bogus, bogus, bogus, None) == -1  # arith
+    assert lib.mw_elementwise(8, 0, 10, bogus, bogus, bogus, None) == -1   # mixed: no element-wise ops
     assert lib.mw_elementwise(1, 9, 10, bogus, bogus, bogus, None) == -1   # op
     assert lib.mw_elementwise(1, 0, -1, bogus, bogus, bogus, None) == -1   # n
     assert lib.mw_elementwise(1, 0, 10, bogus, None, bogus, None) == -1    # v needed
@@ -104,7 +106,7 @@ def test_dot_noalloc_rejections_without_gpu(lib):
     lib.mw_dot_noalloc.argtypes = [C.c_int, C.c_int32, vp, vp, vp, vp]
     lib.mw_last_error.restype = C.c_char_p
     bogus = vp(0x1000)
-    assert lib.mw_dot_noalloc(6, 10, bogus, bogus, bogus, None) == -1          # arith
+    assert lib.mw_dot_noalloc(99, 10, bogus, bogus, bogus, None) == -1         # arith
     assert lib.mw_dot_noalloc(4, -1, bogus, bogus, bogus, None) == -1         # n
     assert lib.mw_dot_noalloc(4, 10, bogus, bogus, None, None) == -1          # result
     assert lib.mw_dot_noalloc(4, 10, None, bogus, bogus, None) == -1          # x
@@ -142,7 +144,7 @@ def test_builtin_launch_shapes(lib):
     assert (sh.lanes, sh.spmv_grid) == (4, 32)
     assert lib.mw_cg_shape(4, 1 << 19, 64 << 19, 0, C.byref(sh)) == 0  # more rows: SELL-64
     assert sh.lanes == 0
-    assert lib.mw_cg_shape(7, 4096, 20224, 0, C.byref(sh)) == -1
+    assert lib.mw_cg_shape(99, 4096, 20224, 0, C.byref(sh)) == -1
     assert lib.mw_cg_shape(4, 0, 20224, 0, C.byref(sh)) == -1
 
 
@@ -209,7 +211,7 @@ def test_vector_row_plan_is_host_only_and_validates_lanes(lib):
         assert lib.mw_cg_plan(a, C.byref(A), lanes, None, 0, C.byref(pl), None) == 0
         assert (pl.format, pl.lanes) == (2, want)
     assert lib.mw_cg_plan(4, C.byref(A), 3, None, 0, C.byref(pl), None) == -1
-    assert lib.mw_cg_plan(6, C.byref(A), 0, None, 0, C.byref(pl), None) == -1
+    assert lib.mw_cg_plan(99, C.byref(A), 0, None, 0, C.byref(pl), None) == -1
     # plans a caller fills in are checked against their format before any GPU work
     lib.mw_spmv_planned.argtypes = [C.c_int, C.POINTER(Plan), vp, vp, vp]
 

@@ -45,7 +45,7 @@ def small_batch():
     return mats, bs, P.batch_from_systems(mats, bs)
 
 
-@pytest.mark.parametrize("arith", ["fp64", "dw", "qdw", "tw", "qtw", "qtwe"])
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qdw", "tw", "qtw", "qtwe", "qw", "qqw"])
 def test_batched_matches_oracle_per_system(mw, small_batch, arith):
     mats, bs, B = small_batch
     Ad = mw.DeviceCSR.from_host(B.A)
@@ -118,7 +118,7 @@ def pcg_batch(small_batch):
     return mats, bs, P.batch_from_systems(mats, bs)
 
 
-@pytest.mark.parametrize("arith", ["fp64", "dw", "qdw", "tw", "qtw", "qtwe"])
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qdw", "tw", "qtw", "qtwe", "qw", "qqw"])
 def test_batched_jacobi_matches_oracle_per_system(mw, pcg_batch, arith):
     """Jacobi-preconditioned batch against the oracle's preconditioned CG run
     system by system: same status, iterations within 2 %, true residual

@@ -22,8 +22,8 @@ from paper_2510_13536_amd import problems as P
 
 pytestmark = pytest.mark.gpu
 
-ARITHS = ["fp64", "dw", "qdw", "tw", "qtw", "qtwe"]
-DOT_BOUND = {1: 2.0 ** -45, 2: 2.0 ** -100, 3: 2.0 ** -145}
+ARITHS = ["fp64", "dw", "qdw", "tw", "qtw", "qtwe", "qw", "qqw"]
+DOT_BOUND = {1: 2.0 ** -45, 2: 2.0 ** -100, 3: 2.0 ** -145, 4: 2.0 ** -195}
 
 
 @pytest.fixture(scope="module")
@@ -221,7 +221,7 @@ def test_spmv_integer_exact(mw, arith):
 # ---------------------------------------------------------------------- DOT
 
 @pytest.mark.parametrize("arith", ARITHS)
-@pytest.mark.parametrize("n", [1, 255, 2048, 2049, 100003])
+@pytest.mark.parametrize("n", [1, 255, 2048, 2049, 100003, 2 ** 21, 2 ** 21 + 5])
 def test_dot_within_bound(mw, arith, n):
     k = O.WORDS[arith]
     rng = np.random.default_rng(n + 7)
@@ -303,7 +303,8 @@ def test_cg_tight_tolerance(mw, arith):
     A = P.poisson2d(40, 30)
     xs = P.integer_vector(A.n, seed=3)
     b = A.matvec(xs)
-    tol = {"fp64": 1e-14, "dw": 1e-28, "qdw": 1e-28, "tw": 1e-40, "qtw": 1e-40, "qtwe": 1e-40}[arith]
+    tol = {"fp64": 1e-14, "dw": 1e-28, "qdw": 1e-28, "tw": 1e-40, "qtw": 1e-40, "qtwe": 1e-40,
+           "qw": 1e-55, "qqw": 1e-55}[arith]
     xg, ig, io = cg_parity(mw, arith, A, b, tol)
     # x_0 - x* is exact (x_0 is within a few units in the last place of the
     # integer); the lower words are then small enough to add in FP64
@@ -311,7 +312,8 @@ def test_cg_tight_tolerance(mw, arith):
     for w in range(1, xg.shape[0]):
         e = e + xg[w]
     err = np.abs(e).max() / np.abs(xs).max()
-    assert err < {"fp64": 1e-12, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-38, "qtwe": 1e-38}[arith]
+    assert err < {"fp64": 1e-12, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-38, "qtwe": 1e-38,
+                  "qw": 1e-53, "qqw": 1e-53}[arith]
 
 
 def _diag_indefinite(seed, n=24):
@@ -334,7 +336,8 @@ def _x_close(arith, xg, xo):
     return np.abs(e).max() / np.abs(xo[0]).max()
 
 
-X_BOUND = {"fp64": 1e-13, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-38, "qtwe": 1e-38}
+X_BOUND = {"fp64": 1e-13, "dw": 1e-26, "qdw": 1e-26, "tw": 1e-38, "qtw": 1e-38, "qtwe": 1e-38,
+           "qw": 1e-53, "qqw": 1e-53}
 
 
 @pytest.mark.parametrize("arith", ARITHS)
@@ -456,15 +459,16 @@ def test_cg_with_vector_row_plans(mw, arith):
     """CG on a matrix with long rows: with the plan the solver picks itself
     for such a matrix (average row length >= 32, n <= 2^18: vector rows) and
     with explicit vector-row plans.  The row sums are associated differently
-    from the oracle's CSR order, so the iteration counts may drift a little
-    further apart in FP64 (5 %) than in the multi-word arithmetics (2 %)."""
+    from the oracle's CSR order; the iteration counts stay within the 2 %
+    bar (measured over six seeds of this matrix: FP64 0.3-0.8 %, DW
+    0-0.5 %)."""
     A = _normal_matrix()
     b = A.matvec(np.random.default_rng(3).uniform(-1, 1, A.n))
     xo, io = O.cg_solve(arith, A, b, tol=1e-12)
     nb = np.linalg.norm(b)
     tro = O.true_residual(arith, A, b, xo) / nb
     Ad = mw.DeviceCSR.from_host(A)
-    slack = 0.05 if arith == "fp64" else 0.02
+    slack = 0.02
     for lanes in (None, 4, 32):
         plan = None if lanes is None else mw.Plan(Ad, rows=lanes)
         xg, ig = mw.cg_solve(arith, Ad, dev(b), tol=1e-12, plan=plan)
@@ -513,7 +517,13 @@ def test_solver_plan_choice_and_irregular_rows(mw, arith):
     assert i1["iters"] == i2["iters"]
     assert np.array_equal(host(x1).view(np.uint64), host(x2).view(np.uint64))
     assert i1["status"] == io["status"] == "ok"
-    slack = 0.05 if arith == "fp64" else 0.02
+    # FP64 on this matrix: 84 iterations against the oracle's 87.  Its rows
+    # of up to 2269 entries, summed by lane trees, round less than the
+    # oracle's sequential sums, and FP64 CG here moves toward the count of
+    # nearly exact arithmetic (DW: 75 iterations); moving five entries of b
+    # by one ulp changes the oracle's own FP64 count by one.  The 2 % bar
+    # holds for every multi-word arithmetic.
+    slack = 0.04 if arith == "fp64" else 0.02
     assert abs(i1["iters"] - io["iters"]) <= max(1, int(slack * io["iters"])), (i1["iters"], io["iters"])
     nb = np.linalg.norm(b)
     assert O.true_residual(arith, A, b, host(x1)) / nb <= 10 * O.true_residual(arith, A, b, xo) / nb
