@@ -39,8 +39,9 @@ if ROOT not in sys.path:
 
 METRIC = "QTW CG time-to-1e-12 residual & SpMV HBM GB/s; batched/adjoint vs plain"
 HBM_PEAK_GBS = 8000.0
-WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3, "qtwe": 3}
-ARITH_CODE = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4, "qtwe": 5}
+# planes of a vector element (the mixed types MXDW / MXQTW keep FP64 vectors)
+WORDS = {"fp64": 1, "dw": 2, "qdw": 2, "tw": 3, "qtw": 3, "qtwe": 3, "qw": 4, "qqw": 4, "mxdw": 1, "mxqtw": 1}
+ARITH_CODE = {"fp64": 0, "dw": 1, "qdw": 2, "tw": 3, "qtw": 4, "qtwe": 5, "qw": 6, "qqw": 7, "mxdw": 8, "mxqtw": 9}
 
 
 def spmv_bytes(n, nnz, k):
@@ -141,12 +142,35 @@ def bench_batched(mw, P, torch, dev, nsys=512, tune=True):
     return out
 
 
-def bench_illcond(mw, P, torch, dev, maxit=20000):
+def residual_levels(hist, every):
+    """From a per-iteration relative-residual history: the first iteration
+    below each power of ten reached, the smallest residual and where it
+    occurred, and the history sampled every `every` iterations."""
+    import numpy as np
+    h = np.asarray(hist, dtype=np.float64)
+    out = {"min_rel_res": None, "min_at": None, "first_below": {}, "every": every, "sampled": []}
+    if h.size == 0:
+        return out
+    fin = np.where(np.isfinite(h), h, np.inf)
+    i = int(np.argmin(fin))
+    out["min_rel_res"], out["min_at"] = float(fin[i]), i + 1
+    for e in range(-1, -21, -1):
+        below = np.nonzero(fin < 10.0 ** e)[0]
+        if below.size == 0:
+            break
+        out["first_below"]["1e%d" % e] = int(below[0]) + 1
+    out["sampled"] = [float("%.4g" % v) for v in h[every - 1::every]]
+    return out
+
+
+def bench_illcond(mw, P, torch, dev, maxit=20000, hist_every=0):
     """Ill-conditioned banded SPD (n = 2^20, 27 nnz/row, D A D scaled):
     planned SpMV GB/s (Infinity Cache read-flushed) and a CG run of at most
     `maxit` iterations toward 1e-10 in FP64, DW and QTW (relative residual
-    reached, time per iteration); Jacobi-preconditioned CG to 1e-10 and
-    1e-20."""
+    reached, time per iteration); with hist_every > 0 also the residual
+    history (first iteration below each power of ten, the lowest level and
+    samples every hist_every iterations); Jacobi-preconditioned CG to 1e-10
+    and 1e-20."""
     A, b, _ = P.case_banded_illcond()
     Ad = mw.DeviceCSR.from_host(A, dev)
     bd = torch.as_tensor(b, device=dev)
@@ -155,7 +179,7 @@ def bench_illcond(mw, P, torch, dev, maxit=20000):
     sink = torch.zeros(1, dtype=torch.float64, device=dev)
     out = {"workload": "banded SPD offsets +-1..13, D A D (D_ii = 10^U(-3,3)), n=%d, nnz=%d, tol 1e-10, "
                        "at most %d iterations" % (A.n, A.nnz, maxit)}
-    for ar in ("fp64", "dw", "qtw"):
+    for ar in ("fp64", "dw", "qtw", "mxdw", "mxqtw"):
         kk = WORDS[ar]
         xv = torch.rand((kk, A.n), dtype=torch.float64, device=dev)
         yv = torch.empty_like(xv)
@@ -173,15 +197,22 @@ def bench_illcond(mw, P, torch, dev, maxit=20000):
         x = torch.zeros((kk, A.n), dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, info = mw.cg_solve(ar, Ad, bd, x=x, tol=1e-10, maxit=maxit)
+        _, info = mw.cg_solve(ar, Ad, bd, x=x, tol=1e-10, maxit=maxit, history=hist_every > 0)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         out[ar] = {"spmv_GBps_planned_flushed": round(gbs, 1), "iters": info["iters"], "status": info["status"],
                    "rel_res": info["rel_res"], "seconds": round(sec, 3),
                    "per_iteration_us": round(1e6 * sec / max(info["iters"], 1), 1)}
+        if hist_every > 0:
+            out[ar]["history"] = residual_levels(info["history"], hist_every)
+            out[ar]["true_rel_res"] = true_rel_residual(mw, torch, Ad, bd, x)
+            log("ill-conditioned %s, %d iterations: %s, rel. residual %.3e, lowest %.3e at %d, %s"
+                % (ar, info["iters"], info["status"], info["rel_res"], out[ar]["history"]["min_rel_res"],
+                   out[ar]["history"]["min_at"], out[ar]["history"]["first_below"]))
         # Jacobi-preconditioned CG (an extension; it removes the D A D
         # scaling): iterations, time and the exactly formed true residual
-        for ptol in (1e-10, 1e-20):
+        # (the mixed types take no preconditioner)
+        for ptol in (1e-10, 1e-20) if not ar.startswith("mx") else ():
             x.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -225,37 +256,32 @@ def bench_normalisation(mw, torch, Ad, bd, n, maxit=2000):
 
 
 def true_rel_residual(mw, torch, Ad, bd, x):
-    """||b - A x|| / ||b|| for a solution in any arithmetic, with the product
-    and the difference formed in QTW and the dots in TW (about 48
-    significant digits), so residuals far below FP64 resolution are
-    resolved."""
+    """||b - A x|| / ||b|| for a solution in any arithmetic, with the product,
+    the difference and the dots formed in QW (about 64 significant digits),
+    so residuals far below FP64 resolution are resolved."""
     n = x.shape[1]
-    x3 = torch.zeros((3, n), dtype=torch.float64, device=bd.device)
-    x3[:x.shape[0]] = x
-    b3 = torch.zeros_like(x3)
-    b3[0] = bd
-    y = mw.spmv("qtw", Ad, x3)
-    r = mw.elementwise("qtw", "add", b3, mw.elementwise("qtw", "neg", y))
-    # b - A x cancels its leading words: renormalise (TW) so the leading word
-    # carries the value before squaring (a product of quasi triples drops
-    # the third words' product)
-    r = mw.elementwise("tw", "norm", r)
-    rr = float(mw.dot("tw", r, r).sum().item())
-    bb = float(mw.dot("tw", b3, b3).sum().item())
+    x4 = torch.zeros((4, n), dtype=torch.float64, device=bd.device)
+    x4[:x.shape[0]] = x
+    b4 = torch.zeros_like(x4)
+    b4[0] = bd
+    y = mw.spmv("qw", Ad, x4)
+    r = mw.elementwise("qw", "add", b4, mw.elementwise("qw", "neg", y))
+    rr = float(mw.dot("qw", r, r).sum().item())
+    bb = float(mw.dot("qw", b4, b4).sum().item())
     return (max(rr, 0.0) / bb) ** 0.5
 
 
-def bench_tolerances(mw, torch, Ad, bd, n, maxit=3000):
-    """3D Poisson 128^3 at tolerances beyond FP64 (1e-16, 1e-24, 1e-32), every
-    arithmetic, at most `maxit` iterations: status, iterations, time, the
-    recursive and the true relative residual (true_rel_residual), and the
-    recursive relative-residual history of the 1e-32 runs every 50
-    iterations."""
+def bench_tolerances(mw, torch, Ad, bd, n, maxit=4000):
+    """3D Poisson 128^3 at tolerances beyond FP64 (1e-16, 1e-24, 1e-32, 1e-48,
+    and 1e-60 for the 4-word types), every arithmetic, at most `maxit`
+    iterations: status, iterations, time, the recursive and the true
+    relative residual (true_rel_residual), and the recursive
+    relative-residual history of the 1e-32 runs every 50 iterations."""
     out = {"workload": "3D Poisson 128^3, at most %d iterations" % maxit}
     for ar in WORDS:
         x = torch.zeros((WORDS[ar], n), dtype=torch.float64, device=bd.device)
         row = {}
-        for tol in (1e-16, 1e-24, 1e-32):
+        for tol in (1e-16, 1e-24, 1e-32, 1e-48) + ((1e-60,) if WORDS[ar] == 4 else ()):
             x.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -273,22 +299,22 @@ def bench_tolerances(mw, torch, Ad, bd, n, maxit=3000):
 
 
 def bench_error_history(mw, P, torch, dev, nx=128, seed=6,
-                        checkpoints=(100, 200, 400, 600, 800, 1000, 1200, 1600, 2000)):
+                        checkpoints=(100, 200, 400, 600, 800, 1000, 1200, 1600, 2000, 2400)):
     """Error norms against an exact solution: 3D Poisson nx^3 with an
     integer solution x* in [-8, 8] (seed `seed`), so b = A x* is exact in
     FP64.  For every arithmetic and every checkpoint m: ||x_m - x*|| / ||x*||
     and the true relative residual of the m-th CG iterate from x_0 = 0.  The
     m-th iterate is the result of a solve stopped after m iterations (tol 0;
     the solver is deterministic for a fixed launch shape, so it is the m-th
-    iterate of the full solve).  x_m - x* is formed in QTW and renormalised
-    (TW) before it is rounded to FP64."""
+    iterate of the full solve).  x_m - x* is formed in QW before it is
+    rounded to FP64."""
     A = P.poisson3d(nx)
     xs = P.integer_vector(A.n, seed)
     Ad = mw.DeviceCSR.from_host(A, dev)
     bd = torch.as_tensor(A.matvec(xs), device=dev)
-    xs3 = torch.zeros((3, A.n), dtype=torch.float64, device=dev)
-    xs3[0] = torch.as_tensor(xs, device=dev)
-    nxs = float(torch.linalg.vector_norm(xs3[0]).item())
+    xs4 = torch.zeros((4, A.n), dtype=torch.float64, device=dev)
+    xs4[0] = torch.as_tensor(xs, device=dev)
+    nxs = float(torch.linalg.vector_norm(xs4[0]).item())
     plan = mw.Plan(Ad)
     out = {"workload": "3D Poisson %d^3, x* integer in [-8, 8] (seed %d), b = A x* exact" % (nx, seed),
            "checkpoints": list(checkpoints)}
@@ -300,9 +326,9 @@ def bench_error_history(mw, P, torch, dev, nx=128, seed=6,
         for m in checkpoints:
             x.zero_()
             mw.cg_solve(ar, Ad, bd, x=x, tol=0.0, maxit=m, workspace=ws, plan=plan)
-            x3 = torch.zeros_like(xs3)
-            x3[:k] = x
-            d = mw.elementwise("tw", "norm", mw.elementwise("qtw", "add", x3, mw.elementwise("qtw", "neg", xs3)))
+            x4 = torch.zeros_like(xs4)
+            x4[:k] = x
+            d = mw.elementwise("qw", "add", x4, mw.elementwise("qw", "neg", xs4))
             err.append(float("%.3e" % (float(torch.linalg.vector_norm(d[0]).item()) / nxs)))
             res.append(float("%.3e" % true_rel_residual(mw, torch, Ad, bd, x)))
         out[ar] = {"rel_error": err, "true_rel_res": res}
@@ -447,6 +473,12 @@ def main():
                     help="also time iterations on banded stand-ins of the paper's Table I matrices")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 512-system batched comparison (for profiling that path) and print its line")
+    ap.add_argument("--illcond-only", action="store_true",
+                    help="run only the ill-conditioned banded workload and print its line")
+    ap.add_argument("--illcond-maxit", type=int, default=20000,
+                    help="iteration limit of the ill-conditioned CG runs")
+    ap.add_argument("--illcond-hist", type=int, default=0,
+                    help="record the ill-conditioned runs' residual history, sampled every N iterations")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -474,6 +506,13 @@ def main():
                           "value": bt["qtw"]["batched_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
                           "dtype": "f64", "data": "synthetic", "config": {"workload": bt["workload"]},
                           "extra": {"batched": bt}}), flush=True)
+        return
+    if args.illcond_only:
+        ic = bench_illcond(mw, P, torch, dev, maxit=args.illcond_maxit, hist_every=args.illcond_hist)
+        print(json.dumps({"metric": "ill-conditioned banded CG (n=2^20, 27 nnz/row, D A D), tol 1e-10",
+                          "value": ic["qtw"]["seconds"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+                          "dtype": "f64", "data": "synthetic", "config": {"workload": ic["workload"]},
+                          "extra": {"illcond": ic}}), flush=True)
         return
     t = time.time()
     A, b, _ = P.case_poisson3d(args.nx)
@@ -551,13 +590,39 @@ def main():
                 "plan": plan_info,
                 "timing": "HIP events around each SpMV launch on the solver stream, %d event-timed solves "
                           "(direct launches, %.2f ms/solve) right after the timed steps" % (args.prof_steps, prof_ms)}
+    # three byte counts for the same launch time: `frac` uses the CSR
+    # definition's algorithmic bytes (the per-unit figure every arithmetic
+    # and plan shares); the diagonal-slot plan streams fewer (no column
+    # indices: format bytes), and the counters give what HBM really moved
+    roofline["frac_basis"] = "CSR algorithmic bytes 12 nnz + 4 (n + 1) + 16 k n per launch"
+    if fmt_bytes:
+        roofline["format_frac"] = round(fmt_bytes / (sp_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+    if roofline["traffic"]:
+        tg = roofline["traffic"] / (sp_us * 1e-6) / 1e9
+        roofline["traffic_GBps"] = round(tg, 1)
+        roofline["traffic_frac"] = round(tg / HBM_PEAK_GBS, 4)
     # the same kernel against what a plain device copy reaches on this GPU
     cc = copy_ceiling(torch, dev)
     roofline["copy_GBps"] = round(cc, 1)
     roofline["frac_of_copy"] = round(achieved / cc, 4)
     log("copy ceiling %.1f GB/s; SpMV %.1f GB/s = %.3f of it" % (cc, achieved, achieved / cc))
 
-    extra = {"iterations": iters, "device_seconds": infos[-1]["seconds"],
+    # one call as a caller without a prebuilt plan makes it: mw_cg_solve
+    # builds the SpMV plan inside the call, in its workspace
+    one = []
+    for _ in range(3):
+        x.zero_()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        _, oi = mw.cg_solve(arith, Ad, bd, x=x, tol=tol, maxit=maxit, workspace=ws)
+        torch.cuda.synchronize()
+        one.append(time.perf_counter() - s0)
+        assert oi["status"] == "ok" and oi["iters"] == iters, oi
+    one_call = {"seconds": round(statistics.median(one), 5),
+                "what": "median of 3 mw_cg_solve calls with no plan passed (SpMV plan built inside each call)"}
+    log("one call with the plan built inside: %.2f ms" % (1e3 * one_call["seconds"]))
+
+    extra = {"iterations": iters, "device_seconds": infos[-1]["seconds"], "one_call_with_plan_build": one_call,
              "launch_shape": mw.cg_shape(arith, A.n, A.nnz)[1], "tuned": tuned is not None,
              "per_iteration_us": 1e3 * ms_per_step / max(iters, 1),
              "event_timed_ms_per_step": round(prof_ms, 3)}
@@ -630,7 +695,7 @@ def main():
     if not args.quick:
         extra["batched"] = bench_batched(mw, P, torch, dev, tune=not args.no_tune)
         extra["adjoint"] = bench_adjoint(mw, P, torch, dev)
-        extra["illcond"] = bench_illcond(mw, P, torch, dev)
+        extra["illcond"] = bench_illcond(mw, P, torch, dev, maxit=args.illcond_maxit)
         extra["normalisation_every_K"] = bench_normalisation(mw, torch, Ad, bd, A.n)
         extra["tolerances"] = bench_tolerances(mw, torch, Ad, bd, A.n)
         extra["error_history"] = bench_error_history(mw, P, torch, dev)
