@@ -226,22 +226,32 @@ def bench_illcond(mw, P, torch, dev, maxit=20000, hist_every=0):
 
 
 def bench_normalisation(mw, torch, Ad, bd, n, maxit=2000):
-    """3D Poisson 128^3, QDW and QTW, tol 1e-12: r normalised every K-th
-    iteration (K = 1 is the paper's placement, 0 never): status, iterations,
-    time; and QTWE, VecSum3 after every operation (the other end of the
-    placement range; for QDW that placement is DW itself)."""
+    """3D Poisson 128^3, QDW, QTW and QQW, tol 1e-12: r normalised every K-th
+    iteration (K = 1 is the paper's placement, 0 never), and the placement
+    variant that normalises p with r ("K=..+p"): status, iterations, time;
+    for the variant also the true residual at tol 1e-30 (QDW) / 1e-44 (QTW,
+    QQW) against K = 1's; and QTWE, VecSum3 after every operation (the other
+    end of the placement range; for QDW that placement is DW itself)."""
     out = {"workload": "3D Poisson 128^3, tol 1e-12, at most %d iterations" % maxit}
-    for ar in ("qdw", "qtw"):
+    for ar in ("qdw", "qtw", "qqw"):
         x = torch.zeros((WORDS[ar], n), dtype=torch.float64, device=bd.device)
         row = {}
-        for K in (1, 2, 4, 8, 0):
+        for K, npz in ((1, False), (2, False), (4, False), (8, False), (0, False),
+                       (2, True), (8, True), (32, True), (64, True)):
             x.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, info = mw.cg_solve(ar, Ad, bd, x=x, tol=1e-12, maxit=maxit, normalize=K)
+            _, info = mw.cg_solve(ar, Ad, bd, x=x, tol=1e-12, maxit=maxit, normalize=K, normalize_p=npz)
             torch.cuda.synchronize()
-            row["K=%d" % K] = {"status": info["status"], "iters": info["iters"], "rel_res": info["rel_res"],
-                               "seconds": round(time.perf_counter() - t0, 4)}
+            row["K=%d%s" % (K, "+p" if npz else "")] = {
+                "status": info["status"], "iters": info["iters"], "rel_res": info["rel_res"],
+                "seconds": round(time.perf_counter() - t0, 4)}
+        tight = 1e-30 if WORDS[ar] == 2 else 1e-44
+        for K, npz in ((1, False), (8, True), (64, True)):
+            x.zero_()
+            _, info = mw.cg_solve(ar, Ad, bd, x=x, tol=tight, maxit=3 * maxit, normalize=K, normalize_p=npz)
+            row["tol_%g_K=%d%s" % (tight, K, "+p" if npz else "")] = {
+                "status": info["status"], "iters": info["iters"], "true_rel_res": true_rel_residual(mw, torch, Ad, bd, x)}
         out[ar] = row
         log("normalisation %s: %s" % (ar, row))
     x = torch.zeros((3, n), dtype=torch.float64, device=bd.device)

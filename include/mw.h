@@ -236,6 +236,15 @@ typedef struct {
                            MW_UNT environment overrides and the built-in
                            shape.  chunk above takes precedence over
                            shape->chunk.  Invalid values: MW_EINVAL.       */
+    int32_t normalize_p;  /* 0 (default): only r is normalised (Sec. IV-D).
+                           1: in the iterations that normalise r, p is
+                           normalised too, as it enters p = r + beta p (a
+                           placement variant for the frequency question of
+                           Sec. VI: with it every normalize = K converges
+                           where r alone breaks down).  Plain CG of the
+                           single solver only; other values, or with a
+                           preconditioner or the batched solver:
+                           MW_EINVAL.                                      */
 } mw_cg_opts_t;
 
 /* Number of FP64 words (planes) of a vector element of an arithmetic:

@@ -820,7 +820,9 @@ typedef struct {
  *     QDW/QTW/QQW: r = normalise(r) when normalise_r = K > 0 and the iteration
  *       number (1, 2, ...) is a multiple of K; K = 1, every iteration, is
  *       Sec. IV-D; K = 0 never (the "-NN" variants of Sec. V-B); other K
- *       explore the frequency the paper leaves open (Sec. VI)
+ *       explore the frequency the paper leaves open (Sec. VI).  With
+ *       normalise_p, p is normalised in the same iterations (after its x
+ *       update): a placement variant, not the paper's
  *     rho' = r^T r;  iters++
  *     sqrt(fp64(rho')) / nb < tol: converged               (Sec. IV-C)
  *     iters == maxit: not converged
@@ -828,9 +830,20 @@ typedef struct {
  * FP64 uses fma for every a*x + y.  `hist`, when non-null, receives the
  * relative residual of every iteration (maxit entries at most).
  */
+int mwo_cg_solve_np(int arith, long n, const int32_t *row_ptr, const int32_t *col,
+                    const double *val, const double *b, double *x, double tol,
+                    int32_t maxit, int32_t normalise_r, int32_t normalise_p, mwo_cg_info *info, double *hist);
+
 int mwo_cg_solve(int arith, long n, const int32_t *row_ptr, const int32_t *col,
                  const double *val, const double *b, double *x, double tol,
                  int32_t maxit, int32_t normalise_r, mwo_cg_info *info, double *hist)
+{
+    return mwo_cg_solve_np(arith, n, row_ptr, col, val, b, x, tol, maxit, normalise_r, 0, info, hist);
+}
+
+int mwo_cg_solve_np(int arith, long n, const int32_t *row_ptr, const int32_t *col,
+                    const double *val, const double *b, double *x, double tol,
+                    int32_t maxit, int32_t normalise_r, int32_t normalise_p, mwo_cg_info *info, double *hist)
 {
     int k = words_of(arith);
     if (k < 0 || n <= 0 || !(tol >= 0.0) || maxit < 0 || !info) return MWO_EINVAL;
@@ -879,7 +892,10 @@ int mwo_cg_solve(int arith, long n, const int32_t *row_ptr, const int32_t *col,
                 mwv pi = mw_load(k, p, n, i), qi = mw_load(k, q, n, i);
                 mw_store(k, x, n, i, mw_add(arith, mw_load(k, x, n, i), mw_mul(arith, alpha, pi)));
                 mwv ri = mw_add(arith, mw_load(k, r, n, i), mw_neg(mw_mul(arith, alpha, qi)));
-                if (quasi && normalise_r > 0 && (info->iters + 1) % normalise_r == 0) ri = mw_normalise(arith, ri);
+                if (quasi && normalise_r > 0 && (info->iters + 1) % normalise_r == 0) {
+                    ri = mw_normalise(arith, ri);
+                    if (normalise_p) mw_store(k, p, n, i, mw_normalise(arith, pi));
+                }
                 mw_store(k, r, n, i, ri);
             }
         }

@@ -52,6 +52,8 @@ def _load(name):
                                  C.c_int32, C.c_int32, C.POINTER(CGInfo), _dp]
     lib.mwo_pcg_jacobi_solve.argtypes = [C.c_int, C.c_long, _ip, _ip, _dp, _dp, _dp, C.c_double,
                                          C.c_int32, C.c_int32, C.POINTER(CGInfo), _dp]
+    lib.mwo_cg_solve_np.argtypes = [C.c_int, C.c_long, _ip, _ip, _dp, _dp, _dp, C.c_double,
+                                    C.c_int32, C.c_int32, C.c_int32, C.POINTER(CGInfo), _dp]
     lib.mwo_cg_mixed_solve.argtypes = [C.c_int, C.c_long, _ip, _ip, _dp, _dp, _dp, C.c_double,
                                        C.c_int32, C.POINTER(CGInfo), _dp]
     lib.mwo_exact_dot_limbs.argtypes = [C.c_int, C.c_long, _dp, _dp, _u64p]
@@ -191,7 +193,7 @@ def axpy(arith, alpha, x, y):
 
 
 def cg_solve(arith, A, b, x0=None, tol=1e-12, maxit=None, normalise=True, history=False, precond=None,
-             mixed=False):
+             mixed=False, normalise_p=False):
     """CG per the oracle.  Returns (x (k, n), info dict).
 
     mixed=True (an arithmetic of two or more words): FP64 vectors, the SpMV
@@ -201,7 +203,9 @@ def cg_solve(arith, A, b, x0=None, tol=1e-12, maxit=None, normalise=True, histor
     normalise (QDW/QTW): True / 1 normalises r every iteration (Sec. IV-D),
     False / 0 never; an integer K > 1 in iterations K, 2K, ...
     precond: None (Alg. 1) or "jacobi" (preconditioned CG with the FP64
-    reciprocal diagonal, mwo_pcg_jacobi_solve)."""
+    reciprocal diagonal, mwo_pcg_jacobi_solve).
+    normalise_p (plain CG): also normalise p in the iterations that
+    normalise r (a placement variant, not the paper's)."""
     if precond not in (None, "jacobi"):
         raise ValueError("precond must be None or 'jacobi'")
     if mixed and (precond is not None or WORDS[arith] < 2):
@@ -219,6 +223,11 @@ def cg_solve(arith, A, b, x0=None, tol=1e-12, maxit=None, normalise=True, histor
     if mixed:
         rc = lib().mwo_cg_mixed_solve(ARITH[arith], n, _i(rp), _i(ci), _d(va), _d(b), _d(x), float(tol),
                                       int(maxit), C.byref(info), _d(hist) if history else None)
+    elif normalise_p:
+        if precond is not None:
+            raise ValueError("normalise_p applies to plain CG")
+        rc = lib().mwo_cg_solve_np(ARITH[arith], n, _i(rp), _i(ci), _d(va), _d(b), _d(x), float(tol),
+                                   int(maxit), int(normalise), 1, C.byref(info), _d(hist) if history else None)
     else:
         fn = lib().mwo_pcg_jacobi_solve if precond == "jacobi" else lib().mwo_cg_solve
         rc = fn(ARITH[arith], n, _i(rp), _i(ci), _d(va), _d(b), _d(x), float(tol),

@@ -766,7 +766,7 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
 {
     mwh::clear_error();
     if (!batched_args_ok(a, nsys, sys_row_off, A, b, x, workspace) || !(tol >= 0.0) || maxit < 0) return MW_EINVAL;
-    if (opts && (!shape_valid(opts->shape) || opts->normalize < 0 ||
+    if (opts && (!shape_valid(opts->shape) || opts->normalize < 0 || opts->normalize_p != 0 ||
                  (opts->precond != MW_PRECOND_NONE && opts->precond != MW_PRECOND_JACOBI)))
         return MW_EINVAL;
     MW_CSR_GUARD(A, stream);

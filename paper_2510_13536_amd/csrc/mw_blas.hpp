@@ -38,7 +38,7 @@ struct CgState {
     int32_t stopped;     // set once, when the solve stops (polled by the host)
     int32_t status;      // final status (valid once stopped)
     int32_t iters_final; // final iteration count (valid once stopped)
-    int32_t pad;
+    int32_t normalize_p; // quasi types: p normalised with r (a placement variant)
 };
 // Loads of the matrix stream in the planned SpMV.  For 3- and 4-word vectors
 // the CG working set (four vectors of 24 or 32 bytes per row) competes with the

@@ -326,6 +326,11 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
     // alpha of iteration k (slot kpos) and, with XR = 2 and kpos = 1, of k - 1
     const Num<A> ak = load_scalar<A>(st->alpha[kpos]);
     const bool two = XR == 2 && kpos == 1;
+    // the placement variant normalize_p: in the iterations that normalise
+    // r, p_k is normalised as it enters p_{k+1} = r + beta p_k (x takes p_k
+    // as the SpMV read it)
+    const int NK = st->normalize;
+    const bool normp = is_quasi(A) && !PC && st->normalize_p && NK > 0 && (st->iters[par ^ 1] + 1) % NK == 0;
     const Num<A> a0 = two ? load_scalar<A>(st->alpha[0]) : zero<A>();
     for (int m = 0; m < tw.count; ++m) {
         const long i = (long)tw[m] * UNT + threadIdx.x;
@@ -351,7 +356,7 @@ __global__ void __launch_bounds__(UNT) mw_cg_step_p_kernel(int n, int nslots_in,
         }
         if (!stop) {
             if constexpr (PC) store_il<A>(pn, n, i, axpy_term<A>(be, pi, jacobi<A>(dinv[i], rv)));
-            else store_il<A>(pn, n, i, axpy_term<A>(be, pi, rv));
+            else store_il<A>(pn, n, i, axpy_term<A>(be, normp ? normalise<A>(pi) : pi, rv));
         }
     }
 }
@@ -386,7 +391,7 @@ CgLayout cg_layout(int a, int32_t n, int32_t nnz)
 
 // Host copy of the integer part of CgState (from `run` on).
 struct Flags {
-    int32_t run[2], iters[2], brk[2], maxit, normalize, stopped, status, iters_final, pad;
+    int32_t run[2], iters[2], brk[2], maxit, normalize, stopped, status, iters_final, normalize_p;
 };
 
 Flags *pinned_flags()
@@ -607,6 +612,7 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     h.tol = tol;
     h.maxit = maxit;
     h.normalize = opts ? opts->normalize : 1;
+    h.normalize_p = opts ? opts->normalize_p : 0;
     h.history = opts ? opts->history : nullptr;
     HIP_TRY(hipMemcpyAsync(st, &h, sizeof(CgState), hipMemcpyHostToDevice, s));
 
@@ -756,6 +762,11 @@ int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, dou
     if (opts && opts->plan && (!plan_valid(opts->plan) || opts->plan->n != A->n || opts->plan->csr.row_ptr != A->row_ptr))
         return MW_EINVAL;
     if (opts && (!shape_valid(opts->shape) || opts->normalize < 0)) return MW_EINVAL;
+    if (opts && (opts->normalize_p < 0 || opts->normalize_p > 1 ||
+                 (opts->normalize_p && opts->precond != MW_PRECOND_NONE))) {
+        set_error("mw_cg_solve: normalize_p is 0 or 1, and applies to plain CG only");
+        return MW_EINVAL;
+    }
     if (opts && opts->precond != MW_PRECOND_NONE && opts->precond != MW_PRECOND_JACOBI) return MW_EINVAL;
     if (opts && opts->precond != MW_PRECOND_NONE && mixed_arith(a)) {
         set_error("mw_cg_solve: the mixed-precision arithmetics take no preconditioner");

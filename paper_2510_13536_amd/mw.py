@@ -86,7 +86,7 @@ class Shape(C.Structure):
 class CgOpts(C.Structure):
     _fields_ = [("normalize", C.c_int32), ("chunk", C.c_int32), ("history", _vp),
                 ("prof", C.POINTER(CgProf)), ("plan", C.POINTER(SpmvPlan)), ("no_graph", C.c_int32),
-                ("precond", C.c_int32), ("shape", C.POINTER(Shape))]
+                ("precond", C.c_int32), ("shape", C.POINTER(Shape)), ("normalize_p", C.c_int32)]
 
 
 PRECOND = {None: 0, "jacobi": 1}
@@ -371,7 +371,7 @@ def cg_workspace(arith, A, device=None):
 
 
 def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0, history=False,
-             workspace=None, prof=None, plan=None, graph=True, shape=None, precond=None):
+             workspace=None, prof=None, plan=None, graph=True, shape=None, precond=None, normalize_p=False):
     """Solve A x = b by CG in `arith`.  Returns (x (k, n) tensor, info dict).
 
     prof: a CgProf to accumulate per-kernel device times into (optional);
@@ -380,7 +380,8 @@ def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0
     graph: replay captured chunks (True) or launch kernels directly;
     shape: launch shape (Shape or dict of its fields; optional);
     precond: None (Alg. 1) or "jacobi" (preconditioned CG, M^-1 the FP64
-    reciprocal diagonal)."""
+    reciprocal diagonal);
+    normalize_p: quasi types, normalise p with r (a placement variant)."""
     if precond not in PRECOND:
         raise MWError("precond must be None or 'jacobi'")
     k = WORDS[arith]
@@ -399,7 +400,7 @@ def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0
     opts = CgOpts(int(normalize), int(chunk), hist.data_ptr() if hist is not None else None,
                   C.pointer(prof) if prof is not None else None,
                   C.pointer(plan.c) if plan is not None else None, 0 if graph else 1, PRECOND[precond],
-                  C.pointer(sh) if sh is not None else None)
+                  C.pointer(sh) if sh is not None else None, 1 if normalize_p else 0)
     info = CgInfo()
     csr = A.c()
     rc = lib().mw_cg_solve(ARITH[arith], C.byref(csr), _ptr(b), _ptr(x), float(tol), int(maxit),

@@ -681,6 +681,28 @@ def test_cg_normalisation_frequency(mw, arith):
         mw.cg_solve(arith, Ad, bd, normalize=-1)
 
 
+@pytest.mark.parametrize("arith", ["qdw", "qtw", "qqw"])
+@pytest.mark.parametrize("K", [2, 8])
+def test_cg_normalise_r_and_p(mw, arith, K):
+    """The placement variant normalize_p (p normalised with r in iterations
+    K, 2K, ...): on C1 it converges where normalising r alone breaks down.
+    Against the oracle's variant: same status, iterations within 2 %, true
+    residual within 10x; graph replay and direct launches give the same
+    bits; with a preconditioner it is rejected."""
+    A, b, _ = P.case_poisson2d_64()
+    Ad = mw.DeviceCSR.from_host(A)
+    xo, io = O.cg_solve(arith, A, b, tol=1e-12, normalise=K, normalise_p=True)
+    xg, ig = mw.cg_solve(arith, Ad, dev(b), tol=1e-12, normalize=K, normalize_p=True)
+    assert ig["status"] == io["status"] == "ok"
+    assert abs(ig["iters"] - io["iters"]) <= max(1, int(0.02 * io["iters"])), (ig, io)
+    tro = O.true_residual(arith, A, b, xo)
+    assert O.true_residual(arith, A, b, host(xg)) <= 10 * tro
+    xd, idd = mw.cg_solve(arith, Ad, dev(b), tol=1e-12, normalize=K, normalize_p=True, graph=False)
+    assert idd["iters"] == ig["iters"] and np.array_equal(host(xd).view(np.uint64), host(xg).view(np.uint64))
+    with pytest.raises(mw.MWError):
+        mw.cg_solve(arith, Ad, dev(b), normalize=K, normalize_p=True, precond="jacobi")
+
+
 # ----------------------------------------------------------- planned SpMV
 
 @pytest.mark.parametrize("arith", ARITHS)

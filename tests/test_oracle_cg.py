@@ -266,9 +266,14 @@ def test_normalise_every_second_iteration_mechanism(arith):
     assert ov2[-1] > 1e4 * ov1[-1]
     # geometric growth: every ten iterations multiply the overlap by >= 10
     assert np.all(ov2[19::10] > 10 * ov2[9:-10:10])
-    # and the K = 2 solve itself breaks down
+    # and the K = 2 solve itself breaks down, while with p normalised too
+    # every K up to 8 converges like K = 1
     _, hb = O.cg_solve(arith, A, b, tol=1e-12, maxit=400, normalise=2)
     assert hb["status"] == "breakdown"
+    _, h1 = O.cg_solve(arith, A, b, tol=1e-12, maxit=400, normalise=1)
+    for K in (2, 4, 8):
+        _, hp = O.cg_solve(arith, A, b, tol=1e-12, maxit=400, normalise=K, normalise_p=True)
+        assert hp["status"] == "ok" and abs(hp["iters"] - h1["iters"]) <= 2
 
 
 @pytest.mark.parametrize("arith", ARITHS)

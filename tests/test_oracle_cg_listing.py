@@ -103,7 +103,7 @@ class Ops:
         return acc
 
 
-def reading_cg(arith, A, b, x0, tol, maxit, normalise=1, jacobi=False):
+def reading_cg(arith, A, b, x0, tol, maxit, normalise=1, jacobi=False, normalise_p=False):
     """CG (or Jacobi PCG) per Alg. 1 and the readings above.  Returns
     (x as k planes, iters, status, history)."""
     ops = Ops(arith)
@@ -149,6 +149,8 @@ def reading_cg(arith, A, b, x0, tol, maxit, normalise=1, jacobi=False):
         r = [ops.axmy(alpha, q[i], r[i]) for i in range(n)]
         if arith in QUASI and normalise > 0 and (it + 1) % normalise == 0:
             r = [ops.norm(v) for v in r]
+            if normalise_p:
+                p = [ops.norm(v) for v in p]
         if jacobi:
             z = [ops.dxmul(d[i], r[i]) for i in range(n)]
         else:
@@ -192,12 +194,12 @@ def systems():
 SYS = systems()
 
 
-def compare(arith, A, b, x0=None, tol=1e-300, maxit=8, normalise=1, jacobi=False):
+def compare(arith, A, b, x0=None, tol=1e-300, maxit=8, normalise=1, jacobi=False, normalise_p=False):
     k = O.WORDS[arith]
     x0 = np.zeros((k, A.n)) if x0 is None else x0
-    xr, ir, sr, hr = reading_cg(arith, A, b, x0, tol, maxit, normalise, jacobi)
+    xr, ir, sr, hr = reading_cg(arith, A, b, x0, tol, maxit, normalise, jacobi, normalise_p)
     xo, io = O.cg_solve(arith, A, b, x0=x0, tol=tol, maxit=maxit, normalise=normalise, history=True,
-                        precond="jacobi" if jacobi else None)
+                        precond="jacobi" if jacobi else None, normalise_p=normalise_p)
     assert (io["iters"], io["status"]) == (ir, sr)
     assert np.array_equal(np.asarray(io["history"]).view(np.uint64), np.asarray(hr, dtype=np.float64).view(np.uint64))
     assert np.array_equal(xo.view(np.uint64), xr.view(np.uint64))
@@ -230,6 +232,15 @@ def test_cg_reading_from_nonzero_start(arith):
 def test_cg_reading_normalise_every_k(arith, K, name):
     A, b = SYS[name]
     compare(arith, A, b, normalise=K)
+
+
+@pytest.mark.parametrize("arith", QUASI)
+@pytest.mark.parametrize("K", [1, 2, 3])
+@pytest.mark.parametrize("name", ["poisson2d", "banded_scaled"])
+def test_cg_reading_normalise_r_and_p(arith, K, name):
+    """The placement variant: p normalised with r, after its x update."""
+    A, b = SYS[name]
+    compare(arith, A, b, normalise=K, normalise_p=True)
 
 
 @pytest.mark.parametrize("arith", ARITHS)
