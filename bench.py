@@ -103,10 +103,10 @@ def copy_ceiling(torch, dev, nbytes=1 << 30, reps=10):
     return best
 
 
-def bench_batched(mw, P, torch, dev, nsys=512, tune=True):
+def bench_batched(mw, P, torch, dev, nsys=512, tune=True, loop=True):
     """512 uneven SPD systems (Poisson 2D/3D and circulant Laplacians, n in
     [1024, 65536]): one batched solve vs a loop of single solves, QTW and
-    DW, tol 1e-12."""
+    DW, tol 1e-12 (loop=False: the batched solves alone, for profiling)."""
     import numpy as np
     B = P.batch_systems(nsys=nsys)
     Ad = mw.DeviceCSR.from_host(B.A, dev)
@@ -125,19 +125,21 @@ def bench_batched(mw, P, torch, dev, nsys=512, tune=True):
         x, iters, status, rel, info = mw.cg_solve_batched(ar, Ad, B.sys_row_off, bd, x=x, tol=1e-12)
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        its = []
-        for (A, b) in devs:
-            its.append(mw.cg_solve(ar, A, b, tol=1e-12)[1]["iters"])
-        torch.cuda.synchronize()
-        tl = time.perf_counter() - t0
-        its = np.array(its)
-        out[ar] = {"batched_s": round(tb, 4), "loop_s": round(tl, 4), "speedup": round(tl / tb, 2),
-                   "tuned_grid": shape["spmv_grid"] if shape else None,
+        out[ar] = {"batched_s": round(tb, 4), "tuned_grid": shape["spmv_grid"] if shape else None,
                    "max_iters": int(iters.max()), "mean_iters": round(float(iters.mean()), 1),
-                   "all_converged": bool((status == 0).all()),
-                   "iters_within_2pct_of_loop": float(np.mean(np.abs(its - iters) <= np.maximum(1, 0.02 * its)))}
+                   "all_converged": bool((status == 0).all())}
+        if loop:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its = []
+            for (A, b) in devs:
+                its.append(mw.cg_solve(ar, A, b, tol=1e-12)[1]["iters"])
+            torch.cuda.synchronize()
+            tl = time.perf_counter() - t0
+            its = np.array(its)
+            out[ar].update({"loop_s": round(tl, 4), "speedup": round(tl / tb, 2),
+                            "iters_within_2pct_of_loop":
+                                float(np.mean(np.abs(its - iters) <= np.maximum(1, 0.02 * its)))})
         log("batched %s: %s" % (ar, out[ar]))
     return out
 
@@ -483,6 +485,8 @@ def main():
                     help="also time iterations on banded stand-ins of the paper's Table I matrices")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 512-system batched comparison (for profiling that path) and print its line")
+    ap.add_argument("--no-loop", action="store_true",
+                    help="with --batched-only: skip the loop of single solves (for profiling the batched one)")
     ap.add_argument("--illcond-only", action="store_true",
                     help="run only the ill-conditioned banded workload and print its line")
     ap.add_argument("--illcond-maxit", type=int, default=20000,
@@ -511,7 +515,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.batched_only:
-        bt = bench_batched(mw, P, torch, dev, tune=not args.no_tune)
+        bt = bench_batched(mw, P, torch, dev, tune=not args.no_tune, loop=not args.no_loop)
         print(json.dumps({"metric": "batched QTW CG time-to-1e-12 (512 systems, one lockstep solve)",
                           "value": bt["qtw"]["batched_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
                           "dtype": "f64", "data": "synthetic", "config": {"workload": bt["workload"]},
