@@ -64,8 +64,9 @@ extern "C" {
  * (each rounded once to FP64) and dots (kept multi-word) in DW / QTW;
  * alpha and beta are DW / QTW quotients rounded to FP64 for FP64 fma
  * updates.  Their scalars (dot results, alpha arguments) have
- * mw_scalar_words() words; mw_elementwise, mw_csr_grad and the batched
- * solver reject them, and mw_cg_solve takes no preconditioner with them. */
+ * mw_scalar_words() words; mw_elementwise and mw_csr_grad reject them (their
+ * vectors are FP64: use MW_FP64 there), and mw_cg_solve and
+ * mw_cg_solve_batched take no preconditioner with them. */
 typedef enum {
     MW_FP64 = 0,
     MW_DW = 1,
@@ -494,7 +495,7 @@ size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int3
  * status (MW_OK < MW_NOT_CONVERGED < MW_BREAKDOWN), seconds.  opts:
  * normalize, chunk (default 16), no_graph, shape (spmv_grid, chunk) and
  * precond (Jacobi per system as in mw_cg_solve, each system's d_i from its
- * own rows) are honoured.  All systems advance in lockstep, five kernels
+ * own rows; not with the mixed types) are honoured.  All systems advance in lockstep, five kernels
  * per iteration replayed from a captured hipGraph;
  * a converged system's rows cost a flag test per 64-row slice afterwards.
  * Each system gives the same results whatever the other systems are, but

@@ -6,11 +6,19 @@ CG (A is SPD, so A^T = A); dL/db = lam; dL/dA_ij = -lam_i x_j on A's
 pattern (mw_csr_grad).  Gradients reach any parameter the values depend
 on through ordinary autograd (e.g. dL/dtheta_i = -lam_i x_i for
 A = L + diag(theta)).  Every step runs in libmwcg; this module only wires
-the calls into autograd.
+the calls into autograd.  The mixed-precision arithmetics (MXDW, MXQTW)
+keep x and lam in FP64: their rounding to FP64 is the identity, and the
+product lam_i x_j rounded once to FP64 is the FP64 product, so those two
+steps take the FP64 entry points.
 """
 import torch
 
 from . import mw
+
+
+def _vector_arith(arith):
+    """The arithmetic of the stored vectors: FP64 for the mixed types."""
+    return "fp64" if mw.WORDS[arith] == 1 else arith
 
 
 class MWCGSolve(torch.autograd.Function):
@@ -29,7 +37,7 @@ class MWCGSolve(torch.autograd.Function):
         ctx.x = x
         if info_out is not None:
             info_out["forward"] = info
-        return mw.elementwise(arith, "tofp64", x).reshape(-1)
+        return mw.elementwise(_vector_arith(arith), "tofp64", x).reshape(-1)
 
     @staticmethod
     def backward(ctx, grad_x):
@@ -42,8 +50,9 @@ class MWCGSolve(torch.autograd.Function):
             ctx.info_out["adjoint"] = info
             ctx.info_out["lam"] = lam
             ctx.info_out["x"] = ctx.x
-        grad_b = mw.elementwise(arith, "tofp64", lam).reshape(-1)
-        grad_val = mw.csr_grad(arith, A, lam, ctx.x)
+        va = _vector_arith(arith)
+        grad_b = mw.elementwise(va, "tofp64", lam).reshape(-1)
+        grad_val = mw.csr_grad(va, A, lam, ctx.x)
         return grad_val, grad_b, None, None, None, None, None, None
 
 

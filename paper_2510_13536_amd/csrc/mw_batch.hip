@@ -430,7 +430,7 @@ struct BatchLayout {
 
 BatchLayout batch_layout(int a, int32_t nsys, int32_t n, int32_t nnz)
 {
-    const size_t K = (size_t)words(a);
+    const size_t K = (size_t)words(a), KV = (size_t)vwords(a);  // scalar / vector words
     BatchLayout L;
     L.ns_max = (long long)(n + 63) / 64 + nsys;
     L.cap = (long long)nnz + (long long)nnz / 4 + 64 * L.ns_max;
@@ -440,9 +440,9 @@ BatchLayout batch_layout(int a, int32_t nsys, int32_t n, int32_t nnz)
         o += align256(bytes);
         return at;
     };
-    L.r = take(sizeof(double) * K * n);
-    L.p = take(sizeof(double) * K * n);
-    L.q = take(sizeof(double) * K * n);
+    L.r = take(sizeof(double) * KV * n);
+    L.p = take(sizeof(double) * KV * n);
+    L.q = take(sizeof(double) * KV * n);
     L.slots_a = take(sizeof(double) * K * L.ns_max);
     L.slots_b = take(sizeof(double) * K * L.ns_max);
     L.slots_c = take(sizeof(double) * K * L.ns_max);
@@ -737,7 +737,7 @@ extern "C" {
 
 size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int32_t nnz)
 {
-    if (!valid_arith(a) || mixed_arith(a) || nsys <= 0 || n <= 0 || nnz < 0) return 0;
+    if (!valid_arith(a) || nsys <= 0 || n <= 0 || nnz < 0) return 0;
     return batch_layout(a, nsys, n, nnz).bytes;
 }
 
@@ -748,8 +748,7 @@ namespace {
 bool batched_args_ok(int a, int32_t nsys, const int32_t *sys_row_off, const mw_csr_t *A, const double *b,
                      const double *x, const void *workspace)
 {
-    if (!valid_arith(a) || mixed_arith(a) || nsys <= 0 || !sys_row_off || !valid_csr(A) || !b || !x || !workspace)
-        return false;
+    if (!valid_arith(a) || nsys <= 0 || !sys_row_off || !valid_csr(A) || !b || !x || !workspace) return false;
     if (sys_row_off[0] != 0 || sys_row_off[nsys] != A->n) return false;
     for (int s = 0; s < nsys; ++s)
         if (sys_row_off[s + 1] < sys_row_off[s]) return false;
@@ -769,8 +768,12 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
     if (opts && (!shape_valid(opts->shape) || opts->normalize < 0 || opts->normalize_p != 0 ||
                  (opts->precond != MW_PRECOND_NONE && opts->precond != MW_PRECOND_JACOBI)))
         return MW_EINVAL;
+    if (opts && opts->precond != MW_PRECOND_NONE && mixed_arith(a)) {
+        set_error("mw_cg_solve_batched: the mixed-precision arithmetics take no preconditioner");
+        return MW_EINVAL;
+    }
     MW_CSR_GUARD(A, stream);
-    MW_DISPATCH_WORDS(a, batched_a, nsys, sys_row_off, A, b, x, tol, maxit, opts, workspace, iters, status, rel_res, info,
+    MW_DISPATCH(a, batched_a, nsys, sys_row_off, A, b, x, tol, maxit, opts, workspace, iters, status, rel_res, info,
                 (hipStream_t)stream);
 }
 

@@ -69,6 +69,9 @@ def test_sizes_at_the_int32_limits(lib):
         assert ws >= 3 * k * big * 8 and ws % 256 == 0
         assert ws > lib.mw_cg_workspace_bytes(a, big // 2, big // 2)
         assert lib.mw_cg_batched_workspace_bytes(a, 1, big, big) >= 3 * k * big * 8
+    for a, base in ((8, 1), (9, 4)):  # mixed types: FP64 vector planes, multi-word scalars
+        wb = lib.mw_cg_batched_workspace_bytes(a, 1, big, big)
+        assert 3 * big * 8 <= wb < lib.mw_cg_batched_workspace_bytes(base, 1, big, big)
     assert lib.mw_spmv_plan_bytes(big, big) >= 12 * big
     class Shape(C.Structure):
         _fields_ = [("spmv_grid", C.c_int32), ("update_grid", C.c_int32), ("update_threads", C.c_int32),

@@ -118,3 +118,30 @@ def test_adjoint_matches_oracle_gradient(mods):
     gb = O.elementwise("qtw", "tofp64", lo)
     np.testing.assert_allclose(theta.grad.cpu().numpy(), gt, rtol=1e-10, atol=1e-12 * np.abs(gt).max())
     np.testing.assert_allclose(b.grad.cpu().numpy(), gb, rtol=1e-10, atol=1e-12 * np.abs(gb).max())
+
+
+@pytest.mark.parametrize("arith", ["mxdw", "mxqtw"])
+def test_adjoint_mixed_matches_oracle_gradient(mods, arith):
+    """The mixed types through the adjoint: x and lam stay FP64, so dL/db =
+    lam and dL/dA_ij = -fl(lam_i x_j); checked against the gradient formed
+    from the oracle's mixed solves."""
+    torch, mw, adjoint = mods
+    base = {"mxdw": "dw", "mxqtw": "qtw"}[arith]
+    Q = _problem(10)
+    Ad = mw.DeviceCSR.from_host(Q.lap)
+    theta = torch.as_tensor(Q.theta, device="cuda").requires_grad_(True)
+    b = torch.as_tensor(Q.b, device="cuda").requires_grad_(True)
+    val = torch.as_tensor(Q.lap.val, device="cuda").index_add(0, torch.as_tensor(Q.diag_pos, device="cuda"), theta)
+    info = {}
+    x = adjoint.cg_solve(Ad, val, b, arith=arith, tol=1e-14, info=info)
+    (0.5 * ((x - torch.as_tensor(Q.x_target, device="cuda")) ** 2).sum()).backward()
+    assert info["forward"]["status"] == "ok" and info["adjoint"]["status"] == "ok"
+    A = Q.matrix()
+    xo, io = O.cg_solve(base, A, Q.b, tol=1e-14, mixed=True)
+    lo, il = O.cg_solve(base, A, xo[0] - Q.x_target, tol=1e-14, mixed=True)
+    assert io["status"] == "ok" and il["status"] == "ok"
+    assert abs(info["forward"]["iters"] - io["iters"]) <= max(1, int(0.02 * io["iters"]))
+    np.testing.assert_allclose(x.detach().cpu().numpy(), xo[0], rtol=1e-11, atol=1e-13 * np.abs(xo).max())
+    gt = -(lo[0] * xo[0])
+    np.testing.assert_allclose(theta.grad.cpu().numpy(), gt, rtol=1e-9, atol=1e-11 * np.abs(gt).max())
+    np.testing.assert_allclose(b.grad.cpu().numpy(), lo[0], rtol=1e-9, atol=1e-11 * np.abs(lo).max())

@@ -45,23 +45,33 @@ def small_batch():
     return mats, bs, P.batch_from_systems(mats, bs)
 
 
-@pytest.mark.parametrize("arith", ["fp64", "dw", "qdw", "tw", "qtw", "qtwe", "qw", "qqw"])
+# the mixed types (FP64 vectors, SpMV rows and dots in DW / QTW) against the
+# oracle's mixed solve in their base arithmetic
+MIXED = {"mxdw": "dw", "mxqtw": "qtw"}
+
+
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qdw", "tw", "qtw", "qtwe", "qw", "qqw", "mxdw", "mxqtw"])
 def test_batched_matches_oracle_per_system(mw, small_batch, arith):
     mats, bs, B = small_batch
     Ad = mw.DeviceCSR.from_host(B.A)
     x, iters, status, rel, info = mw.cg_solve_batched(arith, Ad, B.sys_row_off, dev(B.b), tol=1e-12, maxit=20000)
     x = x.cpu().numpy()
+    assert x.shape[0] == mw.WORDS[arith]
     off = B.sys_row_off
+    va = "fp64" if arith in MIXED else arith  # the arithmetic of the stored x
     for s, (A, b) in enumerate(zip(mats, bs)):
-        xo, io = O.cg_solve(arith, A, b, tol=1e-12, maxit=20000)
+        if arith in MIXED:
+            xo, io = O.cg_solve(MIXED[arith], A, b, tol=1e-12, maxit=20000, mixed=True)
+        else:
+            xo, io = O.cg_solve(arith, A, b, tol=1e-12, maxit=20000)
         st = {0: "ok", 1: "not_converged", 2: "breakdown"}[int(status[s])]
         assert st == io["status"], (s, st, io)
         assert abs(int(iters[s]) - io["iters"]) <= max(1, int(0.02 * io["iters"])), (s, iters[s], io["iters"])
         if io["status"] == "ok" and np.any(b):
             xs = x[:, off[s]:off[s + 1]]
             nb = np.linalg.norm(b)
-            trg = O.true_residual(arith, A, b, xs) / nb
-            tro = O.true_residual(arith, A, b, xo) / nb
+            trg = O.true_residual(va, A, b, xs) / nb
+            tro = O.true_residual(va, A, b, xo) / nb
             assert trg <= 10 * max(tro, 1e-300), (s, trg, tro)
     assert int(iters[3]) == 0 and int(status[3]) == 0          # b = 0
     assert int(status[-1]) == 2                                 # indefinite system

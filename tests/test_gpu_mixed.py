@@ -8,7 +8,8 @@ precision as future work) against the oracle's mixed reading:
 * AXPY: y = fma(fp64(alpha), x, y) bit for bit;
 * CG: same status, iterations within 2 %, true residual within 10x of the
   oracle's mixed solve; the error against an exact solution stays FP64's;
-* the entry points that do not take the mixed types reject them.
+* the entry points that do not take the mixed types reject them (the
+  element-wise ops, the gradient kernel, Jacobi preconditioning).
 """
 import numpy as np
 import pytest
@@ -148,7 +149,7 @@ def test_other_entry_points_reject_mixed(mw):
     with pytest.raises(mw.MWError):
         mw.csr_grad("mxqtw", Ad, x, x)
     with pytest.raises(mw.MWError):
-        mw.cg_solve_batched("mxdw", Ad, [0, A.n], dev(np.ones(A.n)))
+        mw.cg_solve_batched("mxdw", Ad, [0, A.n], dev(np.ones(A.n)), precond="jacobi")
     with pytest.raises(mw.MWError):
         mw.cg_solve("mxdw", Ad, dev(np.ones(A.n)), precond="jacobi")
     assert mw.lib().mw_words(8) == 1 and mw.lib().mw_scalar_words(9) == 3
