@@ -65,8 +65,8 @@ extern "C" {
  * alpha and beta are DW / QTW quotients rounded to FP64 for FP64 fma
  * updates.  Their scalars (dot results, alpha arguments) have
  * mw_scalar_words() words; mw_elementwise and mw_csr_grad reject them (their
- * vectors are FP64: use MW_FP64 there), and mw_cg_solve and
- * mw_cg_solve_batched take no preconditioner with them. */
+ * vectors are FP64: use MW_FP64 there).  With Jacobi preconditioning their
+ * z = D r is an FP64 vector too (z_i = fl(d_i r_i)). */
 typedef enum {
     MW_FP64 = 0,
     MW_DW = 1,
@@ -436,7 +436,8 @@ size_t mw_cg_workspace_bytes(mw_arith_t a, int32_t n, int32_t nnz);
  *   p = r + beta p.
  * With opts->precond = MW_PRECOND_JACOBI the textbook preconditioned CG
  * runs instead, with M^-1 the FP64 diagonal d_i = fl(1 / a_ii) applied as
- * the FP64 x multi-word product (FP64: one rounded product):
+ * the FP64 x multi-word product (FP64 and the mixed types: one rounded
+ * product):
  *   r = b - A x;  z = D r;  p = z;  rho = r^T z;  rr = r^T r;  stop at once
  *   when fp64(rr) = 0;  each iteration as above up to the normalisation of
  *   r, then z = D r;  rho' = r^T z;  rr = r^T r;  the test uses
@@ -495,7 +496,7 @@ size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int3
  * status (MW_OK < MW_NOT_CONVERGED < MW_BREAKDOWN), seconds.  opts:
  * normalize, chunk (default 16), no_graph, shape (spmv_grid, chunk) and
  * precond (Jacobi per system as in mw_cg_solve, each system's d_i from its
- * own rows; not with the mixed types) are honoured.  All systems advance in lockstep, five kernels
+ * own rows) are honoured.  All systems advance in lockstep, five kernels
  * per iteration replayed from a captured hipGraph;
  * a converged system's rows cost a flag test per 64-row slice afterwards.
  * Each system gives the same results whatever the other systems are, but

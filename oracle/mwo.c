@@ -35,7 +35,8 @@
  *   Alg. 1              : the CG iteration.
  *   Sec. VI             : mixed precision (future work): FP64 vectors with
  *                         the SpMV rows and the dots accumulated in a
- *                         multi-word arithmetic (mwo_cg_mixed_solve).
+ *                         multi-word arithmetic (mwo_cg_mixed_solve; with
+ *                         Jacobi preconditioning, mwo_pcg_jacobi_mixed_solve).
  *   Sec. I              : quadruple-word (QW, Hida, Li and Bailey) and quasi
  *                         quadruple-word (QQW, Ozaki and Imamura) formats,
  *                         named but not given by the paper (see below).
@@ -1137,6 +1138,81 @@ int mwo_cg_mixed_solve(int arith, long n, const int32_t *row_ptr, const int32_t 
 done:
     info->status = status;
     free(r); free(p); free(q);
+    return status;
+}
+
+/* Jacobi-preconditioned CG with the mixed-precision vectors (the two
+ * future-work items of Sec. VI together): as mwo_pcg_jacobi_solve, with
+ * d_i = fl(1 / a_ii) and z = D r, but every vector in FP64, so z_i is the
+ * FP64 product fl(d_i r_i); rho = r^T z and r^T r are accumulated in the
+ * arithmetic (dot_mixed), alpha and beta are the multi-word quotients
+ * rounded to FP64, the updates FP64 fmas (p = fma(beta, p, z)); the test is
+ * on r^T r.  A zero or missing diagonal entry gives an infinite reciprocal
+ * and a breakdown. */
+int mwo_pcg_jacobi_mixed_solve(int arith, long n, const int32_t *row_ptr, const int32_t *col,
+                               const double *val, const double *b, double *x, double tol, int32_t maxit,
+                               mwo_cg_info *info, double *hist)
+{
+    if (words_of(arith) < 2 || n <= 0 || !(tol >= 0.0) || maxit < 0 || !info) return MWO_EINVAL;
+    double *r = calloc((size_t)n, sizeof(double));
+    double *z = calloc((size_t)n, sizeof(double));
+    double *p = calloc((size_t)n, sizeof(double));
+    double *q = calloc((size_t)n, sizeof(double));
+    double *d = calloc((size_t)n, sizeof(double));
+    if (!r || !z || !p || !q || !d) { free(r); free(z); free(p); free(q); free(d); return MWO_EINVAL; }
+    for (long i = 0; i < n; i++) {
+        double aii = 0.0;
+        for (int32_t j = row_ptr[i]; j < row_ptr[i + 1]; j++)
+            if (col[j] == i) aii = val[j];
+        d[i] = f_div(1.0, aii);
+    }
+    info->iters = 0;
+    info->status = MWO_OK;
+    info->rel_res = 0.0;
+    info->seconds = 0.0;
+
+    spmv_mixed(arith, n, row_ptr, col, val, x, q);
+    for (long i = 0; i < n; i++) {
+        r[i] = f_sub(b[i], q[i]);
+        z[i] = f_mul(d[i], r[i]);
+    }
+    memcpy(p, z, sizeof(double) * n);
+    mwv rho = dot_mixed(arith, n, r, z);
+    double rr = mw_to_fp64(arith, dot_mixed(arith, n, r, r));
+    double nb = sqrt(mw_to_fp64(arith, dot_mixed(arith, n, b, b)));
+    int status = MWO_OK;
+
+    if (rr == 0.0) goto done;
+    info->rel_res = sqrt(rr) / nb;
+    if (maxit == 0) { status = MWO_NOT_CONVERGED; goto done; }
+
+    for (;;) {
+        spmv_mixed(arith, n, row_ptr, col, val, p, q);
+        mwv sigma = dot_mixed(arith, n, p, q);
+        double s64 = mw_to_fp64(arith, sigma);
+        if (!(s64 > 0.0) || !isfinite(s64)) { status = MWO_BREAKDOWN; break; }
+        double a = mw_to_fp64(arith, mw_div(arith, rho, sigma));
+        if (!isfinite(a)) { status = MWO_BREAKDOWN; break; }
+        for (long i = 0; i < n; i++) {
+            x[i] = f_fma(a, p[i], x[i]);
+            r[i] = f_fma(-a, q[i], r[i]);
+            z[i] = f_mul(d[i], r[i]);
+        }
+        mwv rho_new = dot_mixed(arith, n, r, z);
+        rr = mw_to_fp64(arith, dot_mixed(arith, n, r, r));
+        info->iters++;
+        if (!isfinite(rr) || !isfinite(mw_to_fp64(arith, rho_new))) { status = MWO_BREAKDOWN; break; }
+        info->rel_res = sqrt(rr) / nb;
+        if (hist && info->iters <= maxit) hist[info->iters - 1] = info->rel_res;
+        if (info->rel_res < tol) break;
+        if (info->iters >= maxit) { status = MWO_NOT_CONVERGED; break; }
+        double be = mw_to_fp64(arith, mw_div(arith, rho_new, rho));
+        for (long i = 0; i < n; i++) p[i] = f_fma(be, p[i], z[i]);
+        rho = rho_new;
+    }
+done:
+    info->status = status;
+    free(r); free(z); free(p); free(q); free(d);
     return status;
 }
 

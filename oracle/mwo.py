@@ -56,6 +56,8 @@ def _load(name):
                                     C.c_int32, C.c_int32, C.c_int32, C.POINTER(CGInfo), _dp]
     lib.mwo_cg_mixed_solve.argtypes = [C.c_int, C.c_long, _ip, _ip, _dp, _dp, _dp, C.c_double,
                                        C.c_int32, C.POINTER(CGInfo), _dp]
+    lib.mwo_pcg_jacobi_mixed_solve.argtypes = [C.c_int, C.c_long, _ip, _ip, _dp, _dp, _dp, C.c_double,
+                                               C.c_int32, C.POINTER(CGInfo), _dp]
     lib.mwo_exact_dot_limbs.argtypes = [C.c_int, C.c_long, _dp, _dp, _u64p]
     lib.mwo_exact_sum_limbs.argtypes = [C.c_long, _dp, _u64p]
     lib.mwo_dot_error.argtypes = [C.c_int, C.c_long, _dp, _dp, _dp, _dp, _dp]
@@ -197,8 +199,9 @@ def cg_solve(arith, A, b, x0=None, tol=1e-12, maxit=None, normalise=True, histor
     """CG per the oracle.  Returns (x (k, n), info dict).
 
     mixed=True (an arithmetic of two or more words): FP64 vectors, the SpMV
-    rows and the dots accumulated in the arithmetic (mwo_cg_mixed_solve);
-    x is then one FP64 plane (1, n); normalise and precond do not apply.
+    rows and the dots accumulated in the arithmetic (mwo_cg_mixed_solve;
+    with precond="jacobi", mwo_pcg_jacobi_mixed_solve, z_i = fl(d_i r_i));
+    x is then one FP64 plane (1, n); normalise does not apply.
 
     normalise (QDW/QTW): True / 1 normalises r every iteration (Sec. IV-D),
     False / 0 never; an integer K > 1 in iterations K, 2K, ...
@@ -208,8 +211,8 @@ def cg_solve(arith, A, b, x0=None, tol=1e-12, maxit=None, normalise=True, histor
     normalise r (a placement variant, not the paper's)."""
     if precond not in (None, "jacobi"):
         raise ValueError("precond must be None or 'jacobi'")
-    if mixed and (precond is not None or WORDS[arith] < 2):
-        raise ValueError("mixed needs a multi-word arithmetic and no preconditioner")
+    if mixed and (WORDS[arith] < 2 or normalise_p):
+        raise ValueError("mixed needs a multi-word arithmetic (and has no p normalisation)")
     k = 1 if mixed else WORDS[arith]
     n, rp, ci, va = _csr(A)
     b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
@@ -221,8 +224,9 @@ def cg_solve(arith, A, b, x0=None, tol=1e-12, maxit=None, normalise=True, histor
     info = CGInfo()
     hist = np.zeros(max(int(maxit), 1)) if history else None
     if mixed:
-        rc = lib().mwo_cg_mixed_solve(ARITH[arith], n, _i(rp), _i(ci), _d(va), _d(b), _d(x), float(tol),
-                                      int(maxit), C.byref(info), _d(hist) if history else None)
+        fn = lib().mwo_pcg_jacobi_mixed_solve if precond == "jacobi" else lib().mwo_cg_mixed_solve
+        rc = fn(ARITH[arith], n, _i(rp), _i(ci), _d(va), _d(b), _d(x), float(tol),
+                int(maxit), C.byref(info), _d(hist) if history else None)
     elif normalise_p:
         if precond is not None:
             raise ValueError("normalise_p applies to plain CG")

@@ -768,10 +768,6 @@ int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, 
     if (opts && (!shape_valid(opts->shape) || opts->normalize < 0 || opts->normalize_p != 0 ||
                  (opts->precond != MW_PRECOND_NONE && opts->precond != MW_PRECOND_JACOBI)))
         return MW_EINVAL;
-    if (opts && opts->precond != MW_PRECOND_NONE && mixed_arith(a)) {
-        set_error("mw_cg_solve_batched: the mixed-precision arithmetics take no preconditioner");
-        return MW_EINVAL;
-    }
     MW_CSR_GUARD(A, stream);
     MW_DISPATCH(a, batched_a, nsys, sys_row_off, A, b, x, tol, maxit, opts, workspace, iters, status, rel_res, info,
                 (hipStream_t)stream);

@@ -282,12 +282,12 @@ __device__ __forceinline__ Num<A> wave_sum(Num<A> v)
 }
 
 // z_i = d_i r_i, the Jacobi step of the preconditioned solvers: the FP64
-// reciprocal of a_ii times the multi-word residual (FP64: one rounded
-// product).
+// reciprocal of a_ii times the multi-word residual (FP64, and the mixed
+// types, whose z is an FP64 vector: one rounded product).
 template <int A>
 __device__ __forceinline__ Num<A> jacobi(double d, const Num<A> &r)
 {
-    if constexpr (A == FP64) return promote<A>(d * r.w[0]);
+    if constexpr (A == FP64 || is_mixed(A)) return promote<A>(d * r.w[0]);
     else return dxmul<A>(d, r);
 }
 

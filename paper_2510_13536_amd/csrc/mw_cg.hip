@@ -768,10 +768,6 @@ int mw_cg_solve(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, dou
         return MW_EINVAL;
     }
     if (opts && opts->precond != MW_PRECOND_NONE && opts->precond != MW_PRECOND_JACOBI) return MW_EINVAL;
-    if (opts && opts->precond != MW_PRECOND_NONE && mixed_arith(a)) {
-        set_error("mw_cg_solve: the mixed-precision arithmetics take no preconditioner");
-        return MW_EINVAL;
-    }
     MW_CSR_GUARD(A, stream);
     MW_DISPATCH(a, cg_a, A, b, x, tol, maxit, opts, workspace, info, (hipStream_t)stream);
 }

@@ -128,7 +128,7 @@ def pcg_batch(small_batch):
     return mats, bs, P.batch_from_systems(mats, bs)
 
 
-@pytest.mark.parametrize("arith", ["fp64", "dw", "qdw", "tw", "qtw", "qtwe", "qw", "qqw"])
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qdw", "tw", "qtw", "qtwe", "qw", "qqw", "mxdw", "mxqtw"])
 def test_batched_jacobi_matches_oracle_per_system(mw, pcg_batch, arith):
     """Jacobi-preconditioned batch against the oracle's preconditioned CG run
     system by system: same status, iterations within 2 %, true residual
@@ -143,16 +143,20 @@ def test_batched_jacobi_matches_oracle_per_system(mw, pcg_batch, arith):
     assert np.array_equal(x.cpu().numpy().view(np.uint64), x2.cpu().numpy().view(np.uint64))
     x = x.cpu().numpy()
     off = B.sys_row_off
+    va = "fp64" if arith in MIXED else arith  # the arithmetic of the stored x
     for s, (A, b) in enumerate(zip(mats, bs)):
-        xo, io = O.cg_solve(arith, A, b, tol=1e-10, maxit=20000, precond="jacobi")
+        if arith in MIXED:
+            xo, io = O.cg_solve(MIXED[arith], A, b, tol=1e-10, maxit=20000, precond="jacobi", mixed=True)
+        else:
+            xo, io = O.cg_solve(arith, A, b, tol=1e-10, maxit=20000, precond="jacobi")
         st = {0: "ok", 1: "not_converged", 2: "breakdown"}[int(status[s])]
         assert st == io["status"], (s, st, io)
         assert abs(int(iters[s]) - io["iters"]) <= max(1, int(0.02 * io["iters"])), (s, iters[s], io["iters"])
         if io["status"] == "ok" and np.any(b):
             xs = x[:, off[s]:off[s + 1]]
             nb = np.linalg.norm(b)
-            trg = O.true_residual(arith, A, b, xs) / nb
-            tro = O.true_residual(arith, A, b, xo) / nb
+            trg = O.true_residual(va, A, b, xs) / nb
+            tro = O.true_residual(va, A, b, xo) / nb
             assert trg <= 10 * max(tro, 1e-300), (s, trg, tro)
     assert int(status[-1]) == 2 and int(iters[-1]) == 0        # zero diagonal entry
     # the scaled banded system: Jacobi converges where plain CG stalls

@@ -8,8 +8,9 @@ precision as future work) against the oracle's mixed reading:
 * AXPY: y = fma(fp64(alpha), x, y) bit for bit;
 * CG: same status, iterations within 2 %, true residual within 10x of the
   oracle's mixed solve; the error against an exact solution stays FP64's;
+* Jacobi PCG (z_i = fl(d_i r_i)) against the oracle's mixed PCG;
 * the entry points that do not take the mixed types reject them (the
-  element-wise ops, the gradient kernel, Jacobi preconditioning).
+  element-wise ops, the gradient kernel).
 """
 import numpy as np
 import pytest
@@ -96,10 +97,10 @@ def test_axpy_rounds_alpha_then_fma(mw, arith):
     assert np.array_equal(yd.cpu().numpy()[0].view(np.uint64), want.view(np.uint64))
 
 
-def _cg_parity(mw, arith, A, b, tol, maxit=None):
+def _cg_parity(mw, arith, A, b, tol, maxit=None, precond=None):
     base = MIXED[arith]
-    xo, io = O.cg_solve(base, A, b, tol=tol, maxit=maxit, mixed=True)
-    xg, ig = mw.cg_solve(arith, mw.DeviceCSR.from_host(A), dev(b), tol=tol, maxit=maxit)
+    xo, io = O.cg_solve(base, A, b, tol=tol, maxit=maxit, mixed=True, precond=precond)
+    xg, ig = mw.cg_solve(arith, mw.DeviceCSR.from_host(A), dev(b), tol=tol, maxit=maxit, precond=precond)
     xg = xg.cpu().numpy()
     assert xg.shape == (1, A.n)
     assert ig["status"] == io["status"], (ig, io)
@@ -139,6 +140,28 @@ def test_cg_accuracy_stays_fp64s(mw, arith):
     assert 1e-17 < err < 1e-13
 
 
+@pytest.mark.parametrize("arith", sorted(MIXED))
+def test_cg_jacobi(mw, arith):
+    """Jacobi PCG with FP64 vectors (z_i = fl(d_i r_i)) against the oracle's
+    mixed PCG: the scaled banded case it rescues, a shifted Laplacian with a
+    varying diagonal; diagonal 4 reproduces the plain mixed solve bit for bit."""
+    A, b, _ = P.case_banded_illcond(n=4096)
+    xg, ig = _cg_parity(mw, arith, A, b, 1e-10, maxit=2000, precond="jacobi")
+    assert ig["status"] == "ok" and ig["iters"] <= 60
+    S = P.poisson2d(30, 27).to_scipy().tolil()
+    rng = np.random.default_rng(12)
+    for i in range(S.shape[0]):
+        S[i, i] = S[i, i] + rng.uniform(0.0, 3.0)
+    S = P.CSR.from_scipy(S.tocsr())
+    _cg_parity(mw, arith, S, S.matvec(rng.uniform(-1, 1, S.n)), 1e-12, precond="jacobi")
+    A, b, _ = P.case_poisson2d_64()
+    Ad = mw.DeviceCSR.from_host(A)
+    x1, i1 = mw.cg_solve(arith, Ad, dev(b), tol=1e-12)
+    x2, i2 = mw.cg_solve(arith, Ad, dev(b), tol=1e-12, precond="jacobi")
+    assert i1["iters"] == i2["iters"] and i1["rel_res"] == i2["rel_res"]
+    assert np.array_equal(x1.cpu().numpy().view(np.uint64), x2.cpu().numpy().view(np.uint64))
+
+
 def test_other_entry_points_reject_mixed(mw):
     import torch
     A = P.poisson2d(8)
@@ -149,7 +172,5 @@ def test_other_entry_points_reject_mixed(mw):
     with pytest.raises(mw.MWError):
         mw.csr_grad("mxqtw", Ad, x, x)
     with pytest.raises(mw.MWError):
-        mw.cg_solve_batched("mxdw", Ad, [0, A.n], dev(np.ones(A.n)), precond="jacobi")
-    with pytest.raises(mw.MWError):
-        mw.cg_solve("mxdw", Ad, dev(np.ones(A.n)), precond="jacobi")
+        mw.cg_solve("mxdw", Ad, dev(np.ones(A.n)), normalize_p=True, precond="jacobi")
     assert mw.lib().mw_words(8) == 1 and mw.lib().mw_scalar_words(9) == 3

@@ -14,6 +14,10 @@ FP64 fma updates).  No GPU.
 * The rounded SpMV of a multi-word accumulator is correctly rounded: with
   integer data it is exact, and the first iterate matches an FP64 CG fed
   exactly rounded row sums.
+* With Jacobi preconditioning (z_i = fl(d_i r_i), d_i = fl(1 / a_ii)): the
+  second reading also covers it bit for bit; a power-of-two diagonal gives
+  the plain solve bit for bit; the D A D scaling of the banded case is
+  undone; a zero diagonal entry breaks down at once.
 """
 import math
 
@@ -36,7 +40,9 @@ def to64(v):
     return v[0] + (v[1] + (v[2] + v[3]))
 
 
-def reading_mixed_cg(arith, A, b, tol, maxit):
+def reading_mixed_cg(arith, A, b, tol, maxit, jacobi=False):
+    """jacobi: preconditioned CG with d_i = fl(1 / a_ii), z_i = fl(d_i r_i),
+    rho = r^T z, the test on r^T r and p = fma(beta, p, z)."""
     f = IMPL[arith]
     k = O.WORDS[arith]
     zero = (0.0,) * k
@@ -60,15 +66,28 @@ def reading_mixed_cg(arith, A, b, tol, maxit):
         return acc
 
     n = A.n
+    if jacobi:
+        diag = [0.0] * n
+        for i in range(n):
+            for j in range(int(A.row_ptr[i]), int(A.row_ptr[i + 1])):
+                if int(A.col_idx[j]) == i:
+                    diag[i] = float(A.val[j])
+        d = [1.0 / a if a != 0.0 else math.copysign(math.inf, a) for a in diag]
+
+    def precond(r):
+        return [d[i] * r[i] for i in range(n)] if jacobi else r
+
     bl = [float(v) for v in b]
     x = [0.0] * n
     q = spmv(x)
     r = [bl[i] - q[i] for i in range(n)]
-    p = list(r)
-    rho = dot(r, r)
+    z = precond(r)
+    p = list(z)
+    rho = dot(r, z)
+    rr = to64(dot(r, r))
     nb = math.sqrt(to64(dot(bl, bl)))
     hist = []
-    if to64(rho) == 0.0:
+    if rr == 0.0:
         return np.array(x), 0, "ok", hist
     it = 0
     while True:
@@ -78,18 +97,24 @@ def reading_mixed_cg(arith, A, b, tol, maxit):
         if not (s64 > 0.0) or not math.isfinite(s64):
             return np.array(x), it, "breakdown", hist
         a = to64(mw_div(arith, rho, sigma))
+        if not math.isfinite(a):
+            return np.array(x), it, "breakdown", hist
         x = [fma(a, p[i], x[i]) for i in range(n)]
         r = [fma(-a, q[i], r[i]) for i in range(n)]
-        rho_new = dot(r, r)
+        z = precond(r)
+        rho_new = dot(r, z)
+        rr = to64(dot(r, r))
         it += 1
-        rel = math.sqrt(to64(rho_new)) / nb
+        if not math.isfinite(rr) or not math.isfinite(to64(rho_new)):
+            return np.array(x), it, "breakdown", hist
+        rel = math.sqrt(rr) / nb
         hist.append(rel)
         if rel < tol:
             return np.array(x), it, "ok", hist
         if it >= maxit:
             return np.array(x), it, "not_converged", hist
         be = to64(mw_div(arith, rho_new, rho))
-        p = [fma(be, p[i], r[i]) for i in range(n)]
+        p = [fma(be, p[i], z[i]) for i in range(n)]
         rho = rho_new
 
 
@@ -110,12 +135,14 @@ def small_systems():
 SMALL = small_systems()
 
 
+@pytest.mark.parametrize("jacobi", [False, True])
 @pytest.mark.parametrize("arith", ACC)
 @pytest.mark.parametrize("name", sorted(SMALL))
-def test_second_reading_bit_exact(arith, name):
+def test_second_reading_bit_exact(arith, name, jacobi):
     A, b = SMALL[name]
-    xr, ir, sr, hr = reading_mixed_cg(arith, A, b, 1e-300, 8)
-    xo, io = O.cg_solve(arith, A, b, tol=1e-300, maxit=8, history=True, mixed=True)
+    xr, ir, sr, hr = reading_mixed_cg(arith, A, b, 1e-300, 8, jacobi=jacobi)
+    xo, io = O.cg_solve(arith, A, b, tol=1e-300, maxit=8, history=True, mixed=True,
+                        precond="jacobi" if jacobi else None)
     assert xo.shape == (1, A.n)
     assert (io["iters"], io["status"]) == (ir, sr)
     assert np.array_equal(np.asarray(io["history"]).view(np.uint64), np.asarray(hr).view(np.uint64))
@@ -170,9 +197,36 @@ def test_integer_spmv_is_exact_and_first_iterate_is_fp64_cg_on_exact_rows():
     np.testing.assert_array_equal(x[0], np.array([fma(alpha, float(v), 0.0) for v in b]))
 
 
-def test_rejects_one_word_and_preconditioner():
+def test_rejects_one_word_and_p_normalisation():
     A, b = SMALL["poisson1d"]
     with pytest.raises(ValueError):
         O.cg_solve("fp64", A, b, mixed=True)
     with pytest.raises(ValueError):
-        O.cg_solve("dw", A, b, mixed=True, precond="jacobi")
+        O.cg_solve("dw", A, b, mixed=True, normalise_p=True)
+
+
+@pytest.mark.parametrize("arith", ["dw", "qtw"])
+def test_jacobi_power_of_two_diagonal_is_plain(arith):
+    """Diagonal 4 or 2: z = r / 4 (or / 2) exactly and every dot, quotient
+    and update of the preconditioned solve is the plain one scaled by a power
+    of two, so x, the iterations and the residuals are the plain solve's."""
+    for A, b in ((lambda c: (c[0], c[1]))(P.case_poisson2d_64()),
+                 (P.poisson1d(300), np.random.default_rng(8).uniform(-1, 1, 300))):
+        x1, i1 = O.cg_solve(arith, A, b, tol=1e-12, history=True, mixed=True)
+        x2, i2 = O.cg_solve(arith, A, b, tol=1e-12, history=True, mixed=True, precond="jacobi")
+        assert i1["iters"] == i2["iters"] and i1["status"] == i2["status"] == "ok"
+        assert np.array_equal(x1.view(np.uint64), x2.view(np.uint64))
+        assert np.array_equal(i1["history"], i2["history"])
+
+
+@pytest.mark.parametrize("arith", ["dw", "qtw"])
+def test_jacobi_undoes_diagonal_scaling_and_zero_diagonal_breaks_down(arith):
+    A, b, _ = P.case_banded_illcond(n=2048)
+    _, plain = O.cg_solve(arith, A, b, tol=1e-10, maxit=2000, mixed=True)
+    x, pc = O.cg_solve(arith, A, b, tol=1e-10, maxit=2000, mixed=True, precond="jacobi")
+    assert plain["status"] == "not_converged"
+    assert pc["status"] == "ok" and pc["iters"] <= 40
+    assert O.true_residual("fp64", A, b, x) / np.linalg.norm(b) < 1e-9
+    M = P.CSR.from_scipy(sp.csr_matrix(np.array([[0.0, 1.0], [1.0, 2.0]])))
+    _, info = O.cg_solve(arith, M, np.array([1.0, 1.0]), mixed=True, precond="jacobi")
+    assert info["status"] == "breakdown" and info["iters"] == 0
