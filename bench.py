@@ -213,8 +213,8 @@ def bench_illcond(mw, P, torch, dev, maxit=20000, hist_every=0):
                    out[ar]["history"]["min_at"], out[ar]["history"]["first_below"]))
         # Jacobi-preconditioned CG (an extension; it removes the D A D
         # scaling): iterations, time and the exactly formed true residual
-        # (the mixed types take no preconditioner)
-        for ptol in (1e-10, 1e-20) if not ar.startswith("mx") else ():
+        # (the mixed types keep z = D r in FP64 as well)
+        for ptol in (1e-10, 1e-20):
             x.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
