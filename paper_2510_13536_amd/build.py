@@ -35,12 +35,28 @@ def flags(arch="gfx950"):
 
 
 def build(verbose=False, arch="gfx950", extra=None):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *flags(arch), *(extra or []), "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    """Compiles every source to its own object (in parallel, in a temporary
+    folder), then links them into libmwcg.so."""
+    import tempfile
+    cc = hipcc()
+    common = [f for f in flags(arch) if f != "-shared"] + list(extra or [])
+    with tempfile.TemporaryDirectory(prefix="mwcg_build_") as tmpdir:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpdir, os.path.splitext(src)[0] + ".o")
+            cmd = [cc, *common, "-c", "-o", obj, os.path.join(CSRC, src)]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((cmd, subprocess.Popen(cmd)))
+            objs.append(obj)
+        failed = [cmd for cmd, pr in procs if pr.wait() != 0]
+        if failed:
+            raise subprocess.CalledProcessError(1, failed[0])
+        tmp = LIB + ".tmp"
+        cmd = [cc, "--offload-arch=" + arch, "-shared", "-fPIC", "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
 
