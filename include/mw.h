@@ -185,9 +185,10 @@ typedef struct {
     int32_t update_threads;  /* single system: threads per update
                                 workgroup, 256, 512 or 1024                 */
     int32_t chunk;           /* iterations per captured chunk, 1 .. 4096   */
-    int32_t lanes;           /* single system: lanes per row when the solver
-                                builds a vector-row plan itself
-                                (MW_FMT_CSRVEC), 2, 4, ..., 64             */
+    int32_t lanes;           /* lanes per row, 2, 4, ..., 64: single system,
+                                of the vector-row plan the solver builds
+                                itself (MW_FMT_CSRVEC); batched, of its
+                                vector-row slices                          */
     double us_per_iteration; /* set by the tuners: measured device time per
                                 iteration of the chosen shape              */
 } mw_shape_t;
@@ -496,13 +497,23 @@ size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int3
  * status (MW_OK < MW_NOT_CONVERGED < MW_BREAKDOWN), seconds.  opts:
  * normalize, chunk (default 16), no_graph, shape (spmv_grid, chunk) and
  * precond (Jacobi per system as in mw_cg_solve, each system's d_i from its
- * own rows) are honoured.  All systems advance in lockstep, five kernels
- * per iteration replayed from a captured hipGraph;
- * a converged system's rows cost a flag test per 64-row slice afterwards.
+ * own rows) are honoured; shape->lanes sets the lanes per row of the
+ * vector-row slices (below).  All systems advance in lockstep, five kernels
+ * per iteration (six when there are vector-row slices) replayed from a
+ * captured hipGraph; a converged system's rows cost a flag test per 64-row
+ * slice afterwards.  The matrix is copied into a SELL-64 layout whose
+ * slices never straddle two systems, except 64-row slices whose longest row
+ * has at least 9 entries and more than 4 times their average: those are
+ * summed as vector rows straight from A (L lanes per row, L from the
+ * slice's lengths unless shape->lanes is set; the row order of
+ * mw_spmv_plan_rows with the same L), so a few very long rows cost no
+ * padding.
  * Each system gives the same results whatever the other systems are, but
  * its dots are summed per 64-row slice, so they need not be bit-identical
  * to a single-system mw_cg_solve.  Returns the worst status or a negative
- * error (MW_EINVAL also when a slice's padding would exceed the workspace).
+ * error (MW_EINVAL also when the SELL-64 padding of the remaining slices
+ * would still exceed the workspace: many slices of rows shorter than 9
+ * entries beside much longer ones).
  * Synchronises `stream`.
  */
 int mw_cg_solve_batched(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, const mw_csr_t *A,
@@ -538,8 +549,11 @@ int mw_cg_tune(mw_arith_t a, const mw_csr_t *A, const double *b, double *x, int3
 /*
  * The same for mw_cg_solve_batched: candidate slice-kernel grids 256, 512,
  * 1024, 1536, 2048, each timed over `iters` lockstep iterations of all
- * systems (tol = 0); the table key is (a, n, nnz, nsys).  Arguments as
- * mw_cg_solve_batched plus iters (2 .. 4096) and *best.
+ * systems (tol = 0), then, when the batch has vector-row slices, lanes per
+ * row 2, 4, ..., 64 on the best grid (rows per wavefront 64 / lanes; lanes
+ * change how those rows' sums are associated); the table key is (a, n,
+ * nnz, nsys).  Arguments as mw_cg_solve_batched plus iters (2 .. 4096) and
+ * *best.
  */
 int mw_cg_batched_tune(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, const mw_csr_t *A,
                        const double *b, double *x, int32_t iters, void *workspace, mw_shape_t *best,
@@ -549,7 +563,8 @@ int mw_cg_batched_tune(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, c
  * The launch shape a solve of an n x n matrix with nnz entries would use
  * now with opts->shape unset (nsys = 0: mw_cg_solve; nsys >= 1:
  * mw_cg_solve_batched of nsys systems, whose slice grid depends on the
- * systems' slice count, reported here as 0 when not tuned): a tuned shape,
+ * systems' slice count, reported here as 0 when not tuned, and lanes the
+ * tuned lanes per row of its vector-row slices, 0 for each slice's rule): a tuned shape,
  * else the environment overrides, else the built-in one, with grids
  * clamped to what the matrix needs.  lanes: the lanes per row when a solve
  * would build a vector-row plan by the matrix's size (see opts->plan), else

@@ -8,7 +8,11 @@
 // Layout: a SELL-64 copy of the matrix whose slices never straddle two
 // systems (each system's rows start a new slice), so every wavefront works
 // for exactly one system; slices whose rows fit diagonal slots store no
-// column indices, as in the single-system plan (fill_slice).  Per-system reductions use one partial per slice
+// column indices, as in the single-system plan (fill_slice).  Slices with
+// very uneven rows (the longest more than VEC_PAD times the average, so
+// SELL-64 would pad every row to it) are not copied: they are summed as vector rows straight from the caller's CSR
+// arrays, L lanes per row (vec_slice_sum), so one long row costs neither
+// padding nor a single lane's sequential chain.  Per-system reductions use one partial per slice
 // (a wavefront shuffle tree, no workgroup barrier), summed in slice order by
 // one workgroup per system.
 //
@@ -37,6 +41,16 @@ using namespace mwh;
 
 namespace {
 
+// What the vector-row slices read, kept in device memory so that the
+// slice kernels' arguments stay small.
+struct VecRows {
+    const int32_t *slanes;         // ns: lanes per row of a vector-row slice, 0 = SELL-64
+    const int32_t *vlist;          // the vector-row slices (any order)
+    const int32_t *nvec;           // their count
+    const int32_t *crp, *cci;      // the caller's CSR
+    const double *cva;
+};
+
 // Device view of the batch bookkeeping (passed by value).
 struct BatchDev {
     const int32_t *sys_slice_off;  // nsys + 1
@@ -57,6 +71,7 @@ struct BatchDev {
     int32_t *n_alist;              // their count
     int32_t *list_pos;             // nsys: a running system's first entry in alist
     const double *dinv;            // PC: fl(1 / a_ii) per row
+    const struct VecRows *vec;     // vector-row slices (device memory)
     const double *tol;             // solve parameters in device memory
     const int32_t *maxit, *normalize;
     int nsys, ns, n;
@@ -72,20 +87,58 @@ __device__ __forceinline__ int slice_at(const BatchDev &d, int idx) { return d.a
 
 // ------------------------------------------------------------ plan build
 
+// A slice takes vector rows when its longest row is more than VEC_PAD
+// times its average one and has at least VEC_MIN entries.  Uniform long
+// rows keep SELL-64: on a batch of 96 banded systems (81 to 401 entries
+// per row, 457 k rows) vector rows measured 12-36 % slower than its
+// diagonal slots, which need no column indices.
+constexpr int VEC_PAD = 4;
+constexpr int VEC_MIN = 9;
+
+// Lanes per row of a vector-row slice: the smallest power of two L with
+// L x per >= max(average, longest / 8) (per: 8 entries a lane for FP64
+// vectors, 16 for multi-word ones), at most 64; `lanes` > 0 overrides.
+__device__ __forceinline__ int vec_lanes(int lanes, int vw, int avg, int longest)
+{
+    if (lanes > 0) return lanes;
+    const int per = vw == 1 ? 8 : 16;
+    const int target = max(avg, longest / 8);
+    int L = 2;
+    while (L < 64 && L * per < target) L *= 2;
+    return L;
+}
+
+// Per slice: its SELL-64 width (longest row), or 0 and a lane count when
+// it is to be summed as vector rows; those slices are appended to vlist
+// (nvec counts them; every result is stored by slice index, so their
+// order does not matter).
 __global__ void __launch_bounds__(BNT) mw_batch_width_kernel(BatchDev d, const int32_t *__restrict__ row_ptr,
-                                                             int32_t *__restrict__ width)
+                                                             int32_t *__restrict__ width, int32_t *__restrict__ slanes,
+                                                             int32_t *__restrict__ vlist, int32_t *__restrict__ nvec,
+                                                             int lanes, int vw)
 {
     const int s = blockIdx.x * NWAVE + wave_id();
     const int lane = threadIdx.x & 63;
     if (s >= d.ns) return;
+    const int rows = d.slice_rows[s];
     int len = 0;
-    if (lane < d.slice_rows[s]) {
+    if (lane < rows) {
         const int row = d.slice_row0[s] + lane;
         len = row_ptr[row + 1] - row_ptr[row];
     }
+    int longest = len, total = len;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
-    if (lane == 0) width[s] = len;
+    for (int off = 32; off > 0; off >>= 1) {
+        longest = max(longest, __shfl_xor(longest, off, 64));
+        total += __shfl_xor(total, off, 64);
+    }
+    const int avg = total / rows;
+    const bool vec = longest >= VEC_MIN && (long)rows * longest > (long)VEC_PAD * total;
+    if (lane == 0) {
+        width[s] = vec ? 0 : longest;
+        slanes[s] = vec ? vec_lanes(lanes, vw, avg, longest) : 0;
+        if (vec) vlist[atomicAdd(nvec, 1)] = s;
+    }
 }
 
 __global__ void __launch_bounds__(BNT) mw_batch_fill_kernel(BatchDev d, const int32_t *__restrict__ row_ptr,
@@ -97,7 +150,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_fill_kernel(BatchDev d, const in
 {
     const int s = blockIdx.x * NWAVE + wave_id();
     const int lane = threadIdx.x & 63;
-    if (s >= d.ns) return;
+    if (s >= d.ns || d.vec->slanes[s]) return;
     const int b = slice_ptr[s];
     const int w = (slice_ptr[s + 1] - b) / 64;
     const long row = (long)d.slice_row0[s] + lane;
@@ -110,6 +163,44 @@ __global__ void __launch_bounds__(BNT) mw_batch_fill_kernel(BatchDev d, const in
 }
 
 // ------------------------------------------------------------- kernels
+
+// Row sums of a vector-row slice (rows row0 .. row0 + rows - 1, L lanes per
+// row, L a power of two): L passes of 64 / L rows; lane t of a row's group
+// adds the row's entries t, t + L, ... in order from zero, then the group
+// combines its L sums by a fixed halving tree -- the row order of the
+// single-system vector-row plan with the same L.  Each row's sum is stored
+// by its group's first lane; in CG mode (MODE 1) that lane also adds
+// x_i y_i to the returned per-lane partial.  Called by the whole wavefront.
+template <int A, int MODE>
+__device__ __forceinline__ Num<A> vec_slice_sum(const BatchDev &d, int L, long row0, int rows, int lane,
+                                                const double *__restrict__ x, double *__restrict__ y)
+{
+    const int32_t *__restrict__ crp = d.vec->crp;
+    const int32_t *__restrict__ cci = d.vec->cci;
+    const double *__restrict__ cva = d.vec->cva;
+    const int lg = __builtin_ctz(L);
+    const int t = lane & (L - 1);
+    const int rpw = 64 >> lg;
+    Num<A> part = zero<A>();
+    for (int k = 0; k < L; ++k) {
+        const int rl = k * rpw + (lane >> lg);
+        const long row = row0 + rl;
+        Num<A> acc = zero<A>();
+        if (rl < rows) {
+            const int re = crp[row + 1];
+            for (int j = crp[row] + t; j < re; j += L) acc = row_step<A>(acc, cva[j], load_v<A, MODE>(x, d.n, cci[j]));
+        }
+        for (int off = L >> 1; off > 0; off >>= 1) {
+            const Num<A> o = shfl_down<A>(acc, off);
+            if (t < off) acc = add<A>(acc, o);
+        }
+        if (t == 0 && rl < rows) {
+            store<A>(y, d.n, row, acc);
+            if constexpr (MODE == 1) part = dot_step<A>(part, load_v<A, MODE>(x, d.n, row), acc);
+        }
+    }
+    return part;
+}
 
 // y = A x over the slices; MODE 1 (CG) skips stopped systems and leaves
 // the slice partial of p^T q in slots[s].
@@ -130,6 +221,9 @@ __global__ void __launch_bounds__(BNT) mw_batch_spmv_kernel(BatchDev d, const do
         }
         const int b = d.sp[s];
         const int w = (d.sp[s + 1] - b) >> 6;
+        // a vector-row slice stores nothing in the SELL-64 copy (w = 0):
+        // mw_batch_vec_spmv_kernel sums it
+        if (w == 0 && d.vec->slanes[s]) continue;
         const bool valid = lane < d.slice_rows[s];
         const long row = (long)d.slice_row0[s] + lane;
         Num<A> acc, xc = zero<A>();
@@ -151,6 +245,29 @@ __global__ void __launch_bounds__(BNT) mw_batch_spmv_kernel(BatchDev d, const do
             Num<A> c = zero<A>();
             if (valid) c = dot_step<A>(c, xc, acc);
             c = wave_sum<A>(c);
+            if (lane == 0) store_scalar<A>(slots + (long)s * K, c);
+        }
+    }
+}
+
+// The vector-row slices (vlist), one wavefront each, as the SELL kernel's
+// MODE for the others: y and, in CG mode, the slice partial of p^T q.
+template <int A, int MODE>
+__global__ void __launch_bounds__(BNT) mw_batch_vec_spmv_kernel(BatchDev d, const double *__restrict__ x,
+                                                                double *__restrict__ y, double *__restrict__ slots)
+{
+    constexpr int K = words(A);
+    const int lane = threadIdx.x & 63;
+    const int nv = *d.vec->nvec;
+    const int step = gridDim.x * NWAVE;
+    for (int idx = blockIdx.x * NWAVE + wave_id(); idx < nv; idx += step) {
+        const int s = d.vec->vlist[idx];
+        if constexpr (MODE == 1) {
+            if (!d.active[d.slice_sys[s]]) continue;
+        }
+        const Num<A> part = vec_slice_sum<A, MODE>(d, d.vec->slanes[s], d.slice_row0[s], d.slice_rows[s], lane, x, y);
+        if constexpr (MODE == 1) {
+            const Num<A> c = wave_sum<A>(part);
             if (lane == 0) store_scalar<A>(slots + (long)s * K, c);
         }
     }
@@ -424,7 +541,7 @@ __global__ void __launch_bounds__(BNT) mw_batch_list_fill_kernel(BatchDev d)
 
 struct BatchLayout {
     size_t r, p, q, slots_a, slots_b, slots_c, dinv, sys_slice_off, slice_sys, slice_row0, slice_rows, dscal, iscal, params, width,
-        slice_ptr, total, alist, n_alist, list_pos, soff, smask, col, val, bytes;
+        slice_ptr, total, alist, n_alist, list_pos, slanes, vlist, vecrows, soff, smask, col, val, bytes;
     long long ns_max, cap;
 };
 
@@ -456,10 +573,13 @@ BatchLayout batch_layout(int a, int32_t nsys, int32_t n, int32_t nnz)
     L.params = take(64);
     L.width = take(sizeof(int32_t) * L.ns_max);
     L.slice_ptr = take(sizeof(int32_t) * (L.ns_max + 1));
-    L.total = take(sizeof(long long));
+    L.total = take(2 * sizeof(long long));  // stored entries; vector-row slices
     L.alist = take(sizeof(int32_t) * L.ns_max);
     L.n_alist = take(sizeof(int32_t));
     L.list_pos = take(sizeof(int32_t) * nsys);
+    L.slanes = take(sizeof(int32_t) * L.ns_max);
+    L.vlist = take(sizeof(int32_t) * L.ns_max);
+    L.vecrows = take(sizeof(VecRows));
     L.soff = take(sizeof(int32_t) * (L.cap / 64 + 8));
     L.smask = take(sizeof(uint64_t) * (L.cap / 64 + 8));
     L.col = take(sizeof(int32_t) * L.cap);
@@ -480,6 +600,10 @@ hipStream_t batch_stream()
     return s;
 }
 
+// Vector-row slices of the calling thread's last batched solve (read by
+// the tuner to decide whether lanes per row is worth sweeping).
+thread_local int g_last_vec_slices = 0;
+
 int32_t *pinned_count()
 {
     thread_local int32_t *buf = nullptr;
@@ -491,13 +615,13 @@ int32_t *pinned_count()
 // arrays (batch_layout: n, nnz and nsys move the slice copy's offsets) and
 // every pointer its kernels take, the BatchDev fields included.
 struct BatchKey {
-    int arith, nsys, ns, n, nnz, chunk, grid, pc;
-    static constexpr int NPTR = 14;
+    int arith, nsys, ns, n, nnz, chunk, grid, pc, vgrid;
+    static constexpr int NPTR = 17;
     const void *ptrs[NPTR];
     bool operator==(const BatchKey &o) const
     {
         if (arith != o.arith || nsys != o.nsys || ns != o.ns || n != o.n || nnz != o.nnz || chunk != o.chunk ||
-            grid != o.grid || pc != o.pc)
+            grid != o.grid || pc != o.pc || vgrid != o.vgrid)
             return false;
         for (int i = 0; i < NPTR; ++i)
             if (ptrs[i] != o.ptrs[i]) return false;
@@ -528,13 +652,14 @@ BatchGraph &batch_graph()
 }
 
 template <int A, bool PC>
-int enqueue_batch_chunk(const BatchDev &d, int chunk, int g, double *r, double *p, double *q, double *x, double *sa,
-                        double *sb, double *sc, hipStream_t s)
+int enqueue_batch_chunk(const BatchDev &d, int chunk, int g, int vg, double *r, double *p, double *q, double *x,
+                        double *sa, double *sb, double *sc, hipStream_t s)
 {
     hipLaunchKernelGGL(mw_batch_list_scan_kernel, dim3(1), dim3(BNT), 0, s, d);
     hipLaunchKernelGGL(mw_batch_list_fill_kernel, dim3(d.nsys), dim3(BNT), 0, s, d);
     for (int it = 0; it < chunk; ++it) {
         hipLaunchKernelGGL((mw_batch_spmv_kernel<A, 1>), dim3(g), dim3(BNT), 0, s, d, p, q, sa);
+        if (vg > 0) hipLaunchKernelGGL((mw_batch_vec_spmv_kernel<A, 1>), dim3(vg), dim3(BNT), 0, s, d, p, q, sa);
         hipLaunchKernelGGL((mw_batch_alpha_kernel<A>), dim3(d.nsys), dim3(BNT), 0, s, d, sa);
         hipLaunchKernelGGL((mw_batch_step_r_kernel<A, PC>), dim3(g), dim3(BNT), 0, s, d, q, r, sb, sc);
         hipLaunchKernelGGL((mw_batch_beta_kernel<A, PC>), dim3(d.nsys), dim3(BNT), 0, s, d, sb, sc);
@@ -545,11 +670,11 @@ int enqueue_batch_chunk(const BatchDev &d, int chunk, int g, double *r, double *
 }
 
 template <int A>
-int enqueue_batch_chunk_pc(bool pc, const BatchDev &d, int chunk, int g, double *r, double *p, double *q, double *x,
-                           double *sa, double *sb, double *sc, hipStream_t s)
+int enqueue_batch_chunk_pc(bool pc, const BatchDev &d, int chunk, int g, int vg, double *r, double *p, double *q,
+                           double *x, double *sa, double *sb, double *sc, hipStream_t s)
 {
-    return pc ? enqueue_batch_chunk<A, true>(d, chunk, g, r, p, q, x, sa, sb, sc, s)
-              : enqueue_batch_chunk<A, false>(d, chunk, g, r, p, q, x, sa, sb, sc, s);
+    return pc ? enqueue_batch_chunk<A, true>(d, chunk, g, vg, r, p, q, x, sa, sb, sc, s)
+              : enqueue_batch_chunk<A, false>(d, chunk, g, vg, r, p, q, x, sa, sb, sc, s);
 }
 
 template <int A>
@@ -599,6 +724,10 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     d.alist = nullptr;  // set for the iteration chunks, after the set-up kernels
     d.n_alist = (int32_t *)(base + L.n_alist);
     d.list_pos = (int32_t *)(base + L.list_pos);
+    int32_t *slanes = (int32_t *)(base + L.slanes);
+    int32_t *vlist = (int32_t *)(base + L.vlist);
+    VecRows *vecrows = (VecRows *)(base + L.vecrows);
+    d.vec = vecrows;
     d.soff = (int32_t *)(base + L.soff);
     d.smask = (uint64_t *)(base + L.smask);
     double *dscal = (double *)(base + L.dscal);
@@ -641,13 +770,24 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     }
     // system-aligned SELL-64 plan
     const int nbw = blocks_for(ns > 0 ? ns : 1, NWAVE);
-    hipLaunchKernelGGL(mw_batch_width_kernel, dim3(nbw), dim3(BNT), 0, s, d, M->row_ptr, width);
+    int32_t *nvec = (int32_t *)(total + 1);
+    // (the record is read by the kernels below, on this stream; the host
+    // copy lives until the synchronisation after the scan)
+    const VecRows h_vec{slanes, vlist, nvec, M->row_ptr, M->col_idx, M->val};
+    HIP_TRY(hipMemsetAsync(nvec, 0, sizeof(int32_t), s));
+    HIP_TRY(hipMemcpyAsync(vecrows, &h_vec, sizeof(VecRows), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(mw_batch_width_kernel, dim3(nbw), dim3(BNT), 0, s, d, M->row_ptr, width, slanes, vlist, nvec,
+                       bsh.lanes, vwords(A));
     HIP_TRY(hipGetLastError());
     int rc = launch_sell_scan(ns, width, (int32_t *)d.sp, total, s);
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(hcount, total, sizeof(long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hcount, total, 2 * sizeof(long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));  // also retires the host-array uploads above
     const long long stored = *(long long *)hcount;
+    g_last_vec_slices = *(int32_t *)((long long *)hcount + 1);
+    // grid of the vector-row slice kernel: one wavefront per slice, at most
+    // a persistent grid's worth (0: no such slices, no launch)
+    const int vg = g_last_vec_slices > 0 ? persistent_grid(blocks_for(g_last_vec_slices, NWAVE)) : 0;
     if (stored > L.cap || stored > 0x7fffffffLL) {
         set_error("batched solve: SELL-64 padding exceeds the workspace (rows of very uneven length)");
         return MW_EINVAL;
@@ -660,6 +800,7 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     const int g = bsh.grid;
     HIP_TRY(hipMemsetAsync(d.n_active, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL((mw_batch_spmv_kernel<A, 0>), dim3(g), dim3(BNT), 0, s, d, x, q, sa);
+    if (vg > 0) hipLaunchKernelGGL((mw_batch_vec_spmv_kernel<A, 0>), dim3(vg), dim3(BNT), 0, s, d, x, q, sa);
     if (pc) {
         launch_jacobi_dinv(M, (double *)d.dinv, s);
         hipLaunchKernelGGL((mw_batch_init_kernel<A, true>), dim3(g), dim3(BNT), 0, s, d, b, q, r, p, sa, sb, sc);
@@ -676,12 +817,13 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     int chunks = 0;
     if (*hcount > 0 && use_graph) {
         BatchGraph &G = batch_graph();
-        BatchKey key{A, nsys, ns, n, M->nnz, chunk, g, pc ? 1 : 0,
-                     {r, p, q, x, sa, sb, sc, base, d.sp, d.sc, d.sv, d.soff, d.smask, d.dinv}};
+        BatchKey key{A, nsys, ns, n, M->nnz, chunk, g, pc ? 1 : 0, vg,
+                     {r, p, q, x, sa, sb, sc, base, d.sp, d.sc, d.sv, d.soff, d.smask, d.dinv, M->row_ptr, M->col_idx,
+                      M->val}};
         if (!(G.valid && G.key == key)) {
             G.release();
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            rc = enqueue_batch_chunk_pc<A>(pc, d, chunk, g, r, p, q, x, sa, sb, sc, s);
+            rc = enqueue_batch_chunk_pc<A>(pc, d, chunk, g, vg, r, p, q, x, sa, sb, sc, s);
             hipGraph_t gr = nullptr;
             const hipError_t ce = hipStreamEndCapture(s, &gr);
             if (rc) return rc;
@@ -696,7 +838,7 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
         if (use_graph) {
             HIP_TRY(hipGraphLaunch(batch_graph().exec, s));
         } else {
-            rc = enqueue_batch_chunk_pc<A>(pc, d, chunk, g, r, p, q, x, sa, sb, sc, s);
+            rc = enqueue_batch_chunk_pc<A>(pc, d, chunk, g, vg, r, p, q, x, sa, sb, sc, s);
             if (rc) return rc;
         }
         ++chunks;
@@ -784,14 +926,14 @@ int mw_cg_batched_tune(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, c
     hipStream_t s = (hipStream_t)stream;
     double best_t = 0.0;
     mw_shape_t win{};
-    int last = -1;
-    for (int g : grids) {
-        mw_shape_t cand{g, 0, 0, iters, 0, 0.0};
+    // the time of `iters` lockstep iterations with shape `cand` (best of the
+    // runs after the one that captures the chunk's graph)
+    auto run = [&](mw_shape_t cand, double *out) -> int {
         mw_cg_opts_t o{};
         o.normalize = 1;
         o.shape = &cand;
         double t = 0.0;
-        for (int rep = 0; rep < 3; ++rep) {  // the first run captures the chunk's graph
+        for (int rep = 0; rep < 3; ++rep) {
             HIP_TRY(hipMemsetAsync(x, 0, xbytes, s));
             mw_cg_info_t info{};
             const int rc = mw_cg_solve_batched(a, nsys, sys_row_off, A, b, x, 0.0, iters, &o, workspace, nullptr,
@@ -803,16 +945,34 @@ int mw_cg_batched_tune(mw_arith_t a, int32_t nsys, const int32_t *sys_row_off, c
             }
             if (rep == 1 || (rep > 1 && info.seconds < t)) t = info.seconds;
         }
+        *out = t;
         if (best_t == 0.0 || t < best_t) {
             best_t = t;
             win = cand;
         }
+        return MW_OK;
+    };
+    int last = -1;
+    int ns = 0;
+    for (int k = 0; k < nsys; ++k) ns += (sys_row_off[k + 1] - sys_row_off[k] + 63) / 64;
+    const int need = persistent_grid(blocks_for(ns > 0 ? ns : 1, NWAVE));
+    int vec_slices = 0;
+    for (int g : grids) {
+        double t = 0.0;
+        if (const int rc = run(mw_shape_t{g, 0, 0, iters, 0, 0.0}, &t)) return rc;
+        vec_slices = g_last_vec_slices;
         // larger grids clamp to the slices' own count: stop once they do
-        int ns = 0;
-        for (int k = 0; k < nsys; ++k) ns += (sys_row_off[k + 1] - sys_row_off[k] + 63) / 64;
-        const int need = persistent_grid(blocks_for(ns > 0 ? ns : 1, NWAVE));
         if (g >= need || g == last) break;
         last = g;
+    }
+    // lanes per row of the vector-row slices (rows per wavefront = 64 /
+    // lanes), on the best grid, when the batch has such slices
+    if (vec_slices > 0) {
+        const int g = win.spmv_grid;
+        for (int l = 2; l <= 64; l *= 2) {
+            double t = 0.0;
+            if (const int rc = run(mw_shape_t{g, 0, 0, iters, l, 0.0}, &t)) return rc;
+        }
     }
     win.us_per_iteration = 1e6 * best_t / iters;
     win.chunk = 0;

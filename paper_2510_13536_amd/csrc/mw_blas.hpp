@@ -373,6 +373,7 @@ struct CgShape {
 struct BatchShape {
     int grid;   // workgroups of the slice kernels
     int chunk;  // iterations per chunk
+    int lanes;  // lanes per row of the vector-row slices (0: each slice's rule)
 };
 CgShape cg_shape(int a, int n, int nnz, int tiles, const mw_shape_t *explicit_shape, int opts_chunk);
 BatchShape batch_shape(int a, int n, int nnz, int nsys, int ns, const mw_shape_t *explicit_shape, int opts_chunk);

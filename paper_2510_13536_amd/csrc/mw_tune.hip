@@ -252,6 +252,7 @@ BatchShape batch_shape(int a, int n, int nnz, int nsys, int ns, const mw_shape_t
     const int g = persistent_grid(blocks_for(ns > 0 ? ns : 1, NWAVE));
     r.grid = (s.spmv_grid > 0 && s.spmv_grid < g) ? s.spmv_grid : g;
     r.chunk = opts_chunk > 0 ? opts_chunk : (s.chunk > 0 ? s.chunk : 16);
+    r.lanes = s.lanes;
     return r;
 }
 
@@ -281,6 +282,7 @@ int mw_cg_shape(mw_arith_t a, int32_t n, int32_t nnz, int32_t nsys, mw_shape_t *
     } else {
         shape->spmv_grid = tuned ? t.spmv_grid : 0;
         shape->chunk = tuned && t.chunk > 0 ? t.chunk : 16;
+        shape->lanes = tuned ? t.lanes : 0;
     }
     shape->us_per_iteration = tuned ? t.us_per_iteration : 0.0;
     return tuned ? 1 : 0;

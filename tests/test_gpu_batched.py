@@ -216,3 +216,74 @@ def test_batched_reuse_with_other_sparsity(mw, arith):
             trg = O.true_residual(arith, A, b, xg[:, off[s]:off[s + 1]]) / nb
             tro = O.true_residual(arith, A, b, xo) / nb
             assert trg <= 10 * tro, (s, trg, tro)
+
+
+def _arrow(n, seed):
+    """SPD arrow: tridiag(-1, 3, -1) plus a dense first row and column
+    (weights U[0.1, 0.5]) and a first diagonal entry that dominates them."""
+    rng = np.random.default_rng(seed)
+    M = sp.diags([-np.ones(n - 1), 3.0 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).tolil()
+    w = rng.uniform(0.1, 0.5, n - 1)
+    M[0, 1:] = w
+    M[1:, 0] = w.reshape(-1, 1)
+    M[0, 0] = 2.0 * (w.sum() + 2.0)
+    return P.CSR.from_scipy(M.tocsr())
+
+
+@pytest.fixture(scope="module")
+def long_row_batch():
+    """Systems whose slices take vector rows: an arrow (one row of n entries
+    in an otherwise tridiagonal matrix; SELL-64 would pad that slice to 64
+    such rows) and a banded system of 81 entries per row, among Poisson and
+    circulant systems that keep SELL-64."""
+    mats = [P.poisson2d(20, 15), _arrow(2000, 1), P.banded_spd(1500, half_bw=40, seed=2, dseed=3, scale=False),
+            P.circulant_laplacian(700, [1, 9, 50], [0.5, 0.8, 0.3]), _arrow(300, 4)]
+    bs = [m.matvec(np.random.default_rng(60 + s).uniform(-1, 1, m.n)) for s, m in enumerate(mats)]
+    return mats, bs, P.batch_from_systems(mats, bs)
+
+
+def _per_system(arith, mats, bs, B, x, iters, status, tol):
+    off = B.sys_row_off
+    va = "fp64" if arith in MIXED else arith
+    for s, (A, b) in enumerate(zip(mats, bs)):
+        if arith in MIXED:
+            xo, io = O.cg_solve(MIXED[arith], A, b, tol=tol, maxit=20000, mixed=True)
+        else:
+            xo, io = O.cg_solve(arith, A, b, tol=tol, maxit=20000)
+        assert int(status[s]) == 0 and io["status"] == "ok", (s, status[s], io)
+        assert abs(int(iters[s]) - io["iters"]) <= max(1, int(0.02 * io["iters"])), (s, iters[s], io["iters"])
+        nb = np.linalg.norm(b)
+        trg = O.true_residual(va, A, b, x[:, off[s]:off[s + 1]]) / nb
+        tro = O.true_residual(va, A, b, xo) / nb
+        assert trg <= 10 * max(tro, 1e-300), (s, trg, tro)
+
+
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qtw", "qqw", "mxqtw"])
+def test_batched_vector_row_slices(mw, long_row_batch, arith):
+    """Vector-row slices (long or very uneven rows) against the oracle per
+    system, with the lanes per row of each slice's rule and with 4 and 64
+    forced; graph replay and direct launches give the same bits."""
+    mats, bs, B = long_row_batch
+    Ad = mw.DeviceCSR.from_host(B.A)
+    for lanes in (None, 4, 64):
+        shape = {"lanes": lanes} if lanes else None
+        x, iters, status, _, _ = mw.cg_solve_batched(arith, Ad, B.sys_row_off, dev(B.b), tol=1e-12, maxit=20000,
+                                                     shape=shape)
+        x2, iters2, _, _, _ = mw.cg_solve_batched(arith, Ad, B.sys_row_off, dev(B.b), tol=1e-12, maxit=20000,
+                                                  shape=shape, graph=False)
+        assert np.array_equal(iters, iters2)
+        assert np.array_equal(x.cpu().numpy().view(np.uint64), x2.cpu().numpy().view(np.uint64))
+        _per_system(arith, mats, bs, B, x.cpu().numpy(), iters, status, 1e-12)
+
+
+def test_batched_tuner_sweeps_lanes_of_vector_slices(mw, long_row_batch):
+    mats, bs, B = long_row_batch
+    Ad = mw.DeviceCSR.from_host(B.A)
+    tuned_before, _ = mw.cg_shape("dw", B.A.n, B.A.nnz, nsys=B.nsys)
+    assert not tuned_before
+    best = mw.cg_batched_tune("dw", Ad, B.sys_row_off, dev(B.b), iters=8)
+    assert best["lanes"] in (0, 2, 4, 8, 16, 32, 64) and best["spmv_grid"] > 0
+    tuned, now = mw.cg_shape("dw", B.A.n, B.A.nnz, nsys=B.nsys)
+    assert tuned and now["lanes"] == best["lanes"] and now["spmv_grid"] == best["spmv_grid"]
+    x, iters, status, _, _ = mw.cg_solve_batched("dw", Ad, B.sys_row_off, dev(B.b), tol=1e-12, maxit=20000)
+    _per_system("dw", mats, bs, B, x.cpu().numpy(), iters, status, 1e-12)

@@ -122,6 +122,9 @@ def test_batched_tuner_and_grid_independence(mw):
     assert best["spmv_grid"] in (256, 512, 1024, 1536, 2048) and best["us_per_iteration"] > 0
     tuned, now = mw.cg_shape("qtw", B.A.n, B.A.nnz, len(B.sys_row_off) - 1)
     assert tuned and now["spmv_grid"] == best["spmv_grid"]
+    if best["lanes"]:  # lanes per row of vector-row slices set the row association: compare like with like
+        ref = mw.cg_solve_batched("qtw", Ad, B.sys_row_off, bd, tol=1e-12,
+                                  shape={"spmv_grid": 8, "chunk": 4, "lanes": best["lanes"]})
     got = mw.cg_solve_batched("qtw", Ad, B.sys_row_off, bd, tol=1e-12)   # tuned grid, default chunk
     assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
     assert np.array_equal(got[0].cpu().numpy().view(np.uint64), ref[0].cpu().numpy().view(np.uint64))
