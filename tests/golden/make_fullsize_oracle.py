@@ -5,7 +5,7 @@ and the seeded generators (paper_2510_13536_amd/problems.py).
 
   c2_oracle_solves.json   3D Poisson 128^3 (x* ~ U[-1,1] seed 2, b = A x*),
                           CG from x0 = 0 to 1e-12 in FP64, DW, QDW, TW, QTW,
-                          QW, QQW
+                          QW, QQW, QTWE and the mixed MXDW / MXQTW
                           (Alg. 1 with Sec. IV-C/IV-D): status, iterations,
                           recursive relative residual and the true relative
                           residual ||b - A x|| / ||b|| of the oracle's x,
@@ -32,12 +32,20 @@ import oracle as O  # noqa: E402
 from paper_2510_13536_amd import problems as P  # noqa: E402
 
 
+# the mixed types: FP64 vectors, SpMV rows and dots in their base arithmetic
+MIXED = {"mxdw": "dw", "mxqtw": "qtw"}
+
+
 def solve_record(arith, A, b, tol):
     t = time.time()
-    x, info = O.cg_solve(arith, A, b, tol=tol)
+    if arith in MIXED:
+        x, info = O.cg_solve(MIXED[arith], A, b, tol=tol, mixed=True)
+    else:
+        x, info = O.cg_solve(arith, A, b, tol=tol)
     nb = float(np.linalg.norm(b))
+    va = "fp64" if arith in MIXED else arith
     return {"status": info["status"], "iters": int(info["iters"]), "rel_res": float(info["rel_res"]),
-            "true_rel_res": O.true_residual(arith, A, b, x) / nb, "oracle_seconds": round(time.time() - t, 1)}
+            "true_rel_res": O.true_residual(va, A, b, x) / nb, "oracle_seconds": round(time.time() - t, 1)}
 
 
 def c4_sample(B):
@@ -56,7 +64,7 @@ def main(which):
                "n": A.n, "nnz": A.nnz, "oracle_threads": O.num_threads(), "solves": {}}
         if os.path.exists(path):  # keep the solves already stored (deterministic)
             out["solves"] = json.load(open(path))["solves"]
-        for ar in ("fp64", "dw", "qdw", "tw", "qtw", "qw", "qqw"):
+        for ar in ("fp64", "dw", "qdw", "tw", "qtw", "qw", "qqw", "qtwe", "mxdw", "mxqtw"):
             if ar in out["solves"]:
                 continue
             out["solves"][ar] = solve_record(ar, A, b, 1e-12)

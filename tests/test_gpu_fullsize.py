@@ -121,12 +121,13 @@ def _golden(name):
     return json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)))
 
 
-@pytest.mark.parametrize("arith", ARITHS + ["qw", "qqw"])
+@pytest.mark.parametrize("arith", ARITHS + ["qw", "qqw", "qtwe", "mxdw", "mxqtw"])
 def test_c2_full_solve(mods, c2, arith):
     """The whole 128^3 solve against the oracle's solve in the same
     arithmetic (stored by tests/golden/make_fullsize_oracle.py, which runs
-    only the oracle): same status, iterations within 2 %, true residual
-    (formed exactly) within 10x of the oracle's."""
+    only the oracle; the mixed types against its mixed solve): same status,
+    iterations within 2 %, true residual (formed exactly) within 10x of the
+    oracle's."""
     torch, mw = mods
     A, b, _ = c2
     ref = _golden("c2_oracle_solves.json")
@@ -136,7 +137,8 @@ def test_c2_full_solve(mods, c2, arith):
     assert ig["status"] == io["status"] == "ok" and ig["rel_res"] < 1e-12
     assert abs(ig["iters"] - io["iters"]) <= max(1, int(0.02 * io["iters"])), (ig, io)
     nb = np.linalg.norm(b)
-    tr = O.true_residual(arith, A, b, xg.cpu().numpy()) / nb
+    va = "fp64" if arith in ("mxdw", "mxqtw") else arith  # the mixed types' x is FP64
+    tr = O.true_residual(va, A, b, xg.cpu().numpy()) / nb
     assert tr <= 10 * io["true_rel_res"], (tr, io["true_rel_res"])
 
 
