@@ -106,7 +106,8 @@ def copy_ceiling(torch, dev, nbytes=1 << 30, reps=10):
 def bench_batched(mw, P, torch, dev, nsys=512, tune=True, loop=True):
     """512 uneven SPD systems (Poisson 2D/3D and circulant Laplacians, n in
     [1024, 65536]): one batched solve vs a loop of single solves, QTW and
-    DW, tol 1e-12 (loop=False: the batched solves alone, for profiling)."""
+    DW, tol 1e-12 (loop=False: the batched solves alone, for profiling);
+    then the batched solve alone in the mixed types MXDW and MXQTW."""
     import numpy as np
     B = P.batch_systems(nsys=nsys)
     Ad = mw.DeviceCSR.from_host(B.A, dev)
@@ -140,6 +141,20 @@ def bench_batched(mw, P, torch, dev, nsys=512, tune=True, loop=True):
             out[ar].update({"loop_s": round(tl, 4), "speedup": round(tl / tb, 2),
                             "iters_within_2pct_of_loop":
                                 float(np.mean(np.abs(its - iters) <= np.maximum(1, 0.02 * its)))})
+        log("batched %s: %s" % (ar, out[ar]))
+    # the mixed types (FP64 vectors, rows and dots in DW / QTW), batched solve only
+    for ar in ("mxdw", "mxqtw"):
+        x = torch.zeros((WORDS[ar], B.A.n), dtype=torch.float64, device=dev)
+        shape = mw.cg_batched_tune(ar, Ad, B.sys_row_off, bd, iters=16) if tune else None
+        mw.cg_solve_batched(ar, Ad, B.sys_row_off, bd, x=x, tol=1e-12, maxit=100)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, iters, status, rel, info = mw.cg_solve_batched(ar, Ad, B.sys_row_off, bd, x=x, tol=1e-12)
+        torch.cuda.synchronize()
+        out[ar] = {"batched_s": round(time.perf_counter() - t0, 4), "tuned_grid": shape["spmv_grid"] if shape else None,
+                   "max_iters": int(iters.max()), "mean_iters": round(float(iters.mean()), 1),
+                   "all_converged": bool((status == 0).all())}
         log("batched %s: %s" % (ar, out[ar]))
     return out
 
