@@ -10,15 +10,17 @@
 // for exactly one system; slices whose rows fit diagonal slots store no
 // column indices, as in the single-system plan (fill_slice).  Slices with
 // very uneven rows (the longest more than VEC_PAD times the average, so
-// SELL-64 would pad every row to it) are not copied: they are summed as vector rows straight from the caller's CSR
-// arrays, L lanes per row (vec_slice_sum), so one long row costs neither
-// padding nor a single lane's sequential chain.  Per-system reductions use one partial per slice
-// (a wavefront shuffle tree, no workgroup barrier), summed in slice order by
-// one workgroup per system.
+// SELL-64 would pad every row to it) are not copied: they are summed as
+// vector rows straight from the caller's CSR arrays, L lanes per row
+// (vec_slice_sum), so one long row costs neither padding nor a single
+// lane's sequential chain.  Per-system reductions use one partial per
+// slice (a wavefront shuffle tree, no workgroup barrier), summed in slice
+// order by one workgroup per system.
 //
-// One lockstep iteration of the whole batch is five kernels, replayed from
-// a captured hipGraph in chunks:
-//   1. q = A p over the slices of running systems; p^T q per slice
+// One lockstep iteration of the whole batch is five kernels (six when there
+// are vector-row slices), replayed from a captured hipGraph in chunks:
+//   1. q = A p over the slices of running systems; p^T q per slice (the
+//      vector-row slices in a kernel of their own right after)
 //   2. one workgroup per running system: sigma, alpha = rho / sigma
 //   3. r = r - alpha q, quasi normalisation, r^T r per slice
 //   4. one workgroup per running system: rho', FP64 test, beta; a system
