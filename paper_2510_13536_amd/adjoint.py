@@ -23,16 +23,18 @@ def _vector_arith(arith):
 
 class MWCGSolve(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, val, b, row_ptr, col_idx, arith, tol, maxit, info_out):
+    def forward(ctx, val, b, row_ptr, col_idx, arith, tol, maxit, info_out, precond=None):
         A = mw.DeviceCSR(b.numel(), row_ptr, col_idx, val.detach().contiguous())
         # one SpMV plan (the solver's own choice) and workspace serve the
         # forward and the adjoint solve
         plan = mw.Plan(A, solver=arith)
         ws = mw.cg_workspace(arith, A)
-        x, info = mw.cg_solve(arith, A, b.detach().contiguous(), tol=tol, maxit=maxit, plan=plan, workspace=ws)
+        x, info = mw.cg_solve(arith, A, b.detach().contiguous(), tol=tol, maxit=maxit, plan=plan, workspace=ws,
+                              precond=precond)
         if info["status"] != "ok":
             raise mw.MWError("forward solve did not converge: %s" % info)
         ctx.A, ctx.arith, ctx.tol, ctx.maxit, ctx.info_out = A, arith, tol, maxit, info_out
+        ctx.precond = precond
         ctx.plan, ctx.ws = plan, ws
         ctx.x = x
         if info_out is not None:
@@ -43,7 +45,7 @@ class MWCGSolve(torch.autograd.Function):
     def backward(ctx, grad_x):
         A, arith = ctx.A, ctx.arith
         lam, info = mw.cg_solve(arith, A, grad_x.detach().contiguous().reshape(-1), tol=ctx.tol, maxit=ctx.maxit,
-                                plan=ctx.plan, workspace=ctx.ws)
+                                plan=ctx.plan, workspace=ctx.ws, precond=ctx.precond)
         if info["status"] != "ok":
             raise mw.MWError("adjoint solve did not converge: %s" % info)
         if ctx.info_out is not None:
@@ -53,12 +55,14 @@ class MWCGSolve(torch.autograd.Function):
         va = _vector_arith(arith)
         grad_b = mw.elementwise(va, "tofp64", lam).reshape(-1)
         grad_val = mw.csr_grad(va, A, lam, ctx.x)
-        return grad_val, grad_b, None, None, None, None, None, None
+        return grad_val, grad_b, None, None, None, None, None, None, None
 
 
-def cg_solve(A, val, b, arith="qtw", tol=1e-12, maxit=None, info=None):
+def cg_solve(A, val, b, arith="qtw", tol=1e-12, maxit=None, info=None, precond=None):
     """x = A(val)^-1 b, differentiable in val and b.  A supplies n, row_ptr
-    and col_idx (a DeviceCSR); val: FP64 values on A's pattern."""
+    and col_idx (a DeviceCSR); val: FP64 values on A's pattern.  precond:
+    None or "jacobi", for the forward and the adjoint solve alike (it
+    changes how the solves get there, not the gradient's formula)."""
     if maxit is None:
         maxit = 10 * A.n
-    return MWCGSolve.apply(val, b, A.row_ptr, A.col_idx, arith, tol, maxit, info)
+    return MWCGSolve.apply(val, b, A.row_ptr, A.col_idx, arith, tol, maxit, info, precond)

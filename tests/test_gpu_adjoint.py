@@ -145,3 +145,26 @@ def test_adjoint_mixed_matches_oracle_gradient(mods, arith):
     gt = -(lo[0] * xo[0])
     np.testing.assert_allclose(theta.grad.cpu().numpy(), gt, rtol=1e-9, atol=1e-11 * np.abs(gt).max())
     np.testing.assert_allclose(b.grad.cpu().numpy(), lo[0], rtol=1e-9, atol=1e-11 * np.abs(lo).max())
+
+
+@pytest.mark.parametrize("arith", ["dw", "qtw"])
+def test_adjoint_with_jacobi_matches_plain(mods, arith):
+    """Jacobi-preconditioned forward and adjoint solves give the gradient of
+    the plain ones (the same x and lam to the solves' tolerance), on a
+    system whose diagonal varies (A = L + diag(theta))."""
+    torch, mw, adjoint = mods
+    Q = _problem(10)
+    Ad = mw.DeviceCSR.from_host(Q.lap)
+    grads = []
+    for pc in (None, "jacobi"):
+        theta = torch.as_tensor(Q.theta, device="cuda").requires_grad_(True)
+        b = torch.as_tensor(Q.b, device="cuda").requires_grad_(True)
+        val = torch.as_tensor(Q.lap.val, device="cuda").index_add(0, torch.as_tensor(Q.diag_pos, device="cuda"),
+                                                                  theta)
+        info = {}
+        x = adjoint.cg_solve(Ad, val, b, arith=arith, tol=1e-20, info=info, precond=pc)
+        (0.5 * ((x - torch.as_tensor(Q.x_target, device="cuda")) ** 2).sum()).backward()
+        assert info["forward"]["status"] == "ok" and info["adjoint"]["status"] == "ok"
+        grads.append((theta.grad.cpu().numpy(), b.grad.cpu().numpy()))
+    for g0, g1 in zip(*grads):
+        np.testing.assert_allclose(g1, g0, rtol=1e-12, atol=1e-14 * np.abs(g0).max())
