@@ -397,9 +397,21 @@ def bench_table1(mw, P, torch, dev, iters=100):
             row[ar] = round(1e6 * best / max(info["iters"], 1), 1)
         row["over_fp64"] = {ar: round(row[ar] / row["fp64"], 2) for ar in WORDS if ar != "fp64"}
         row["qtw_over_dw"] = round(row["qtw"] / row["dw"], 2)
+        # for comparison: FP64 and QTW with the SELL-64 plan (one lane per row)
+        splan = mw.Plan(Ad)
+        for ar in ("fp64", "qtw"):
+            ws = mw.cg_workspace(ar, Ad)
+            x = torch.zeros((WORDS[ar], A.n), dtype=torch.float64, device=dev)
+            mw.cg_solve(ar, Ad, b, x=x, tol=0.0, maxit=4, workspace=ws, plan=splan)
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = mw.cg_solve(ar, Ad, b, x=x, tol=0.0, maxit=iters, workspace=ws, plan=splan)
+            torch.cuda.synchronize()
+            row["%s_%s_us" % (splan.format, ar)] = round(1e6 * (time.perf_counter() - t0) / max(info["iters"], 1), 1)
         out[name] = row
         log("table I stand-in %s: %s" % (name, row))
-        del Ad, plan
+        del Ad, plan, splan
     return out
 
 
@@ -498,6 +510,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape tuner (built-in shapes)")
     ap.add_argument("--table1", action="store_true",
                     help="also time iterations on banded stand-ins of the paper's Table I matrices")
+    ap.add_argument("--table1-only", action="store_true",
+                    help="run only the Table I stand-ins (per-iteration time of every arithmetic) and print their line")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 512-system batched comparison (for profiling that path) and print its line")
     ap.add_argument("--no-loop", action="store_true",
@@ -529,6 +543,13 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.table1_only:
+        t1 = bench_table1(mw, P, torch, dev)
+        print(json.dumps({"metric": "CG time per iteration on banded stand-ins of the paper's Table I matrices",
+                          "value": t1["nd24k"]["qtw"], "unit": "us", "n_gpus": 1, "higher_is_better": False,
+                          "dtype": "f64", "data": "synthetic", "config": {"workload": "Table I stand-ins"},
+                          "extra": {"table1_standins": t1}}), flush=True)
+        return
     if args.batched_only:
         bt = bench_batched(mw, P, torch, dev, tune=not args.no_tune, loop=not args.no_loop)
         print(json.dumps({"metric": "batched QTW CG time-to-1e-12 (512 systems, one lockstep solve)",
