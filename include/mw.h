@@ -39,7 +39,10 @@
  *             enqueued) and MW_EHIP for a HIP runtime error (details from
  *             mw_last_error()).
  *   Threads:  calls are re-entrant across streams when their workspaces
- *             and outputs are distinct.
+ *             and outputs are distinct.  The solvers' own streams, captured
+ *             graphs and pinned host flags are kept per calling thread (the
+ *             streams also per device, the one current at the call), and
+ *             held until the process ends.
  */
 #ifndef MW_H
 #define MW_H

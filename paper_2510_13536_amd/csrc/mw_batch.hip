@@ -595,13 +595,6 @@ struct BatchParams {
     int32_t maxit, normalize;
 };
 
-hipStream_t batch_stream()
-{
-    thread_local hipStream_t s = nullptr;
-    if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
-    return s;
-}
-
 // Vector-row slices of the calling thread's last batched solve (read by
 // the tuner to decide whether lanes per row is worth sweeping).
 thread_local int g_last_vec_slices = 0;
@@ -709,7 +702,7 @@ int batched_a(int32_t nsys, const int32_t *off, const mw_csr_t *M, const double 
     const BatchShape bsh = batch_shape(A, n, M->nnz, nsys, ns, opts ? opts->shape : nullptr, opts ? opts->chunk : 0);
     const int chunk = bsh.chunk;
 
-    hipStream_t s = batch_stream();
+    hipStream_t s = thread_stream<1>();
     int32_t *hcount = pinned_count();
     if (!s || !hcount) return hip_fail(hipErrorOutOfMemory, "stream/pinned buffer");
     SolveEvents se;

@@ -401,14 +401,6 @@ Flags *pinned_flags()
     return buf;
 }
 
-// The library's own stream per thread (default priority): graph capture is
-// not possible on the legacy default stream a caller may pass.
-hipStream_t own_stream()
-{
-    thread_local hipStream_t s = nullptr;
-    if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
-    return s;
-}
 
 struct EventPool {
     hipEvent_t *e = nullptr;
@@ -587,7 +579,7 @@ int cg_a(const mw_csr_t *M, const double *b, double *x, double tol, int32_t maxi
     // events recorded by graph nodes cannot be read back: timing uses direct launches
     const bool use_graph = !(opts && opts->no_graph) && !prof;
 
-    hipStream_t s = own_stream();
+    hipStream_t s = thread_stream<0>();
     Flags *fl = pinned_flags();
     if (!s || !fl) return hip_fail(hipErrorOutOfMemory, "stream/pinned buffer");
 

@@ -165,6 +165,27 @@ inline bool valid_csr(const mw_csr_t *A)
     return A && A->n > 0 && A->nnz >= 0 && A->row_ptr && A->col_idx && A->val;
 }
 
+// The library's own stream for the calling thread on the current device
+// (default priority, non-blocking: graph capture is not possible on the
+// legacy default stream a caller may pass).  One per (thread, device, use),
+// created at first use; nullptr when it cannot be created.
+constexpr int MAX_DEVICES = 64;
+template <int USE>
+hipStream_t thread_stream()
+{
+    thread_local hipStream_t s[MAX_DEVICES] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (!s[dev] && hipStreamCreateWithFlags(&s[dev], hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        s[dev] = nullptr;
+    }
+    return s[dev];
+}
+
 }  // namespace mwh
 
 #define HIP_TRY(call)                                              \
