@@ -516,6 +516,8 @@ def main():
                     help="run only the 512-system batched comparison (for profiling that path) and print its line")
     ap.add_argument("--no-loop", action="store_true",
                     help="with --batched-only: skip the loop of single solves (for profiling the batched one)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint workload (forward + adjoint QTW solves) and print its line")
     ap.add_argument("--illcond-only", action="store_true",
                     help="run only the ill-conditioned banded workload and print its line")
     ap.add_argument("--illcond-maxit", type=int, default=20000,
@@ -556,6 +558,13 @@ def main():
                           "value": bt["qtw"]["batched_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
                           "dtype": "f64", "data": "synthetic", "config": {"workload": bt["workload"]},
                           "extra": {"batched": bt}}), flush=True)
+        return
+    if args.adjoint_only:
+        ad = bench_adjoint(mw, P, torch, dev)
+        print(json.dumps({"metric": "adjoint gradient (forward + adjoint QTW solve), tol 1e-12",
+                          "value": round(ad["tol_1e-12"]["forward_s"] + ad["tol_1e-12"]["backward_s"], 4),
+                          "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": ad["workload"]}, "extra": {"adjoint": ad}}), flush=True)
         return
     if args.illcond_only:
         ic = bench_illcond(mw, P, torch, dev, maxit=args.illcond_maxit, hist_every=args.illcond_hist)

@@ -354,17 +354,35 @@ __global__ void __launch_bounds__(NT) mw_vec_spmv_kernel(int n, const int32_t *_
 // grad_val[k] = -(lam_i * x_j) for the k-th stored entry (i, j): the
 // derivative of a loss with respect to A_ij when x = A^-1 b and lam solves
 // A^T lam = dL/dx.  The product is formed in the arithmetic and rounded
-// to FP64 (FP64: -(lam_i * x_j), one rounding).  One thread per row.
+// to FP64 (FP64: -(lam_i * x_j), one rounding).  One wavefront per block
+// of 64 rows: the block's entries are contiguous in the CSR arrays, so the
+// lanes walk them 64 at a time (coalesced column loads and gradient
+// stores); a lane finds its entry's row by a binary search over the
+// block's row starts, which the lanes hold one each.
 template <int A>
 __global__ void __launch_bounds__(NT) mw_csr_grad_kernel(int n, const int32_t *__restrict__ row_ptr,
                                                          const int32_t *__restrict__ col,
                                                          const double *__restrict__ lam,
                                                          const double *__restrict__ x, double *__restrict__ grad)
 {
-    const long i = (long)xcd_remap(blockIdx.x, gridDim.x) * NT + threadIdx.x;
-    if (i >= n) return;
-    const Num<A> li = load<A>(lam, n, i);
-    for (int z = row_ptr[i]; z < row_ptr[i + 1]; ++z) grad[z] = -to_fp64<A>(mul<A>(li, load<A>(x, n, col[z])));
+    const long r0 = ((long)blockIdx.x * NWAVE + wave_id()) * 64;
+    if (r0 >= n) return;
+    const int lane = threadIdx.x & 63;
+    // row starts of the block; lanes past the last row hold a start no
+    // entry index reaches
+    const int start = r0 + lane < n ? row_ptr[r0 + lane] : 0x7fffffff;
+    const int e0 = row_ptr[r0];
+    const int e1 = row_ptr[r0 + 64 < n ? r0 + 64 : n];
+    for (int z0 = e0; z0 < e1; z0 += 64) {
+        const int z = z0 + lane;
+        // the last row whose start is <= z (a row with entries: an empty
+        // row's start equals the next row's); all lanes take part
+        int l = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (__shfl(start, l + step, 64) <= z) l += step;
+        if (z < e1) grad[z] = -to_fp64<A>(mul<A>(load<A>(lam, n, r0 + l), load<A>(x, n, col[z])));
+    }
 }
 
 // ------------------------------------------------------------- CSR check
@@ -461,7 +479,7 @@ __global__ void __launch_bounds__(NT) mw_sell_fill_kernel(int n, int ns, const i
                                                           const int32_t *__restrict__ slice_ptr,
                                                           int32_t *__restrict__ scol, double *__restrict__ sval,
                                                           int32_t *__restrict__ soff, uint64_t *__restrict__ smask,
-                                                          int32_t *__restrict__ ndiag)
+                                                          int32_t *__restrict__ is_diag)
 {
     const int s = blockIdx.x * NWAVE + wave_id();
     const int lane = threadIdx.x & 63;
@@ -471,7 +489,27 @@ __global__ void __launch_bounds__(NT) mw_sell_fill_kernel(int n, int ns, const i
     const int w = (slice_ptr[s + 1] - b) / 64;
     const int rs = row < n ? row_ptr[row] : 0;
     const int len = row < n ? row_ptr[row + 1] - rs : 0;
-    if (fill_slice(b, w, lane, row, rs, len, col, val, scol, sval, soff, smask) && lane == 0) atomicAdd(ndiag, 1);
+    const bool diag = fill_slice(b, w, lane, row, rs, len, col, val, scol, sval, soff, smask);
+    if (lane == 0) is_diag[s] = diag ? 1 : 0;
+}
+
+// *out = number of non-zero flags[0 .. ns) (one workgroup of FIN_NT
+// threads; a single counter bumped by every slice serialises on it).
+__global__ void __launch_bounds__(FIN_NT) mw_flag_count_kernel(int ns, const int32_t *__restrict__ flags,
+                                                               int32_t *__restrict__ out)
+{
+    __shared__ int part[FIN_NT / 64];
+    int c = 0;
+    for (int i = threadIdx.x; i < ns; i += FIN_NT) c += flags[i] != 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < FIN_NT / 64; ++w) t += part[w];
+        *out = t;
+    }
 }
 
 // Plan buffer: slice_ptr, the width scratch, the 64-bit total and the
@@ -738,9 +776,10 @@ int plan_build(const mw_csr_t *A, void *buffer, size_t bytes, mw_spmv_plan_t *pl
     HIP_TRY(hipStreamSynchronize(s));
     const long long stored = htot[0];
     if (stored > L.cap || stored > 0x7fffffffLL) return MW_OK;  // CSR fallback
-    HIP_TRY(hipMemsetAsync(ndiag, 0, sizeof(int32_t), s));
+    // the width scratch, read by the scan only, takes the per-slice flags
     hipLaunchKernelGGL(mw_sell_fill_kernel, dim3(nbw), dim3(NT), 0, s, n, ns, A->row_ptr, A->col_idx, A->val, sp,
-                       scol, sval, soff, smask, ndiag);
+                       scol, sval, soff, smask, width);
+    hipLaunchKernelGGL(mw_flag_count_kernel, dim3(1), dim3(FIN_NT), 0, s, ns, width, ndiag);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(htot + 1, ndiag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -848,8 +887,8 @@ int scratch_slots(double **out)
 template <int A>
 int grad_a(const mw_csr_t *M, const double *lam, const double *x, double *grad, hipStream_t s)
 {
-    hipLaunchKernelGGL((mw_csr_grad_kernel<A>), dim3(blocks_for(M->n, NT)), dim3(NT), 0, s, M->n, M->row_ptr,
-                       M->col_idx, lam, x, grad);
+    hipLaunchKernelGGL((mw_csr_grad_kernel<A>), dim3(blocks_for(blocks_for(M->n, 64), NWAVE)), dim3(NT), 0, s, M->n,
+                       M->row_ptr, M->col_idx, lam, x, grad);
     HIP_TRY(hipGetLastError());
     return MW_OK;
 }

@@ -242,19 +242,39 @@ __device__ __forceinline__ bool fill_slice(int b, int w, int lane, long row, int
 {
     const int sl = b >> 6;
     int k = 0;  // this lane's entries placed so far
+    // the lane's next FW entries (k .. k + FW - 1), loaded ahead so that a
+    // slot does not wait for the load of the entry it places
+    constexpr int FW = 4;
+    int c[FW];
+    double v[FW];
+#pragma unroll
+    for (int d = 0; d < FW; ++d) {
+        c[d] = d < len ? col[rs + d] : 0;
+        v[d] = d < len ? val[rs + d] : 0.0;
+    }
     for (int j = 0; j < w; ++j) {
-        const int cand = k < len ? (int)(col[rs + k] - row) : 0x7fffffff;
+        const int cand = k < len ? (int)(c[0] - row) : 0x7fffffff;
         int m = cand;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
         const bool has = k < len && cand == m;
         const uint64_t mask = __ballot(has);
-        sval[sell_pos(b, w, j, lane)] = has ? val[rs + k] : 0.0;
+        sval[sell_pos(b, w, j, lane)] = has ? v[0] : 0.0;
         if (lane == 0) {
             soff[sl + j] = m;
             smask[sl + j] = mask;
         }
-        if (has) ++k;
+        if (has) {
+#pragma unroll
+            for (int d = 0; d + 1 < FW; ++d) {
+                c[d] = c[d + 1];
+                v[d] = v[d + 1];
+            }
+            const int nk = k + FW;
+            c[FW - 1] = nk < len ? col[rs + nk] : 0;
+            v[FW - 1] = nk < len ? val[rs + nk] : 0.0;
+            ++k;
+        }
     }
     if (__ballot(k != len) == 0) return w > 0;
     for (int j = 0; j < w; ++j) {

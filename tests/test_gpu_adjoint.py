@@ -42,6 +42,41 @@ def test_grad_kernel_bit_exact(mods, arith):
     assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
 
 
+def _irregular(n=1000, seed=11):
+    """Rows of 0 .. 300 entries and one of 990 (empty rows at both ends and
+    inside, a ragged last block of rows), columns ascending."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, 12, n)
+    lens[rng.choice(n, 40, replace=False)] = 0
+    lens[:3] = 0
+    lens[-2:] = 0
+    lens[rng.choice(n, 6, replace=False)] = rng.integers(65, 300, 6)
+    rows = np.repeat(np.arange(n), lens)
+    cols = np.concatenate([np.sort(rng.choice(n, l, replace=False)) for l in lens])
+    M = sp.csr_matrix((rng.uniform(-1, 1, rows.size), (rows, cols)), shape=(n, n))
+    M = M + sp.csr_matrix((np.ones(n - 10), (np.full(n - 10, 500), np.arange(5, n - 5))), shape=(n, n))
+    M.sort_indices()
+    return P.CSR.from_scipy(M)
+
+
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qtw", "qtwe", "qw", "qqw"])
+def test_grad_kernel_bit_exact_irregular_rows(mods, arith):
+    torch, mw, _ = mods
+    A = _irregular()
+    assert (np.diff(A.row_ptr) == 0).any() and np.diff(A.row_ptr).max() > 128
+    k = O.WORDS[arith]
+    rng = np.random.default_rng(4)
+    lam = rand_mw(rng, k, A.n)
+    x = rand_mw(rng, k, A.n)
+    got = mw.csr_grad(arith, mw.DeviceCSR.from_host(A), torch.as_tensor(lam, device="cuda"),
+                      torch.as_tensor(x, device="cuda")).cpu().numpy()
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    prod = O.elementwise(arith, "mul", lam[:, rows], x[:, A.col_idx])
+    want = -O.elementwise(arith, "tofp64", prod)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
 def _problem(nx=12):
     Q = P.adjoint_problem(nx=nx, seed=5, bseed=555, tseed=55)
     return Q
