@@ -29,6 +29,11 @@
  *             nnz), col_idx[nnz] in [0, n) and ascending within each row,
  *             val[nnz] FP64; all int32.  Symmetric matrices are stored in
  *             full (both triangles).
+ *   Sizes:    n (rows, vector length) and nnz at most MW_MAX_N = 2^31 -
+ *             2^16, so that no 32-bit index a kernel forms past the end of
+ *             its range (a partial tile, a row group, a padded slice)
+ *             overflows; larger sizes are MW_EINVAL (byte-count queries
+ *             return 0).
  *   Streams:  `stream` is a hipStream_t (NULL = the default stream).  All
  *             work is enqueued on it.  mw_spmv, mw_dot, mw_axpy and
  *             mw_elementwise are asynchronous; the solvers return after
@@ -53,6 +58,9 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* Largest n and nnz (see Sizes above). */
+#define MW_MAX_N 2147418112
 
 /* The five arithmetics (Sec. I list; Sec. V-B naming CG-FP64 ... CG-QTW),
  * and QTWE: QTW with VecSum3 (Alg. 9) after every operation, the

@@ -64,5 +64,5 @@ def cg_solve(A, val, b, arith="qtw", tol=1e-12, maxit=None, info=None, precond=N
     None or "jacobi", for the forward and the adjoint solve alike (it
     changes how the solves get there, not the gradient's formula)."""
     if maxit is None:
-        maxit = 10 * A.n
+        maxit = min(10 * A.n, mw.MAXIT_MAX)
     return MWCGSolve.apply(val, b, A.row_ptr, A.col_idx, arith, tol, maxit, info, precond)

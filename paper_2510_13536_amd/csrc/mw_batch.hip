@@ -551,7 +551,7 @@ BatchLayout batch_layout(int a, int32_t nsys, int32_t n, int32_t nnz)
 {
     const size_t K = (size_t)words(a), KV = (size_t)vwords(a);  // scalar / vector words
     BatchLayout L;
-    L.ns_max = (long long)(n + 63) / 64 + nsys;
+    L.ns_max = ((long long)n + 63) / 64 + nsys;
     L.cap = (long long)nnz + (long long)nnz / 4 + 64 * L.ns_max;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -874,7 +874,7 @@ extern "C" {
 
 size_t mw_cg_batched_workspace_bytes(mw_arith_t a, int32_t nsys, int32_t n, int32_t nnz)
 {
-    if (!valid_arith(a) || nsys <= 0 || n <= 0 || nnz < 0) return 0;
+    if (!valid_arith(a) || nsys <= 0 || n <= 0 || !size_ok(n) || !size_ok(nnz)) return 0;
     return batch_layout(a, nsys, n, nnz).bytes;
 }
 

@@ -932,7 +932,7 @@ const char *mw_last_error(void) { return mwh::g_err; }
 int mw_elementwise(mw_arith_t a, int op, int32_t n, const double *u, const double *v, double *w, void *stream)
 {
     mwh::clear_error();
-    if (!valid_arith(a) || mixed_arith(a) || op < MW_OP_ADD || op > MW_OP_TOFP64 || n < 0 || (n > 0 && (!u || !w)))
+    if (!valid_arith(a) || mixed_arith(a) || op < MW_OP_ADD || op > MW_OP_TOFP64 || !size_ok(n) || (n > 0 && (!u || !w)))
         return MW_EINVAL;
     const bool needs_v = (op == MW_OP_ADD || op == MW_OP_MUL || op == MW_OP_DXMUL || op == MW_OP_DIV);
     if (needs_v && n > 0 && !v) return MW_EINVAL;
@@ -944,7 +944,7 @@ int mw_elementwise(mw_arith_t a, int op, int32_t n, const double *u, const doubl
 int mw_axpy(mw_arith_t a, int32_t n, const double *alpha, const double *x, double *y, void *stream)
 {
     mwh::clear_error();
-    if (!valid_arith(a) || n < 0 || (n > 0 && (!alpha || !x || !y))) return MW_EINVAL;
+    if (!valid_arith(a) || !size_ok(n) || (n > 0 && (!alpha || !x || !y))) return MW_EINVAL;
     if (n == 0) return MW_OK;
     hipStream_t s = (hipStream_t)stream;
     MW_DISPATCH(a, axpy_a, n, alpha, x, y, s);
@@ -952,7 +952,7 @@ int mw_axpy(mw_arith_t a, int32_t n, const double *alpha, const double *x, doubl
 
 size_t mw_dot_workspace_bytes(mw_arith_t a, int32_t n)
 {
-    if (!valid_arith(a) || n < 0) return 0;
+    if (!valid_arith(a) || !size_ok(n)) return 0;
     const size_t nb = (size_t)(n > 0 ? blocks_for(n, (long)NT * DOT_EPT) : 0);
     return align256(sizeof(double) * words(a) * (nb > 0 ? nb : 1));
 }
@@ -961,7 +961,7 @@ int mw_dot(mw_arith_t a, int32_t n, const double *x, const double *y, double *re
            void *stream)
 {
     mwh::clear_error();
-    if (!valid_arith(a) || n < 0 || !result || !workspace || (n > 0 && (!x || !y))) return MW_EINVAL;
+    if (!valid_arith(a) || !size_ok(n) || !result || !workspace || (n > 0 && (!x || !y))) return MW_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     MW_DISPATCH(a, dot_a, n, x, y, result, workspace, s);
 }
@@ -1008,7 +1008,7 @@ int mw_csr_grad(mw_arith_t a, const mw_csr_t *A, const double *lam, const double
 
 size_t mw_spmv_plan_bytes(int32_t n, int32_t nnz)
 {
-    if (n <= 0 || nnz < 0) return 0;
+    if (n <= 0 || !size_ok(n) || !size_ok(nnz)) return 0;
     return mwh::plan_bytes(n, nnz);
 }
 

@@ -730,7 +730,7 @@ extern "C" {
 
 size_t mw_cg_workspace_bytes(mw_arith_t a, int32_t n, int32_t nnz)
 {
-    if (!valid_arith(a) || n <= 0 || nnz < 0) return 0;
+    if (!valid_arith(a) || n <= 0 || !size_ok(n) || !size_ok(nnz)) return 0;
     return cg_layout(a, n, nnz).total;
 }
 

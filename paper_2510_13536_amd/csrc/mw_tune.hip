@@ -263,7 +263,7 @@ extern "C" {
 int mw_cg_shape(mw_arith_t a, int32_t n, int32_t nnz, int32_t nsys, mw_shape_t *shape)
 {
     mwh::clear_error();
-    if (!valid_arith(a) || n <= 0 || nnz < 0 || nsys < 0 || !shape) return MW_EINVAL;
+    if (!valid_arith(a) || n <= 0 || !size_ok(n) || !size_ok(nnz) || nsys < 0 || !shape) return MW_EINVAL;
     mw_shape_t t{};
     const bool tuned = tuned_get(a, n, nnz, nsys, &t);
     *shape = mw_shape_t{};

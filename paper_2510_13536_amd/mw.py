@@ -90,6 +90,8 @@ class CgOpts(C.Structure):
 
 
 PRECOND = {None: 0, "jacobi": 1}
+MAX_N = 2 ** 31 - 2 ** 16   # MW_MAX_N: the largest n and nnz the library takes
+MAXIT_MAX = 2 ** 31 - 1     # maxit is an int32
 
 
 class MWError(RuntimeError):
@@ -392,7 +394,9 @@ def cg_solve(arith, A, b, x=None, tol=1e-12, maxit=None, normalize=True, chunk=0
         x = torch.zeros((k, A.n), dtype=torch.float64, device=b.device)
     x = _vec(x, k, A.n, name="x")
     if maxit is None:
-        maxit = 10 * A.n
+        maxit = min(10 * A.n, MAXIT_MAX)
+    if not 0 <= int(maxit) <= MAXIT_MAX:
+        raise MWError("maxit must be in [0, 2^31 - 1]")
     if workspace is None:
         workspace = cg_workspace(arith, A, b.device)
     hist = torch.zeros(max(int(maxit), 1), dtype=torch.float64, device=b.device) if history else None
@@ -431,7 +435,9 @@ def cg_solve_batched(arith, A, sys_row_off, b, x=None, tol=1e-12, maxit=None, no
         x = torch.zeros((k, A.n), dtype=torch.float64, device=b.device)
     x = _vec(x, k, A.n, name="x")
     if maxit is None:
-        maxit = 10 * int(np.max(np.diff(off))) if nsys > 0 else 0
+        maxit = min(10 * int(np.max(np.diff(off))), MAXIT_MAX) if nsys > 0 else 0
+    if not 0 <= int(maxit) <= MAXIT_MAX:
+        raise MWError("maxit must be in [0, 2^31 - 1]")
     if workspace is None:
         nbytes = lib().mw_cg_batched_workspace_bytes(ARITH[arith], nsys, A.n, A.nnz)
         workspace = torch.empty(nbytes, dtype=torch.uint8, device=b.device)

@@ -56,14 +56,28 @@ def test_workspace_sizes(lib):
     assert lib.mw_cg_workspace_bytes(0, 0, 0) == 0
 
 
-def test_sizes_at_the_int32_limits(lib):
-    """n = nnz = 2^31 - 1 (the largest the int32 CSR allows): every byte
-    count is formed in 64 bits (a QTW workspace is then ~150 GB, inside one
-    GPU's 288 GB), the plan and shape helpers stay consistent."""
+MW_MAX_N = 2 ** 31 - 2 ** 16  # include/mw.h
+
+
+def test_max_n_matches_the_header():
+    text = open(HEADER).read()
+    assert int(re.search(r"#define MW_MAX_N (\d+)", text).group(1)) == MW_MAX_N
+
+
+def test_sizes_at_the_limit(lib):
+    """n = nnz = MW_MAX_N (2^31 - 2^16): every byte count is formed in 64
+    bits (an FP64 workspace is then ~128 GB and a QTW one ~283 GB, with the
+    SpMV plan's 59 GB), the plan and shape helpers stay consistent; one more
+    is rejected."""
     lib.mw_cg_workspace_bytes.restype = C.c_size_t
     lib.mw_spmv_plan_bytes.restype = C.c_size_t
     lib.mw_cg_batched_workspace_bytes.restype = C.c_size_t
-    big = 2 ** 31 - 1
+    lib.mw_dot_workspace_bytes.restype = C.c_size_t
+    big = MW_MAX_N
+    for f in (lambda n, z: lib.mw_cg_workspace_bytes(4, n, z), lambda n, z: lib.mw_spmv_plan_bytes(n, z),
+              lambda n, z: lib.mw_cg_batched_workspace_bytes(4, 1, n, z)):
+        assert f(big, big) > 0 and f(big + 1, big) == 0 and f(big, big + 1) == 0
+    assert lib.mw_dot_workspace_bytes(4, big) > 0 and lib.mw_dot_workspace_bytes(4, big + 1) == 0
     for a, k in enumerate([1, 2, 2, 3, 3, 3]):
         ws = lib.mw_cg_workspace_bytes(a, big, big)
         assert ws >= 3 * k * big * 8 and ws % 256 == 0
@@ -80,6 +94,21 @@ def test_sizes_at_the_int32_limits(lib):
     sh = Shape()
     assert lib.mw_cg_shape(4, big, big, 0, C.byref(sh)) == 0
     assert (sh.spmv_grid, sh.update_grid, sh.lanes) == (1536, 1024, 0)
+    assert lib.mw_cg_shape(4, big + 1, big, 0, C.byref(sh)) == -1
+    vp = C.c_void_p
+    lib.mw_elementwise.argtypes = [C.c_int, C.c_int, C.c_int32, vp, vp, vp, vp]
+    lib.mw_axpy.argtypes = [C.c_int, C.c_int32, vp, vp, vp, vp]
+    lib.mw_dot.argtypes = [C.c_int, C.c_int32, vp, vp, vp, vp, vp]
+    lib.mw_csr_check.argtypes = [vp, vp]
+    bogus = vp(0x1000)
+    assert lib.mw_elementwise(4, 0, big + 1, bogus, bogus, bogus, None) == -1
+    assert lib.mw_axpy(4, big + 1, bogus, bogus, bogus, None) == -1
+    assert lib.mw_dot(4, big + 1, bogus, bogus, bogus, bogus, None) == -1
+
+    class Csr(C.Structure):
+        _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", vp), ("col_idx", vp), ("val", vp)]
+    for n, nnz in ((big + 1, 10), (10, big + 1)):
+        assert lib.mw_csr_check(C.byref(Csr(n, nnz, bogus, bogus, bogus)), None) == -1
 
 
 def test_invalid_arguments_rejected_without_gpu(lib):
