@@ -7,6 +7,7 @@ import pytest
 import scipy.sparse as sp
 
 import oracle as O
+from conftest import rand_mw
 from paper_2510_13536_amd import problems as P
 
 pytestmark = pytest.mark.gpu
@@ -88,6 +89,57 @@ def test_batched_matches_single_solver_and_is_deterministic(mw, small_batch):
     for s in range(0, len(mats), 4):
         _, i = mw.cg_solve("qtw", mw.DeviceCSR.from_host(mats[s]), dev(bs[s]), tol=1e-12)
         assert abs(i["iters"] - int(it1[s])) <= max(1, int(0.02 * i["iters"])), (s, i, it1[s])
+
+
+@pytest.mark.parametrize("arith", ["fp64", "qtw", "mxdw"])
+def test_batched_empty_systems(mw, small_batch, arith):
+    """Systems of zero rows (repeated row offsets) at the start, inside and
+    at the end of the batch: each stops at once (status ok, 0 iterations,
+    relative residual 0), and every other system's x, iterations and status
+    are bit-identical to the batch without them (its slices and per-slice
+    partials do not change)."""
+    mats, bs, B = small_batch
+    Ad = mw.DeviceCSR.from_host(B.A)
+    off = np.asarray(B.sys_row_off)
+    x0, it0, st0, _, _ = mw.cg_solve_batched(arith, Ad, off, dev(B.b), tol=1e-12, maxit=20000)
+    empty_at = [0, 0, 5, 11, len(off) - 1, len(off) - 1]   # before system k: a zero-row system
+    off2 = np.insert(off, empty_at, off[empty_at])
+    keep = np.ones(len(off2) - 1, dtype=bool)
+    for j, k in enumerate(empty_at):
+        keep[k + j] = False
+    assert (np.diff(off2)[~keep] == 0).all() and (off2[1:][keep] == off[1:]).all()
+    x1, it1, st1, rel1, _ = mw.cg_solve_batched(arith, Ad, off2, dev(B.b), tol=1e-12, maxit=20000)
+    assert (it1[~keep] == 0).all() and (st1[~keep] == 0).all() and (rel1[~keep] == 0).all()
+    assert np.array_equal(it1[keep], it0) and np.array_equal(st1[keep], st0)
+    assert np.array_equal(x1.cpu().numpy().view(np.uint64), x0.cpu().numpy().view(np.uint64))
+
+
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qtw", "mxqtw"])
+def test_batched_initial_guess(mw, small_batch, arith):
+    """A nonzero x0 (random planes, per system r0 = b - A x0): per system
+    the oracle's status, iterations within 2 % and true residual within 10x
+    of the oracle started from the same x0."""
+    mats, bs, _ = small_batch
+    keep = [s for s in range(12) if np.any(bs[s])]   # with b = 0, x0 != 0 has no relative residual
+    mats, bs = [mats[s] for s in keep], [bs[s] for s in keep]
+    B = P.batch_from_systems(mats, bs)
+    k = mw.WORDS[arith]
+    x0 = rand_mw(np.random.default_rng(23), k, B.A.n, emin=-2, emax=2)
+    xg, iters, status, _, _ = mw.cg_solve_batched(arith, mw.DeviceCSR.from_host(B.A), B.sys_row_off, dev(B.b),
+                                                  x=dev(x0), tol=1e-12, maxit=20000)
+    xg = xg.cpu().numpy()
+    off = B.sys_row_off
+    base = MIXED.get(arith, arith)
+    for s, (A, b) in enumerate(zip(mats, bs)):
+        xs = x0[:, off[s]:off[s + 1]]
+        xo, io = O.cg_solve(base, A, b, x0=xs, tol=1e-12, maxit=20000, mixed=arith in MIXED)
+        assert mw.STATUS[int(status[s])] == io["status"], (s, status[s], io)
+        assert abs(int(iters[s]) - io["iters"]) <= max(1, int(0.02 * io["iters"])), (s, iters[s], io["iters"])
+        nb = np.linalg.norm(b)
+        tr_arith = "fp64" if arith in MIXED else arith
+        trg = O.true_residual(tr_arith, A, b, xg[:, off[s]:off[s + 1]]) / nb
+        tro = O.true_residual(tr_arith, A, b, xo) / nb
+        assert trg <= 10 * max(tro, 1e-300), (s, trg, tro)
 
 
 def test_batched_maxit(mw, small_batch):
