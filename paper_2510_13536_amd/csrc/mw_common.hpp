@@ -160,7 +160,13 @@ inline int blocks_for(long n, long per) { return (int)((n + per - 1) / per); }
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 inline bool valid_arith(int a) { return a >= MW_FP64 && a <= MW_MXQTW; }
 inline bool mixed_arith(int a) { return a == MW_MXDW || a == MW_MXQTW; }
-inline bool size_ok(long n) { return n >= 0 && n <= MW_MAX_N; }
+// A size the library takes (0 .. MW_MAX_N); a larger one also leaves a
+// message for mw_last_error.
+inline bool size_ok(long n)
+{
+    if (n > MW_MAX_N) set_error("n or nnz exceeds MW_MAX_N (2^31 - 2^16)");
+    return n >= 0 && n <= MW_MAX_N;
+}
 inline bool valid_csr(const mw_csr_t *A)
 {
     return A && A->n > 0 && A->nnz >= 0 && size_ok(A->n) && size_ok(A->nnz) && A->row_ptr && A->col_idx && A->val;

@@ -107,8 +107,10 @@ def test_sizes_at_the_limit(lib):
 
     class Csr(C.Structure):
         _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", vp), ("col_idx", vp), ("val", vp)]
+    lib.mw_last_error.restype = C.c_char_p
     for n, nnz in ((big + 1, 10), (10, big + 1)):
         assert lib.mw_csr_check(C.byref(Csr(n, nnz, bogus, bogus, bogus)), None) == -1
+        assert b"MW_MAX_N" in lib.mw_last_error()
 
 
 def test_invalid_arguments_rejected_without_gpu(lib):
