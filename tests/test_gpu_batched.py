@@ -142,6 +142,21 @@ def test_batched_initial_guess(mw, small_batch, arith):
         assert trg <= 10 * max(tro, 1e-300), (s, trg, tro)
 
 
+@pytest.mark.parametrize("arith", ["dw", "qtw"])
+def test_batched_bits_do_not_depend_on_chunk_length(mw, small_batch, arith):
+    """Iterations per captured graph (1, 5, 16, 64) change only when the
+    host polls and the running-slice list is rebuilt: x, iterations and
+    status are bit-identical."""
+    mats, bs, B = small_batch
+    Ad = mw.DeviceCSR.from_host(B.A)
+    runs = [mw.cg_solve_batched(arith, Ad, B.sys_row_off, dev(B.b), tol=1e-12, maxit=20000, chunk=c)
+            for c in (1, 5, 16, 64)]
+    x0, it0, st0, _, _ = runs[0]
+    for x, it, st, _, _ in runs[1:]:
+        assert np.array_equal(it, it0) and np.array_equal(st, st0)
+        assert np.array_equal(x.cpu().numpy().view(np.uint64), x0.cpu().numpy().view(np.uint64))
+
+
 def test_batched_maxit(mw, small_batch):
     mats, bs, B = small_batch
     Ad = mw.DeviceCSR.from_host(B.A)

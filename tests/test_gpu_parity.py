@@ -776,3 +776,19 @@ def test_cg_with_plan_and_timing(mw):
     d = prof.as_dict()
     assert d["spmv"]["launches"] == i2["iters"] - 1 and d["spmv"]["ms"] > 0
     assert d["update_r"]["launches"] == 0
+
+
+@pytest.mark.parametrize("arith", ["fp64", "dw", "qtw", "qqw"])
+def test_cg_bits_do_not_depend_on_chunk_length(mw, arith):
+    """Iterations per captured graph (1 and 5, rounded up to even, 32, 100)
+    change only where the host polls the stop flag: x and the iteration
+    count are bit-identical, also when the stop falls inside a chunk."""
+    A = P.poisson3d(20, 18, 16)
+    b = A.matvec(np.random.default_rng(31).uniform(-1.0, 1.0, A.n))
+    Ad = mw.DeviceCSR.from_host(A)
+    runs = [mw.cg_solve(arith, Ad, dev(b), tol=1e-12, chunk=c) for c in (1, 5, 32, 100)]
+    x0, i0 = runs[0]
+    assert i0["status"] == "ok" and i0["iters"] % 100 != 0   # the stop inside a chunk of 100
+    for x, info in runs[1:]:
+        assert info["iters"] == i0["iters"] and info["status"] == i0["status"]
+        assert np.array_equal(x.cpu().numpy().view(np.uint64), x0.cpu().numpy().view(np.uint64))
