@@ -371,17 +371,30 @@ __global__ void __launch_bounds__(NT) mw_csr_grad_kernel(int n, const int32_t *_
     // row starts of the block; lanes past the last row hold a start no
     // entry index reaches
     const int start = r0 + lane < n ? row_ptr[r0 + lane] : 0x7fffffff;
+    // lam of the block's rows, one per lane (coalesced), passed to the
+    // entries' lanes by shuffles
+    const Num<A> lrow = r0 + lane < n ? load<A>(lam, n, r0 + lane) : zero<A>();
     const int e0 = row_ptr[r0];
     const int e1 = row_ptr[r0 + 64 < n ? r0 + 64 : n];
-    for (int z0 = e0; z0 < e1; z0 += 64) {
-        const int z = z0 + lane;
+    // two 64-entry chunks per pass: their searches and loads are independent
+    for (int z0 = e0; z0 < e1; z0 += 128) {
+        const int za = z0 + lane, zb = z0 + 64 + lane;
         // the last row whose start is <= z (a row with entries: an empty
         // row's start equals the next row's); all lanes take part
-        int l = 0;
+        int la = 0, lb = 0;
 #pragma unroll
-        for (int step = 32; step > 0; step >>= 1)
-            if (__shfl(start, l + step, 64) <= z) l += step;
-        if (z < e1) grad[z] = -to_fp64<A>(mul<A>(load<A>(lam, n, r0 + l), load<A>(x, n, col[z])));
+        for (int step = 32; step > 0; step >>= 1) {
+            if (__shfl(start, la + step, 64) <= za) la += step;
+            if (__shfl(start, lb + step, 64) <= zb) lb += step;
+        }
+        Num<A> lia, lib;
+#pragma unroll
+        for (int w = 0; w < words(A); ++w) {
+            lia.w[w] = __shfl(lrow.w[w], la, 64);
+            lib.w[w] = __shfl(lrow.w[w], lb, 64);
+        }
+        if (za < e1) grad[za] = -to_fp64<A>(mul<A>(lia, load<A>(x, n, col[za])));
+        if (zb < e1) grad[zb] = -to_fp64<A>(mul<A>(lib, load<A>(x, n, col[zb])));
     }
 }
 
@@ -450,6 +463,9 @@ __global__ void __launch_bounds__(FIN_NT) mw_sell_scan_kernel(int ns, const int3
     const int per = (ns + FIN_NT - 1) / FIN_NT;
     const int lo = min(t * per, ns), hi = min(lo + per, ns);
     long long s = 0;
+    // unrolled so that the loads of a thread's contiguous range are issued
+    // together, not one round trip after another
+#pragma unroll 16
     for (int i = lo; i < hi; ++i) s += 64LL * width[i];
     sums[t] = s;
     __syncthreads();
@@ -461,6 +477,7 @@ __global__ void __launch_bounds__(FIN_NT) mw_sell_scan_kernel(int ns, const int3
         __syncthreads();
     }
     long long run = sums[t] - s;
+#pragma unroll 16
     for (int i = lo; i < hi; ++i) {
         slice_ptr[i] = (int32_t)run;
         run += 64LL * width[i];
