@@ -13,8 +13,15 @@ and the seeded generators (paper_2510_13536_amd/problems.py).
   c4_oracle_solves.json   the 512-system batch (seed 4): the four largest
                           systems and four of median size, CG from x0 = 0
                           to 1e-12 in DW and QTW, the same fields.
+  c5_oracle_gradient.json the adjoint problem 100^3 + diag(theta): the QTW
+                          forward solve x = A^-1 b and adjoint solve
+                          A lam = fp64(x) - x_target to 1e-26, and the
+                          gradients -fp64(lam_i x_i) (theta) and fp64(lam)
+                          (b) at the 64 + 64 coordinates drawn with seed 5555
+                          (theta first, then b), with their largest
+                          magnitudes over all coordinates.
 
-Usage: python tests/golden/make_fullsize_oracle.py [c2] [c4]
+Usage: python tests/golden/make_fullsize_oracle.py [c2] [c4] [c5]
 """
 import json
 import os
@@ -83,6 +90,28 @@ def main(which):
             out["systems"][str(s)] = rec
             print(s, rec, flush=True)
         json.dump(out, open(os.path.join(HERE, "c4_oracle_solves.json"), "w"), indent=1)
+    if "c5" in which:
+        Q = P.adjoint_problem(nx=100)
+        A = Q.matrix()
+        t = time.time()
+        xo, io = O.cg_solve("qtw", A, Q.b, tol=1e-26)
+        g = O.elementwise("qtw", "tofp64", xo) - Q.x_target
+        lo, il = O.cg_solve("qtw", A, g, tol=1e-26)
+        gt = -O.elementwise("qtw", "tofp64", O.elementwise("qtw", "mul", lo, xo))
+        gb = O.elementwise("qtw", "tofp64", lo)
+        rng = np.random.default_rng(5555)
+        ith = rng.choice(A.n, 64, replace=False)
+        ib = rng.choice(A.n, 64, replace=False)
+        out = {"workload": "3D Laplacian 100^3 + diag(theta) (seeds 5, 555, 55), loss 0.5 ||x - x_target||^2, "
+                           "QTW solves to 1e-26",
+               "forward": {"status": io["status"], "iters": int(io["iters"])},
+               "adjoint": {"status": il["status"], "iters": int(il["iters"])},
+               "theta_index": [int(i) for i in ith], "theta_grad": [float(gt[i]) for i in ith],
+               "b_index": [int(i) for i in ib], "b_grad": [float(gb[i]) for i in ib],
+               "theta_grad_absmax": float(np.abs(gt).max()), "b_grad_absmax": float(np.abs(gb).max()),
+               "oracle_seconds": round(time.time() - t, 1)}
+        print({k: out[k] for k in ("forward", "adjoint", "oracle_seconds")}, flush=True)
+        json.dump(out, open(os.path.join(HERE, "c5_oracle_gradient.json"), "w"), indent=1)
 
 
 if __name__ == "__main__":

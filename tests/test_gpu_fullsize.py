@@ -14,7 +14,7 @@ benchmark uses (planned SELL-64 SpMV, graph-replayed CG chunks):
 * the 512-system batch: small, median and the largest systems against
   oracle solves (live or stored);
 * the adjoint problem at 100^3: gradients against central differences at
-  64 + 64 coordinates.
+  64 + 64 coordinates, and against the oracle's gradient there.
 """
 import numpy as np
 import pytest
@@ -228,7 +228,9 @@ def test_c5_adjoint_finite_differences(mods):
     """Adjoint gradients on 100^3 + diag(theta) against central differences
     at 64 random theta and 64 random b coordinates (seed 5555), every
     difference solve in QTW to 1e-24 (plan rebuilt inside each solve, one
-    workspace); accept |g - g_fd| <= 1e-6 |g_fd| + 1e-9 ||g||_inf."""
+    workspace); accept |g - g_fd| <= 1e-6 |g_fd| + 1e-9 ||g||_inf.  At the
+    same coordinates the gradient equals the oracle's (its QTW solves to
+    1e-26, stored) to 1e-10 relative."""
     torch, mw = mods
     from paper_2510_13536_amd import adjoint
     Q = P.adjoint_problem(nx=100)
@@ -269,6 +271,15 @@ def test_c5_adjoint_finite_differences(mods):
     ith = rng.choice(Q.lap.n, 64, replace=False)
     ib = rng.choice(Q.lap.n, 64, replace=False)
     gmax, gbmax = np.abs(g).max(), np.abs(gb).max()
+
+    # the oracle's gradient at the same coordinates (its forward and adjoint
+    # QTW solves to 1e-26, stored by tests/golden/make_fullsize_oracle.py)
+    ref = _golden("c5_oracle_gradient.json")
+    assert ref["forward"]["status"] == ref["adjoint"]["status"] == "ok"
+    assert ref["theta_index"] == [int(i) for i in ith] and ref["b_index"] == [int(i) for i in ib]
+    np.testing.assert_allclose(g[ith], ref["theta_grad"], rtol=1e-10, atol=1e-12 * ref["theta_grad_absmax"])
+    np.testing.assert_allclose(gb[ib], ref["b_grad"], rtol=1e-10, atol=1e-12 * ref["b_grad_absmax"])
+    assert abs(gmax - ref["theta_grad_absmax"]) <= 1e-10 * gmax and abs(gbmax - ref["b_grad_absmax"]) <= 1e-10 * gbmax
     for i in ith:
         h = 1e-4 * max(abs(Q.theta[i]), 1e-2)
         k = int(Q.diag_pos[i])
