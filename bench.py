@@ -495,6 +495,57 @@ def bench_adjoint(mw, P, torch, dev):
     return out
 
 
+def bench_batched_adjoint(mw, P, torch, dev, nsys=512):
+    """The 512-system batch with theta ~ U[0.01, 1] (seed 6) added to its
+    diagonal, loss 0.5 ||x - x_target||^2 (x_target ~ N(0, 1), seed 66), QTW
+    to 1e-12: all systems' theta and b gradients from one batched forward
+    and one batched adjoint solve, against a loop of single-system adjoints."""
+    import numpy as np
+    from paper_2510_13536_amd import adjoint
+    B = P.batch_systems(nsys=nsys)
+    theta0 = np.random.default_rng(6).uniform(0.01, 1.0, B.A.n)
+    xt0 = np.random.default_rng(66).standard_normal(B.A.n)
+    Ad = mw.DeviceCSR.from_host(B.A, dev)
+    pos = torch.as_tensor(P.diagonal_positions(B.A), device=dev)
+    lap_val = torch.as_tensor(B.A.val, device=dev)
+    xt = torch.as_tensor(xt0, device=dev)
+    out = {"workload": "%d systems, n=%d, nnz=%d, + diag(theta), QTW, tol 1e-12" % (B.nsys, B.A.n, B.A.nnz)}
+    times = []
+    for rep in range(2):
+        theta = torch.as_tensor(theta0, device=dev).requires_grad_(True)
+        b = torch.as_tensor(B.b, device=dev).requires_grad_(True)
+        info = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = adjoint.cg_solve_batched(Ad, lap_val.index_add(0, pos, theta), B.sys_row_off, b, arith="qtw", tol=1e-12,
+                                     info=info)
+        (0.5 * ((x - xt) ** 2).sum()).backward()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    out["batched_s"] = round(times[-1], 4)
+    out["forward_iters_max"] = int(info["forward"]["iters"].max())
+    out["adjoint_iters_max"] = int(info["adjoint"]["iters"].max())
+    # the loop: one single-system differentiable solve per system
+    subs = []
+    for s in range(B.nsys):
+        lo, hi = int(B.sys_row_off[s]), int(B.sys_row_off[s + 1])
+        A, bs = B.system(s)
+        subs.append((mw.DeviceCSR.from_host(A, dev), torch.as_tensor(A.val, device=dev),
+                     torch.as_tensor(P.diagonal_positions(A), device=dev), lo, hi, bs))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for As, vals, ps, lo, hi, bs in subs:
+        th = torch.as_tensor(theta0[lo:hi], device=dev).requires_grad_(True)
+        bb = torch.as_tensor(bs, device=dev).requires_grad_(True)
+        x = adjoint.cg_solve(As, vals.index_add(0, ps, th), bb, arith="qtw", tol=1e-12)
+        (0.5 * ((x - xt[lo:hi]) ** 2).sum()).backward()
+    torch.cuda.synchronize()
+    out["loop_s"] = round(time.perf_counter() - t0, 4)
+    out["speedup"] = round(out["loop_s"] / out["batched_s"], 2)
+    log("batched adjoint: %s" % out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -754,6 +805,7 @@ def main():
     if not args.quick:
         extra["batched"] = bench_batched(mw, P, torch, dev, tune=not args.no_tune)
         extra["adjoint"] = bench_adjoint(mw, P, torch, dev)
+        extra["batched_adjoint"] = bench_batched_adjoint(mw, P, torch, dev)
         extra["illcond"] = bench_illcond(mw, P, torch, dev, maxit=args.illcond_maxit)
         extra["normalisation_every_K"] = bench_normalisation(mw, torch, Ad, bd, A.n)
         extra["tolerances"] = bench_tolerances(mw, torch, Ad, bd, A.n)

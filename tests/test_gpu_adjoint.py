@@ -203,3 +203,39 @@ def test_adjoint_with_jacobi_matches_plain(mods, arith):
         grads.append((theta.grad.cpu().numpy(), b.grad.cpu().numpy()))
     for g0, g1 in zip(*grads):
         np.testing.assert_allclose(g1, g0, rtol=1e-12, atol=1e-14 * np.abs(g0).max())
+
+
+@pytest.mark.parametrize("arith", ["dw", "qtw"])
+def test_batched_adjoint_matches_single_system_adjoint(mods, arith):
+    """Six adjoint problems (100 .. 1331 rows, their own theta, b and
+    x_target) on one block diagonal: the batched differentiable solve (one
+    batched forward and one batched adjoint solve, the gradient on the
+    whole pattern) gives every system's theta and b gradients of the
+    single-system adjoint (itself checked against central differences and
+    the oracle), to 1e-10 relative, both solving to 1e-26."""
+    torch, mw, adjoint = mods
+    probs = [P.adjoint_problem(nx=k, seed=50 + k, bseed=550 + k, tseed=5500 + k) for k in (5, 6, 7, 8, 9, 11)]
+    B = P.batch_from_systems([q.lap for q in probs], [q.b for q in probs])
+    off = B.sys_row_off
+    AdB = mw.DeviceCSR.from_host(B.A)
+    posB = torch.as_tensor(P.diagonal_positions(B.A), device="cuda")
+    theta = torch.as_tensor(np.concatenate([q.theta for q in probs]), device="cuda").requires_grad_(True)
+    b = torch.as_tensor(B.b, device="cuda").requires_grad_(True)
+    xt = torch.as_tensor(np.concatenate([q.x_target for q in probs]), device="cuda")
+    valB = torch.as_tensor(B.A.val, device="cuda").index_add(0, posB, theta)
+    info = {}
+    x = adjoint.cg_solve_batched(AdB, valB, off, b, arith=arith, tol=1e-26, info=info)
+    (0.5 * ((x - xt) ** 2).sum()).backward()
+    assert (info["forward"]["status"] == 0).all() and (info["adjoint"]["status"] == 0).all()
+    gt_b, gb_b = theta.grad.cpu().numpy(), b.grad.cpu().numpy()
+    for s, q in enumerate(probs):
+        Ad = mw.DeviceCSR.from_host(q.lap)
+        th = torch.as_tensor(q.theta, device="cuda").requires_grad_(True)
+        bs = torch.as_tensor(q.b, device="cuda").requires_grad_(True)
+        val = torch.as_tensor(q.lap.val, device="cuda").index_add(0, torch.as_tensor(q.diag_pos, device="cuda"), th)
+        xs = adjoint.cg_solve(Ad, val, bs, arith=arith, tol=1e-26)
+        (0.5 * ((xs - torch.as_tensor(q.x_target, device="cuda")) ** 2).sum()).backward()
+        g1, gb1 = th.grad.cpu().numpy(), bs.grad.cpu().numpy()
+        sl = slice(off[s], off[s + 1])
+        np.testing.assert_allclose(gt_b[sl], g1, rtol=1e-10, atol=1e-12 * np.abs(g1).max())
+        np.testing.assert_allclose(gb_b[sl], gb1, rtol=1e-10, atol=1e-12 * np.abs(gb1).max())
