@@ -205,14 +205,15 @@ def test_adjoint_with_jacobi_matches_plain(mods, arith):
         np.testing.assert_allclose(g1, g0, rtol=1e-12, atol=1e-14 * np.abs(g0).max())
 
 
-@pytest.mark.parametrize("arith", ["dw", "qtw"])
-def test_batched_adjoint_matches_single_system_adjoint(mods, arith):
-    """Six adjoint problems (100 .. 1331 rows, their own theta, b and
+@pytest.mark.parametrize("arith,tol,rtol", [("dw", 1e-26, 1e-10), ("qtw", 1e-26, 1e-10), ("mxqtw", 1e-12, 1e-6)])
+def test_batched_adjoint_matches_single_system_adjoint(mods, arith, tol, rtol):
+    """Six adjoint problems (125 .. 1331 rows, their own theta, b and
     x_target) on one block diagonal: the batched differentiable solve (one
     batched forward and one batched adjoint solve, the gradient on the
     whole pattern) gives every system's theta and b gradients of the
     single-system adjoint (itself checked against central differences and
-    the oracle), to 1e-10 relative, both solving to 1e-26."""
+    the oracle): to 1e-10 relative with both solving to 1e-26; MXQTW, whose
+    FP64 vectors stop near 1e-12, to 1e-6."""
     torch, mw, adjoint = mods
     probs = [P.adjoint_problem(nx=k, seed=50 + k, bseed=550 + k, tseed=5500 + k) for k in (5, 6, 7, 8, 9, 11)]
     B = P.batch_from_systems([q.lap for q in probs], [q.b for q in probs])
@@ -224,7 +225,7 @@ def test_batched_adjoint_matches_single_system_adjoint(mods, arith):
     xt = torch.as_tensor(np.concatenate([q.x_target for q in probs]), device="cuda")
     valB = torch.as_tensor(B.A.val, device="cuda").index_add(0, posB, theta)
     info = {}
-    x = adjoint.cg_solve_batched(AdB, valB, off, b, arith=arith, tol=1e-26, info=info)
+    x = adjoint.cg_solve_batched(AdB, valB, off, b, arith=arith, tol=tol, info=info)
     (0.5 * ((x - xt) ** 2).sum()).backward()
     assert (info["forward"]["status"] == 0).all() and (info["adjoint"]["status"] == 0).all()
     gt_b, gb_b = theta.grad.cpu().numpy(), b.grad.cpu().numpy()
@@ -233,9 +234,9 @@ def test_batched_adjoint_matches_single_system_adjoint(mods, arith):
         th = torch.as_tensor(q.theta, device="cuda").requires_grad_(True)
         bs = torch.as_tensor(q.b, device="cuda").requires_grad_(True)
         val = torch.as_tensor(q.lap.val, device="cuda").index_add(0, torch.as_tensor(q.diag_pos, device="cuda"), th)
-        xs = adjoint.cg_solve(Ad, val, bs, arith=arith, tol=1e-26)
+        xs = adjoint.cg_solve(Ad, val, bs, arith=arith, tol=tol)
         (0.5 * ((xs - torch.as_tensor(q.x_target, device="cuda")) ** 2).sum()).backward()
         g1, gb1 = th.grad.cpu().numpy(), bs.grad.cpu().numpy()
         sl = slice(off[s], off[s + 1])
-        np.testing.assert_allclose(gt_b[sl], g1, rtol=1e-10, atol=1e-12 * np.abs(g1).max())
-        np.testing.assert_allclose(gb_b[sl], gb1, rtol=1e-10, atol=1e-12 * np.abs(gb1).max())
+        np.testing.assert_allclose(gt_b[sl], g1, rtol=rtol, atol=1e-2 * rtol * np.abs(g1).max())
+        np.testing.assert_allclose(gb_b[sl], gb1, rtol=rtol, atol=1e-2 * rtol * np.abs(gb1).max())
