@@ -567,6 +567,8 @@ def main():
                     help="run only the 512-system batched comparison (for profiling that path) and print its line")
     ap.add_argument("--no-loop", action="store_true",
                     help="with --batched-only: skip the loop of single solves (for profiling the batched one)")
+    ap.add_argument("--batched-adjoint-only", action="store_true",
+                    help="run only the batched differentiable solve on the 512-system batch and print its line")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint workload (forward + adjoint QTW solves) and print its line")
     ap.add_argument("--illcond-only", action="store_true",
@@ -609,6 +611,13 @@ def main():
                           "value": bt["qtw"]["batched_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
                           "dtype": "f64", "data": "synthetic", "config": {"workload": bt["workload"]},
                           "extra": {"batched": bt}}), flush=True)
+        return
+    if args.batched_adjoint_only:
+        ba = bench_batched_adjoint(mw, P, torch, dev)
+        print(json.dumps({"metric": "batched adjoint gradients (512 systems + diag theta, QTW, tol 1e-12)",
+                          "value": ba["batched_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+                          "dtype": "f64", "data": "synthetic", "config": {"workload": ba["workload"]},
+                          "extra": {"batched_adjoint": ba}}), flush=True)
         return
     if args.adjoint_only:
         ad = bench_adjoint(mw, P, torch, dev)
