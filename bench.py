@@ -20,11 +20,14 @@ adds:
   extra         SpMV GB/s for every arithmetic (MALL flushed between
                 repetitions), time to solution of every arithmetic, the
                 QTW / DW time ratio, per-kernel times, the batched and
-                adjoint workloads, the ill-conditioned banded matrix,
+                adjoint workloads and the two together (gradients of the
+                512 systems), the ill-conditioned banded matrix,
                 normalisation frequencies, tolerances beyond FP64 with
                 true residuals, error norms against an exact integer
                 solution, and one GPU's share of an 8-way split.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
+One workload alone (its own JSON line, for profiling): --table1-only,
+--batched-only, --illcond-only, --adjoint-only, --batched-adjoint-only.
 """
 import argparse
 import json
