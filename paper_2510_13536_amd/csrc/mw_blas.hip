@@ -365,7 +365,9 @@ __global__ void __launch_bounds__(NT) mw_csr_grad_kernel(int n, const int32_t *_
                                                          const double *__restrict__ lam,
                                                          const double *__restrict__ x, double *__restrict__ grad)
 {
-    const long r0 = ((long)blockIdx.x * NWAVE + wave_id()) * 64;
+    // XCD x takes the x-th contiguous range of row blocks, so the gathers
+    // of x for a block's neighbours hit that XCD's L2
+    const long r0 = ((long)xcd_remap(blockIdx.x, gridDim.x) * NWAVE + wave_id()) * 64;
     if (r0 >= n) return;
     const int lane = threadIdx.x & 63;
     // row starts of the block; lanes past the last row hold a start no

@@ -252,6 +252,9 @@ __device__ __forceinline__ bool fill_slice(int b, int w, int lane, long row, int
         c[d] = d < len ? col[rs + d] : 0;
         v[d] = d < len ? val[rs + d] : 0.0;
     }
+    // values of a slot pair are stored together (one 16-byte store per
+    // lane at the pair's position), the odd last slot alone
+    double pend = 0.0;
     for (int j = 0; j < w; ++j) {
         const int cand = k < len ? (int)(c[0] - row) : 0x7fffffff;
         int m = cand;
@@ -259,7 +262,10 @@ __device__ __forceinline__ bool fill_slice(int b, int w, int lane, long row, int
         for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
         const bool has = k < len && cand == m;
         const uint64_t mask = __ballot(has);
-        sval[sell_pos(b, w, j, lane)] = has ? v[0] : 0.0;
+        const double vj = has ? v[0] : 0.0;
+        if (j >= 2 * (w >> 1)) sval[sell_pos(b, w, j, lane)] = vj;
+        else if (j & 1) *(dvec2 *)(sval + sell_pos(b, w, j - 1, lane)) = dvec2{pend, vj};
+        else pend = vj;
         if (lane == 0) {
             soff[sl + j] = m;
             smask[sl + j] = mask;
